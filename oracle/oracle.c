@@ -1,0 +1,985 @@
+/*
+ * oracle.c -- plain sequential FP64 reference of the GIRG / HRG sampler of
+ * arXiv:1905.06706 (Blaesius et al.).  TEST INFRASTRUCTURE: only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark load it.
+ *
+ * The code follows the paper's steps in the paper's order and notation:
+ *   weights / positions (Sec. 2.1, 2.2), the mapping HRG -> GIRG (Sec. 2.3),
+ *   weight buckets ("layers", Sec. 3.1), comparison level CL(i,j) and insertion
+ *   level I(i) (Sec. 3.1; HRG: search over levels, Sec. 4.3), vertices sorted by
+ *   Morton code of their cell (Sec. 3.4, Lemma 1, App. A) with prefix sums,
+ *   Algorithm 1 (recursive cell-pair iteration, Sec. 3.3) with the double
+ *   counting rules of App. B.1, type-I pairs tested one by one, type-II pairs
+ *   sampled by geometric jumps under an upper bound pbar and accepted with
+ *   p_uv / pbar (Sec. 3.2).
+ * Nothing is blocked, fused or reordered.  The readings taken where the paper
+ * is silent are listed in the design doc and restated briefly at each use.
+ */
+#define _GNU_SOURCE
+#include "oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* error reporting                                                           */
+/* ------------------------------------------------------------------------- */
+static __thread char g_err[256];
+const char* orc_last_error(void) { return g_err; }
+static void set_err(const char* msg) {
+  strncpy(g_err, msg, sizeof(g_err) - 1);
+  g_err[sizeof(g_err) - 1] = 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw,        */
+/* "Parallel Random Numbers: As Easy as 1, 2, 3", SC 2011).  One round maps  */
+/* (c0,c1,c2,c3) to (hi(M1*c2)^c1^k0, lo(M1*c2), hi(M0*c0)^c3^k1, lo(M0*c0)); */
+/* the key is bumped by the Weyl constants between rounds.                   */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; round++) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 53-bit uniforms from two 32-bit words: the top 53 bits of hi:lo. */
+double orc_u53(uint32_t lo, uint32_t hi) {
+  uint64_t v = ((uint64_t)hi << 32) | lo;
+  return (double)(v >> 11) * 0x1p-53;
+}
+double orc_u53_open(uint32_t lo, uint32_t hi) {
+  uint64_t v = ((uint64_t)hi << 32) | lo;
+  return (double)((v >> 11) + 1) * 0x1p-53;
+}
+
+/* Stream layout (our contract; the paper uses thread-local generators,
+ * App. B.5).  key = seed.  counter word 3 packs level, layer pair, kind and a
+ * high index part. */
+enum { KIND_TYPE1 = 0, KIND_TYPE2 = 1, KIND_POINTS = 2 };
+
+static void stream_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                         uint32_t out[4]) {
+  uint32_t ctr[4] = {c0, c1, c2, c3};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+static uint32_t word3(int level, int i, int j, int kind, uint32_t high) {
+  return (uint32_t)level | ((uint32_t)i << 6) | ((uint32_t)j << 12) | ((uint32_t)kind << 18) |
+         (high << 20);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Morton code (Sec. 4.2, App. B.3): bitwise interleaving, dimension 0 most   */
+/* significant within each group, so (a3a2a1a0, b3b2b1b0) -> a3b3a2b2a1b1a0b0. */
+/* Written as the plain bit loop ("FOR").                                    */
+/* ------------------------------------------------------------------------- */
+uint64_t orc_morton_encode(const uint32_t* coord, int d, int bits) {
+  uint64_t code = 0;
+  for (int b = bits - 1; b >= 0; b--)
+    for (int k = 0; k < d; k++) code = (code << 1) | ((coord[k] >> b) & 1u);
+  return code;
+}
+void orc_morton_decode(uint64_t code, int d, int bits, uint32_t* coord) {
+  for (int k = 0; k < d; k++) coord[k] = 0;
+  for (int b = 0; b < bits; b++)
+    for (int k = 0; k < d; k++) {
+      int pos = b * d + (d - 1 - k);
+      coord[k] |= (uint32_t)((code >> pos) & 1u) << b;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Points (Sec. 2.1 GIRG; Sec. 2.2 HRG).                                     */
+/* ------------------------------------------------------------------------- */
+/* GIRG: power-law weights with exponent beta, w_min = 1, drawn by inverting
+ * the Pareto tail P(w > t) = t^{-(beta-1)}; positions uniform on the torus as
+ * exact multiples of 2^-53. */
+void orc_points_girg(uint64_t n, int d, double beta, uint64_t seed, double* w, double* x) {
+  double expo = -1.0 / (beta - 1.0);
+  for (uint64_t u = 0; u < n; u++) {
+    uint32_t o[4];
+    stream_block(seed, (uint32_t)u, 0u, 0u, word3(0, 0, 0, KIND_POINTS, 0), o);
+    w[u] = pow(orc_u53_open(o[0], o[1]), expo);
+    for (int k = 0; k < d; k++) {
+      if (k % 2 == 0) stream_block(seed, (uint32_t)u, (uint32_t)(1 + k / 2), 0u,
+                                   word3(0, 0, 0, KIND_POINTS, 0), o);
+      int h = k % 2;
+      x[u * (uint64_t)d + k] = orc_u53(o[2 * h], o[2 * h + 1]);
+    }
+  }
+}
+
+/* HRG: radius with density alpha sinh(alpha r) / (cosh(alpha R) - 1) on
+ * [0, R), by inverting its CDF (cosh(alpha r) - 1) / (cosh(alpha R) - 1);
+ * angle theta = 2 pi x with x uniform on [0,1).  A radius that rounds to R or
+ * above is clamped to R (the layer formula needs r <= R). */
+void orc_points_hrg(uint64_t n, double alpha, double R, uint64_t seed, double* r, double* x) {
+  double cm1 = cosh(alpha * R) - 1.0;
+  for (uint64_t u = 0; u < n; u++) {
+    uint32_t o[4];
+    stream_block(seed, (uint32_t)u, 0u, 0u, word3(0, 0, 0, KIND_POINTS, 0), o);
+    double U = orc_u53(o[0], o[1]);
+    double ru = acosh(1.0 + U * cm1) / alpha;
+    r[u] = ru < R ? ru : R;
+    stream_block(seed, (uint32_t)u, 1u, 0u, word3(0, 0, 0, KIND_POINTS, 0), o);
+    x[u] = orc_u53(o[0], o[1]);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Expected average degree and estimation of c (Sec. 4.1, App. B.2).          */
+/* ------------------------------------------------------------------------- */
+static double sum_ld(const double* v, uint64_t n) {
+  long double s = 0.0L;
+  for (uint64_t i = 0; i < n; i++) s += v[i];
+  return (double)s;
+}
+
+static int cmp_desc(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x < y) - (x > y);
+}
+
+/* f(c) = E[average degree] for the given weights.  T > 0: the formula for
+ * f(c) of App. B.2 (Eqs. short, long, shortlong, deg) with the error term
+ * over E_R = ordered pairs u != v with c^T w_u w_v / W > 2^-d (k > 1/2).
+ * T = 0 ("analogous"): E[X_uv] = (2k)^d with k = c (w_u w_v / W)^{1/d} when
+ * k <= 1/2, else 1. */
+typedef struct {
+  uint64_t n;
+  int d;
+  double T, W, s1, s2;
+  double* sorted; /* weights in descending order */
+} cctx;
+
+static double f_of_c(const cctx* q, double c) {
+  uint64_t n = q->n;
+  int d = q->d;
+  double T = q->T, W = q->W;
+  double err = 0.0;
+  if (T == 0.0) {
+    double a = ldexp(pow(c, (double)d), d); /* 2^d c^d */
+    for (uint64_t u = 0; u < n; u++) {
+      double wu = q->sorted[u];
+      if (a * wu * q->sorted[0] / W <= 1.0) break;
+      for (uint64_t v = 0; v < n; v++) {
+        double X = wu * q->sorted[v] / W;
+        if (a * X <= 1.0) break;
+        if (v != u) err += a * X - 1.0;
+      }
+    }
+    return (a * q->s1 - err) / (double)n;
+  }
+  double cT = pow(c, T);
+  double A = cT * ldexp(1.0, d) / (1.0 - T);
+  double B = c * pow(2.0, (double)d / T) / (1.0 / T - 1.0);
+  double thr = ldexp(1.0, -d);
+  for (uint64_t u = 0; u < n; u++) {
+    double wu = q->sorted[u];
+    if (cT * (wu * q->sorted[0] / W) <= thr) break;
+    for (uint64_t v = 0; v < n; v++) {
+      double X = wu * q->sorted[v] / W;
+      if (cT * X <= thr) break;
+      if (v != u) err += A * X - B * pow(X, 1.0 / T) - 1.0;
+    }
+  }
+  return (A * q->s1 - B * q->s2 - err) / (double)n;
+}
+
+static int cctx_init(cctx* q, uint64_t n, int d, double T, const double* w) {
+  q->n = n; q->d = d; q->T = T;
+  q->W = sum_ld(w, n);
+  long double s1 = 0.0L, p = 0.0L, r = 0.0L;
+  for (uint64_t u = 0; u < n; u++) {
+    s1 += (long double)(w[u] * w[u] / q->W);
+    if (T > 0.0) {
+      p += (long double)pow(w[u], 1.0 / T);
+      r += (long double)pow(w[u] * w[u] / q->W, 1.0 / T);
+    }
+  }
+  q->s1 = q->W - (double)s1; /* sum_u sum_{v != u} w_u w_v / W */
+  if (T > 0.0) {
+    /* sum_u (w_u^{1/T} / W^{1/T}) sum_v w_v^{1/T} - sum_v (w_v^2/W)^{1/T} */
+    double P = (double)p;
+    q->s2 = P / pow(q->W, 1.0 / T) * P - (double)r;
+  } else {
+    q->s2 = 0.0;
+  }
+  q->sorted = (double*)malloc(sizeof(double) * n);
+  if (!q->sorted) return -1;
+  memcpy(q->sorted, w, sizeof(double) * n);
+  qsort(q->sorted, n, sizeof(double), cmp_desc);
+  return 0;
+}
+
+double orc_expected_avg_degree(uint64_t n, int d, double T, double c, const double* w) {
+  cctx q;
+  if (cctx_init(&q, n, d, T, w)) return NAN;
+  double f = f_of_c(&q, c);
+  free(q.sorted);
+  return f;
+}
+
+/* Exponential search for a bracket, then bisection in log c (App. B.2: f is
+ * monotone in c).  Stops when the geometric midpoint no longer separates the
+ * bracket (adjacent doubles) or after 200 halvings; returns the upper end. */
+int orc_solve_c(uint64_t n, int d, double T, double avg_deg, const double* w, double* c_out) {
+  if (!(avg_deg > 0.0) || n < 2) { set_err("solve_c: avg_deg must be > 0 and n >= 2"); return -1; }
+  cctx q;
+  if (cctx_init(&q, n, d, T, w)) { set_err("solve_c: out of memory"); return -2; }
+  double lo = 1.0, hi = 1.0;
+  int it = 0;
+  if (f_of_c(&q, 1.0) < avg_deg) {
+    while (f_of_c(&q, hi) < avg_deg) {
+      lo = hi; hi *= 2.0;
+      if (++it > 2000) { free(q.sorted); set_err("solve_c: no bracket"); return -5; }
+    }
+  } else {
+    while (f_of_c(&q, lo) >= avg_deg) {
+      hi = lo; lo *= 0.5;
+      if (++it > 2000) { free(q.sorted); set_err("solve_c: no bracket"); return -5; }
+    }
+  }
+  for (it = 0; it < 200; it++) {
+    double mid = sqrt(lo) * sqrt(hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (f_of_c(&q, mid) < avg_deg) lo = mid; else hi = mid;
+  }
+  free(q.sorted);
+  *c_out = hi;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* HRG expected average degree (not in the paper).  For independent points   */
+/* with the radial density of Sec. 2.2 and uniform angles, the angular       */
+/* distance phi is uniform on [0, pi] and                                    */
+/*   E[deg] = (n-1) * int int f(r1) f(r2) (1/pi) int_0^pi p(d(r1,r2,phi)) dphi */
+/* with cosh d = cosh(r1-r2) + 2 sinh r1 sinh r2 sin^2(phi/2).  Composite     */
+/* Gauss-Legendre quadrature with breakpoints at the kink r1 + r2 = R and at */
+/* the angle phi* where d = R.                                               */
+/* ------------------------------------------------------------------------- */
+#define GL_N 16
+static double gl_x[GL_N], gl_w[GL_N];
+static int gl_ready = 0;
+static void gl_init(void) {
+  if (gl_ready) return;
+  /* Gauss-Legendre nodes by Newton iteration on the Legendre polynomial P_N. */
+  for (int i = 0; i < GL_N; i++) {
+    double z = cos(M_PI * (i + 0.75) / (GL_N + 0.5)), p0 = 1.0, p1 = z, dp = 1.0;
+    for (int it = 0; it < 100; it++) {
+      p0 = 1.0; p1 = z;
+      for (int k = 2; k <= GL_N; k++) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1; p1 = p2;
+      }
+      dp = GL_N * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    p0 = 1.0; p1 = z;
+    for (int k = 2; k <= GL_N; k++) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1; p1 = p2;
+    }
+    dp = GL_N * (z * p1 - p0) / (z * z - 1.0);
+    gl_x[i] = z;
+    gl_w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  gl_ready = 1;
+}
+
+typedef struct { double alpha, T, R, coshR, norm; } hrgq;
+
+static double hrg_density(const hrgq* h, double r) {
+  return h->alpha * sinh(h->alpha * r) / h->norm;
+}
+
+static double p_T_of_coshd(const hrgq* h, double coshd) {
+  double dist = acosh(coshd < 1.0 ? 1.0 : coshd);
+  return 1.0 / (exp((dist - h->R) / (2.0 * h->T)) + 1.0);
+}
+
+static double gl_panel_p(const hrgq* h, double base, double amp, double a, double b) {
+  double hm = 0.5 * (b - a), mid = 0.5 * (a + b), tot = 0.0;
+  for (int k = 0; k < GL_N; k++) {
+    double sh = sin(0.5 * (mid + hm * gl_x[k]));
+    tot += hm * gl_w[k] * p_T_of_coshd(h, base + amp * sh * sh);
+  }
+  return tot;
+}
+
+/* (1/pi) int_0^pi p(d(phi)) dphi.  T = 0: phi* / pi, with phi* the angle at
+ * which d = R.  T > 0: panels below phi*, and panels growing geometrically
+ * above it (the probability decays like a power of phi there). */
+static double angular_prob(const hrgq* h, double r1, double r2) {
+  double base = cosh(r1 - r2), amp = 2.0 * sinh(r1) * sinh(r2);
+  double s2 = amp > 0.0 ? (h->coshR - base) / amp : (base < h->coshR ? 2.0 : -1.0);
+  double phis;
+  if (s2 >= 1.0) phis = M_PI;
+  else if (s2 <= 0.0) phis = 0.0;
+  else phis = 2.0 * asin(sqrt(s2));
+  if (h->T == 0.0) return phis / M_PI;
+  double tot = 0.0;
+  if (phis <= 0.0 || phis >= M_PI) {
+    for (int q = 0; q < 4; q++) tot += gl_panel_p(h, base, amp, M_PI * q / 4.0, M_PI * (q + 1) / 4.0);
+    return tot / M_PI;
+  }
+  for (int q = 0; q < 3; q++) tot += gl_panel_p(h, base, amp, phis * q / 3.0, phis * (q + 1) / 3.0);
+  double a = phis;
+  while (a < M_PI) {
+    double b = a * 2.0 < M_PI ? a * 2.0 : M_PI;
+    tot += gl_panel_p(h, base, amp, a, b);
+    a = b;
+  }
+  return tot / M_PI;
+}
+
+/* int_a^b f(r2) P(r1, r2) dr2 on panels of unit width */
+static double hrg_inner(const hrgq* h, double r1, double a, double b) {
+  double tot = 0.0;
+  if (b <= a) return 0.0;
+  int panels = (int)ceil(b - a);
+  if (panels < 1) panels = 1;
+  for (int q = 0; q < panels; q++) {
+    double pa = a + (b - a) * q / panels, pb = a + (b - a) * (q + 1) / panels;
+    double hm = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+    for (int k = 0; k < GL_N; k++) {
+      double r2 = mid + hm * gl_x[k];
+      tot += hm * gl_w[k] * hrg_density(h, r2) * angular_prob(h, r1, r2);
+    }
+  }
+  return tot;
+}
+
+double orc_hrg_expected_avg_degree(uint64_t n, double alpha, double T, double R) {
+  gl_init();
+  hrgq h = {alpha, T, R, cosh(R), cosh(alpha * R) - 1.0};
+  double tot = 0.0;
+  int panels = (int)ceil(R);
+  for (int q = 0; q < panels; q++) {
+    double pa = R * q / panels, pb = R * (q + 1) / panels;
+    double hm = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+    for (int k = 0; k < GL_N; k++) {
+      double r1 = mid + hm * gl_x[k];
+      double kink = R - r1; /* at T = 0 every angle connects when r1 + r2 <= R */
+      double inner = hrg_inner(&h, r1, 0.0, kink) + hrg_inner(&h, r1, kink, R);
+      tot += hm * gl_w[k] * hrg_density(&h, r1) * inner;
+    }
+  }
+  return (double)(n - 1) * tot;
+}
+
+/* E[deg] decreases in R.  Bracket around 2 ln n, then regula falsi on
+ * log E[deg] with the Illinois modification, to relative width 1e-12. */
+int orc_hrg_solve_R(uint64_t n, double alpha, double T, double avg_deg, double* R_out) {
+  if (!(avg_deg > 0.0) || n < 2) { set_err("solve_R: avg_deg must be > 0 and n >= 2"); return -1; }
+  double lo = 2.0 * log((double)n), hi = lo;
+  double flo = orc_hrg_expected_avg_degree(n, alpha, T, lo), fhi = flo;
+  int it = 0;
+  while (flo < avg_deg) {
+    hi = lo; fhi = flo;
+    lo *= 0.5;
+    flo = orc_hrg_expected_avg_degree(n, alpha, T, lo);
+    if (++it > 200) { set_err("solve_R: no bracket"); return -5; }
+  }
+  while (fhi > avg_deg) {
+    lo = hi; flo = fhi;
+    hi *= 1.5;
+    fhi = orc_hrg_expected_avg_degree(n, alpha, T, hi);
+    if (++it > 400) { set_err("solve_R: no bracket"); return -5; }
+  }
+  double glo = log(flo / avg_deg), ghi = log(fhi / avg_deg); /* glo >= 0 >= ghi */
+  int side = 0;
+  for (it = 0; it < 200 && (hi - lo) > 1e-12 * hi; it++) {
+    double mid = (glo == ghi) ? 0.5 * (lo + hi) : lo + (hi - lo) * glo / (glo - ghi);
+    if (!(mid > lo && mid < hi)) mid = 0.5 * (lo + hi);
+    double gm = log(orc_hrg_expected_avg_degree(n, alpha, T, mid) / avg_deg);
+    if (gm == 0.0) { lo = hi = mid; break; }
+    if (gm > 0.0) {
+      lo = mid; glo = gm;
+      if (side == 1) ghi *= 0.5;
+      side = 1;
+    } else {
+      hi = mid; ghi = gm;
+      if (side == -1) glo *= 0.5;
+      side = -1;
+    }
+  }
+  *R_out = 0.5 * (lo + hi);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The sampling run.                                                         */
+/* ------------------------------------------------------------------------- */
+typedef struct { uint32_t* a; uint64_t n, cap; } vec32;
+typedef struct { uint64_t* a; uint64_t n, cap; } vec64;
+static int push32(vec32* v, uint32_t x, uint32_t y) {
+  if (v->n + 2 > v->cap) {
+    uint64_t nc = v->cap ? 2 * v->cap : 1024;
+    uint32_t* p = (uint32_t*)realloc(v->a, nc * sizeof(uint32_t));
+    if (!p) return -1;
+    v->a = p; v->cap = nc;
+  }
+  v->a[v->n++] = x; v->a[v->n++] = y;
+  return 0;
+}
+static int push64x4(vec64* v, uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
+  if (v->n + 4 > v->cap) {
+    uint64_t nc = v->cap ? 2 * v->cap : 256;
+    uint64_t* p = (uint64_t*)realloc(v->a, nc * sizeof(uint64_t));
+    if (!p) return -1;
+    v->a = p; v->cap = nc;
+  }
+  v->a[v->n++] = a; v->a[v->n++] = b; v->a[v->n++] = c; v->a[v->n++] = d;
+  return 0;
+}
+
+struct orc_run {
+  orc_params p;
+  int L, D, Dmax;
+  double W, w0, kappa, coshR;
+  int32_t CL[ORC_MAX_LAYERS][ORC_MAX_LAYERS];
+  int32_t I[ORC_MAX_LAYERS];
+  int64_t count[ORC_MAX_LAYERS];
+  double ext[ORC_MAX_LAYERS];   /* GIRG: max weight of the layer; HRG: min radius */
+  uint64_t lstart[ORC_MAX_LAYERS + 1];
+  uint32_t* P[ORC_MAX_LAYERS];  /* prefix sums at level I(i), 2^{d I(i)} + 1 entries */
+  /* per original id */
+  int32_t* layer;
+  uint64_t* morton;             /* at level Dmax */
+  /* sorted order */
+  uint32_t* sid;                /* sorted position -> original id */
+  uint32_t* spos;               /* original id -> sorted position */
+  double* sw;                   /* weight (GIRG) or radius (HRG) */
+  double* sx;                   /* n*d */
+  /* output */
+  vec32 edges, near;
+  vec64 ties;
+  uint64_t ctr[ORC_NSTATS];
+  uint64_t lvl_nb[40], lvl_dist[40]; /* visited cell pairs per level */
+  int failed;
+};
+
+enum {
+  S_NBPAIRS = 5, S_DISTPAIRS = 6, S_T1ITEMS = 7, S_T2ITEMS = 8, S_TESTS = 9, S_DRAWS = 10,
+  S_CANDS = 11, S_EDGES = 12, S_NEAR = 13, S_TIES = 14, S_SEGS = 15, S_T1EDGES = 17,
+  S_T2EDGES = 18
+};
+
+void orc_free(orc_run* r) {
+  if (!r) return;
+  for (int i = 0; i < ORC_MAX_LAYERS; i++) free(r->P[i]);
+  free(r->layer); free(r->morton); free(r->sid); free(r->spos); free(r->sw); free(r->sx);
+  free(r->edges.a); free(r->near.a); free(r->ties.a);
+  free(r);
+}
+
+static int bitlen(uint64_t v) {
+  int b = 0;
+  while (v) { b++; v >>= 1; }
+  return b;
+}
+
+/* L-infinity distance on the torus (Sec. 2.1). */
+static double torus_dist(const double* a, const double* b, int d) {
+  double r = 0.0;
+  for (int k = 0; k < d; k++) {
+    double delta = fabs(a[k] - b[k]);
+    double m = delta < 1.0 - delta ? delta : 1.0 - delta;
+    if (m > r) r = m;
+  }
+  return r;
+}
+
+/* Edge probability of Eq. (1), T > 0.  r^d by repeated multiplication. */
+static double girg_p(const orc_run* R, double wu, double wv, double r) {
+  if (r == 0.0) return 1.0;
+  double rd = r;
+  for (int k = 1; k < R->p.d; k++) rd *= r;
+  double p = R->p.c * pow((wu * wv / R->W) / rd, 1.0 / R->p.T);
+  return p < 1.0 ? p : 1.0;
+}
+
+/* HRG: cosh of the hyperbolic distance (Sec. 2.2), written with the identity
+ * cosh r_u cosh r_v - sinh r_u sinh r_v cos(dtheta)
+ *   = cosh(r_u - r_v) + 2 sinh r_u sinh r_v sin^2(dtheta / 2),
+ * dtheta = 2 pi dx, which avoids the cancellation of the product form. */
+static double hrg_coshd(double ru, double rv, double dx) {
+  double s = sin(M_PI * dx);
+  return cosh(ru - rv) + 2.0 * sinh(ru) * sinh(rv) * s * s;
+}
+static double hrg_pT(const orc_run* R, double coshd) {
+  double dist = acosh(coshd);
+  return 1.0 / (exp((dist - R->p.R) / (2.0 * R->p.T)) + 1.0);
+}
+
+/* Morton code of the cell of sorted vertex s at level l. */
+static uint64_t cell_of_sorted(const orc_run* R, uint64_t s, int l) {
+  return R->morton[R->sid[s]] >> (R->p.d * (R->Dmax - l));
+}
+
+/* V_i^A as a range of sorted positions (Lemma 1). */
+static void vertex_range(const orc_run* R, int i, int l, uint64_t A, uint64_t* first, uint64_t* num) {
+  int sh = R->p.d * (R->I[i] - l);
+  uint64_t lo = R->P[i][A << sh], hi = R->P[i][(A + 1) << sh];
+  *first = lo; *num = hi - lo;
+}
+
+/* Per-dimension torus distance between cell coordinates at level l. */
+static void cell_deltas(const orc_run* R, uint64_t A, uint64_t B, int l, uint32_t* delta) {
+  uint32_t ca[8], cb[8];
+  int d = R->p.d;
+  orc_morton_decode(A, d, l, ca);
+  orc_morton_decode(B, d, l, cb);
+  uint64_t side = (uint64_t)1 << l;
+  for (int k = 0; k < d; k++) {
+    uint64_t df = ca[k] > cb[k] ? ca[k] - cb[k] : cb[k] - ca[k];
+    uint64_t wrap = side - df;
+    delta[k] = (uint32_t)(df < wrap ? df : wrap);
+  }
+}
+static int are_neighbours(const orc_run* R, uint64_t A, uint64_t B, int l) {
+  uint32_t delta[8];
+  cell_deltas(R, A, B, l, delta);
+  for (int k = 0; k < R->p.d; k++)
+    if (delta[k] > 1) return 0;
+  return 1;
+}
+
+/* ---- type-I: every pair of V_i^A x V_j^B gets its own coin (Sec. 3.2). ---- */
+static void emit(orc_run* R, uint32_t u, uint32_t v, int type) {
+  if (push32(&R->edges, u, v)) R->failed = 1;
+  R->ctr[S_EDGES]++;
+  R->ctr[type ? S_T2EDGES : S_T1EDGES]++;
+}
+static void near_pair(orc_run* R, uint32_t u, uint32_t v) {
+  if (push32(&R->near, u, v)) R->failed = 1;
+  R->ctr[S_NEAR]++;
+}
+
+static void type1_pair(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j, uint64_t su,
+                       uint64_t sv, uint64_t k) {
+  const orc_params* p = &R->p;
+  uint32_t u = R->sid[su], v = R->sid[sv];
+  R->ctr[S_TESTS]++;
+  if (p->accept_all) { emit(R, u, v, 0); return; }
+  const double* xu = R->sx + su * (uint64_t)p->d;
+  const double* xv = R->sx + sv * (uint64_t)p->d;
+  double r = torus_dist(xu, xv, p->d);
+  if (p->model == 0 && p->T == 0.0) {
+    /* threshold variant: edge iff ||x_u - x_v|| <= c (w_u w_v / W)^{1/d} */
+    double t = p->c * pow(R->sw[su] * R->sw[sv] / R->W, 1.0 / p->d);
+    if (fabs(r - t) <= 1e-12 * t) near_pair(R, u, v);
+    if (r <= t) emit(R, u, v, 0);
+    return;
+  }
+  if (p->model == 1 && p->T == 0.0) {
+    /* threshold HRG: edge iff d < R, i.e. cosh d < cosh R (Sec. 4.3) */
+    double ch = hrg_coshd(R->sw[su], R->sw[sv], r);
+    if (fabs(ch - R->coshR) <= 1e-12 * R->coshR) near_pair(R, u, v);
+    if (ch < R->coshR) emit(R, u, v, 0);
+    return;
+  }
+  double prob = p->model == 0 ? girg_p(R, R->sw[su], R->sw[sv], r)
+                              : hrg_pT(R, hrg_coshd(R->sw[su], R->sw[sv], r));
+  uint64_t blk = k >> 1;
+  uint32_t o[4];
+  stream_block(p->seed, (uint32_t)blk, (uint32_t)A, (uint32_t)B,
+               word3(l, i, j, KIND_TYPE1, (uint32_t)(blk >> 32)), o);
+  int h = (int)(k & 1);
+  double U = orc_u53(o[2 * h], o[2 * h + 1]);
+  if (fabs(U - prob) < 1e-12) near_pair(R, u, v);
+  if (U < prob) emit(R, u, v, 0);
+}
+
+static void type1(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
+  uint64_t a0, na, b0, nb;
+  vertex_range(R, i, l, A, &a0, &na);
+  vertex_range(R, j, l, B, &b0, &nb);
+  if (na == 0 || nb == 0) return;
+  if (A == B && i == j) {
+    if (na < 2) return;
+    R->ctr[S_T1ITEMS]++;
+    /* only a < b within V_i^A (App. B.1); pair index k = b(b-1)/2 + a */
+    for (uint64_t b = 1; b < na; b++)
+      for (uint64_t a = 0; a < b; a++) type1_pair(R, l, A, B, i, j, a0 + a, a0 + b, b * (b - 1) / 2 + a);
+    return;
+  }
+  R->ctr[S_T1ITEMS]++;
+  for (uint64_t a = 0; a < na; a++)
+    for (uint64_t b = 0; b < nb; b++) type1_pair(R, l, A, B, i, j, a0 + a, b0 + b, a * nb + b);
+}
+
+/* ---- type-II: geometric jumps under pbar, acceptance p_uv / pbar (Sec. 3.2). ---- */
+#define SEG_EXP 5
+#define SEG_MAX_BITS 12
+
+/* Upper bound pbar for the layer pair (i,j) at level l with gap g: the maximum
+ * weights of the layers and the minimum distance g 2^-l between points of the
+ * two cells (GIRG); for the HRG the smallest radii of the layers and the same
+ * minimum angular distance. */
+static double type2_pbar(const orc_run* R, int l, int i, int j, int g) {
+  const orc_params* p = &R->p;
+  if (p->accept_all) return 1.0;
+  double dist = ldexp((double)g, -l);
+  if (p->model == 0) {
+    double dd = dist;
+    for (int k = 1; k < p->d; k++) dd *= dist;
+    double pb = p->c * pow((R->ext[i] * R->ext[j] / R->W) / dd, 1.0 / p->T);
+    return pb < 1.0 ? pb : 1.0;
+  }
+  double s = sin(M_PI * dist);
+  double ch = 1.0 + 2.0 * sinh(R->ext[i]) * sinh(R->ext[j]) * s * s;
+  return hrg_pT(R, ch);
+}
+
+static int near_pow2(double x) {
+  int e;
+  double m = frexp(x, &e); /* x = m 2^e, m in [0.5, 1) */
+  return m < 0.5 * (1.0 + 4.0 * 0x1p-52) || m > 1.0 - 4.0 * 0x1p-53;
+}
+
+static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
+  const orc_params* p = &R->p;
+  uint64_t a0, na, b0, nb;
+  vertex_range(R, i, l, A, &a0, &na);
+  vertex_range(R, j, l, B, &b0, &nb);
+  if (na == 0 || nb == 0) return;
+  R->ctr[S_T2ITEMS]++;
+  uint32_t delta[8];
+  cell_deltas(R, A, B, l, delta);
+  int g = 0;
+  for (int k = 0; k < p->d; k++)
+    if ((int)delta[k] - 1 > g) g = (int)delta[k] - 1;
+  double pbar = type2_pbar(R, l, i, j, g);
+  if (!(pbar > 0.0)) return;
+  double Lg = log1p(-pbar);
+  uint64_t N = na * nb;
+  /* The candidate range [0, N) is cut into segments of G = 2^e candidates,
+   * each with its own geometric-jump sequence (exact: the candidates are
+   * independent).  e = 5 - ilogb(pbar), raised until at most 2^12 segments. */
+  int e = SEG_EXP - ilogb(pbar);
+  int emin = bitlen(N - 1) - SEG_MAX_BITS;
+  if (e < emin) e = emin;
+  uint64_t G = (e >= 63 || ((uint64_t)1 << e) >= N) ? N : ((uint64_t)1 << e);
+  uint64_t nseg = (N + G - 1) / G;
+  int tie = near_pow2(pbar) && e > emin;
+  for (uint64_t s = 0; s < nseg; s++) {
+    uint64_t k = s * G, kend = (s + 1) * G < N ? (s + 1) * G : N;
+    R->ctr[S_SEGS]++;
+    for (uint32_t t = 0;; t++) {
+      uint32_t o[4];
+      stream_block(p->seed, t, (uint32_t)A, (uint32_t)B,
+                   word3(l, i, j, KIND_TYPE2, (uint32_t)s), o);
+      R->ctr[S_DRAWS]++;
+      double S = orc_u53_open(o[0], o[1]);
+      double Acc = orc_u53(o[2], o[3]);
+      /* number of skipped candidates: X ~ Geom_0(pbar) = floor(ln S / ln(1 - pbar)) */
+      double q = pbar >= 1.0 ? 0.0 : log(S) / Lg;
+      /* a skip length whose quotient lies within 1e-12 (relative) of an
+       * integer >= 1 may round either way under another libm; it matters only
+       * when it decides a candidate or the end of the segment: log the item */
+      double fl = floor(q + 0.5);
+      if (pbar < 1.0 && fl >= 1.0 && fabs(q - fl) < 1e-12 * q && q < (double)(kend - k) + 1.0) tie = 1;
+      if (q >= (double)(kend - k)) break;
+      k += (uint64_t)q;
+      uint64_t a = k / nb, b = k % nb;
+      uint64_t su = a0 + a, sv = b0 + b;
+      uint32_t u = R->sid[su], v = R->sid[sv];
+      R->ctr[S_CANDS]++;
+      if (p->accept_all) {
+        emit(R, u, v, 1);
+      } else {
+        double r = torus_dist(R->sx + su * (uint64_t)p->d, R->sx + sv * (uint64_t)p->d, p->d);
+        double prob = p->model == 0 ? girg_p(R, R->sw[su], R->sw[sv], r)
+                                    : hrg_pT(R, hrg_coshd(R->sw[su], R->sw[sv], r));
+        double lhs = Acc * pbar;
+        if (fabs(lhs - prob) < 1e-12) near_pair(R, u, v);
+        if (lhs < prob) emit(R, u, v, 1);
+      }
+      k += 1;
+      if (k >= kend) break;
+    }
+  }
+  if (tie) {
+    if (push64x4(&R->ties, a0, na, b0, nb)) R->failed = 1;
+    R->ctr[S_TIES]++;
+  }
+}
+
+/* ---- Algorithm 1: recursive iteration of cell pairs (Sec. 3.3). ---- */
+static int any_nonempty(const orc_run* R, int l, uint64_t A) {
+  /* some layer with I(i) > l has vertices in A (a recursion below l can only
+   * touch such layers) */
+  for (int i = 0; i < R->L; i++) {
+    if (R->count[i] == 0 || R->I[i] <= l) continue;
+    uint64_t f, num;
+    vertex_range(R, i, l, A, &f, &num);
+    if (num) return 1;
+  }
+  return 0;
+}
+
+static void recur(orc_run* R, int l, uint64_t A, uint64_t B, int nb, int selected) {
+  const orc_params* p = &R->p;
+  if (p->filter_mod && l == p->filter_level) selected = (A % p->filter_mod) == p->filter_rem;
+  if (selected) {
+    R->ctr[nb ? S_NBPAIRS : S_DISTPAIRS]++;
+    if (nb) R->lvl_nb[l]++; else R->lvl_dist[l]++;
+    /* for all bucket pairs (i,j) that process (A,B): neighbouring pairs at
+     * level l serve pairs with CL(i,j) = l, distant ones those with CL >= l
+     * (loop swap, Sec. 3.3).  A <= B; for A = B only i <= j (App. B.1). */
+    for (int i = 0; i < R->L; i++) {
+      if (R->count[i] == 0) continue;
+      for (int j = 0; j < R->L; j++) {
+        if (R->count[j] == 0) continue;
+        if (A == B && j < i) continue;
+        if (nb) {
+          if (R->CL[i][j] == l) type1(R, l, A, B, i, j);
+        } else {
+          /* threshold variants: distant cells hold no edges (their points are
+           * farther apart than the cell side, which is at least the threshold) */
+          if (R->CL[i][j] >= l && p->T > 0.0) type2(R, l, A, B, i, j);
+        }
+      }
+    }
+  }
+  if (!nb || l >= R->D) return;
+  /* children of neighbouring pairs (lines 8-9 of the algorithm), A <= B */
+  if (!any_nonempty(R, l, A) || !any_nonempty(R, l, B)) return;
+  int d = p->d;
+  uint64_t nch = (uint64_t)1 << d;
+  for (uint64_t x = 0; x < nch; x++)
+    for (uint64_t y = 0; y < nch; y++) {
+      uint64_t X = (A << d) | x, Y = (B << d) | y;
+      if (A == B && Y < X) continue;
+      recur(R, l + 1, X, Y, are_neighbours(R, X, Y, l + 1), selected);
+    }
+}
+
+/* ---- setup: layers, levels, sorted layout ---- */
+static const orc_run* g_sort_ctx;
+static int cmp_sorted(const void* a, const void* b) {
+  uint32_t u = *(const uint32_t*)a, v = *(const uint32_t*)b;
+  const orc_run* R = g_sort_ctx;
+  if (R->layer[u] != R->layer[v]) return R->layer[u] < R->layer[v] ? -1 : 1;
+  if (R->morton[u] != R->morton[v]) return R->morton[u] < R->morton[v] ? -1 : 1;
+  return (u > v) - (u < v);
+}
+
+orc_run* orc_run_graph(const orc_params* pin, const double* w, const double* x) {
+  const orc_params* p = pin;
+  uint64_t n = p->n;
+  int d = p->d;
+  if (n < 1 || n > 0xFFFFFFFFull) { set_err("n must be in [1, 2^32-1]"); return NULL; }
+  if (d < 1 || d > 8) { set_err("d must be in [1, 8]"); return NULL; }
+  if (p->model == 1 && d != 1) { set_err("HRG requires d = 1"); return NULL; }
+  if (!(p->T >= 0.0 && p->T < 1.0)) { set_err("T must be in [0, 1)"); return NULL; }
+  if (p->model == 0 && !(p->c > 0.0)) { set_err("c must be > 0"); return NULL; }
+  if (p->model == 1 && !(p->R > 0.0)) { set_err("R must be > 0"); return NULL; }
+  if (p->T == 0.0 && p->cl_bias > 0) { set_err("cl_bias > 0 is inexact at T = 0"); return NULL; }
+  orc_run* R = (orc_run*)calloc(1, sizeof(orc_run));
+  if (!R) { set_err("out of memory"); return NULL; }
+  R->p = *p;
+  R->Dmax = 32 / d;
+  R->layer = (int32_t*)malloc(sizeof(int32_t) * n);
+  R->morton = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  R->sid = (uint32_t*)malloc(sizeof(uint32_t) * n);
+  R->spos = (uint32_t*)malloc(sizeof(uint32_t) * n);
+  R->sw = (double*)malloc(sizeof(double) * n);
+  R->sx = (double*)malloc(sizeof(double) * n * d);
+  if (!R->layer || !R->morton || !R->sid || !R->spos || !R->sw || !R->sx) {
+    orc_free(R); set_err("out of memory"); return NULL;
+  }
+  for (uint64_t u = 0; u < n * (uint64_t)d; u++)
+    if (!(x[u] >= 0.0 && x[u] < 1.0)) { orc_free(R); set_err("positions must lie in [0,1)"); return NULL; }
+
+  /* weight buckets (Sec. 3.1): max / min weight within a bucket at most 2 */
+  if (p->model == 0) {
+    R->W = sum_ld(w, n);
+    double w0 = w[0];
+    for (uint64_t u = 0; u < n; u++) {
+      if (!(w[u] > 0.0) || isinf(w[u])) { orc_free(R); set_err("weights must be finite and > 0"); return NULL; }
+      if (w[u] < w0) w0 = w[u];
+    }
+    R->w0 = w0;
+    for (uint64_t u = 0; u < n; u++) {
+      int li = ilogb(w[u] / w0);
+      if (li >= ORC_MAX_LAYERS) { orc_free(R); set_err("weight range exceeds 2^64"); return NULL; }
+      R->layer[u] = li;
+    }
+  } else {
+    /* HRG -> GIRG mapping (Sec. 2.3): w = exp((R - r)/2), so the bucket of a
+     * vertex is floor(log2 w) = floor((R - r) / (2 ln 2)). */
+    R->coshR = cosh(p->R);
+    for (uint64_t u = 0; u < n; u++) {
+      if (!(w[u] >= 0.0 && w[u] <= p->R)) { orc_free(R); set_err("radii must lie in [0, R]"); return NULL; }
+      int li = (int)floor((p->R - w[u]) / (2.0 * 0.6931471805599453));
+      if (li >= ORC_MAX_LAYERS) { orc_free(R); set_err("radius range too large"); return NULL; }
+      R->layer[u] = li;
+    }
+  }
+  R->L = 0;
+  for (int i = 0; i < ORC_MAX_LAYERS; i++) { R->count[i] = 0; R->ext[i] = 0.0; }
+  for (uint64_t u = 0; u < n; u++) {
+    int li = R->layer[u];
+    if (li + 1 > R->L) R->L = li + 1;
+    if (R->count[li] == 0 || (p->model == 0 ? w[u] > R->ext[li] : w[u] < R->ext[li])) R->ext[li] = w[u];
+    R->count[li]++;
+  }
+
+  /* comparison levels (Sec. 3.1): the deepest level whose cell side is at
+   * least the connection threshold of the largest weights of the two buckets;
+   * HRG: found by search over levels (Sec. 4.3). */
+  int Dcap = (bitlen(n) + 3) / d;
+  if (Dcap > R->Dmax) Dcap = R->Dmax;
+  if (p->model == 0) R->kappa = p->T > 0.0 ? pow(p->c, p->T) : 0.0;
+  for (int i = 0; i < ORC_MAX_LAYERS; i++)
+    for (int j = 0; j < ORC_MAX_LAYERS; j++) R->CL[i][j] = -1;
+  R->D = 0;
+  for (int i = 0; i < R->L; i++) {
+    if (!R->count[i]) continue;
+    for (int j = 0; j < R->L; j++) {
+      if (!R->count[j]) continue;
+      int l = 0;
+      if (p->model == 0 && p->T == 0.0) {
+        double tmax = p->c * pow(R->ext[i] * R->ext[j] / R->W, 1.0 / d);
+        while (l < Dcap && ldexp(1.0, -(l + 1)) >= tmax) l++;
+      } else if (p->model == 0) {
+        double V = R->kappa * R->ext[i] * R->ext[j] / R->W;
+        while (l < Dcap && ldexp(1.0, -(l + 1) * d) >= V) l++;
+      } else {
+        double shh = 2.0 * sinh(R->ext[i]) * sinh(R->ext[j]);
+        while (l < Dcap) {
+          int nl = l + 1;
+          if (nl >= 2) {
+            double s = sin(M_PI * ldexp(1.0, -nl));
+            if (!(1.0 + shh * s * s >= R->coshR)) break;
+          }
+          l = nl;
+        }
+      }
+      l += p->cl_bias;
+      if (l < 0) l = 0;
+      if (l > Dcap) l = Dcap;
+      if (p->max_depth >= 0 && l > p->max_depth) l = p->max_depth;
+      R->CL[i][j] = l;
+      if (l > R->D) R->D = l;
+    }
+  }
+  for (int i = 0; i < R->L; i++) {
+    R->I[i] = -1;
+    if (!R->count[i]) continue;
+    for (int j = 0; j < R->L; j++)
+      if (R->count[j] && R->CL[i][j] > R->I[i]) R->I[i] = R->CL[i][j];
+  }
+
+  /* cells: Morton code at level Dmax; the cell at level l is its top d*l bits */
+  for (uint64_t u = 0; u < n; u++) {
+    uint32_t q[8];
+    for (int k = 0; k < d; k++) q[k] = (uint32_t)(x[u * (uint64_t)d + k] * ldexp(1.0, R->Dmax));
+    R->morton[u] = orc_morton_encode(q, d, R->Dmax);
+  }
+  /* sort by (bucket, Morton code, id): within a bucket this orders vertices by
+   * their cell on every level, in particular on I(i) (Sec. 3.4); the paper
+   * leaves the tie-break free, we break ties by the finer cells, then by id. */
+  for (uint64_t u = 0; u < n; u++) R->sid[u] = (uint32_t)u;
+  g_sort_ctx = R;
+  qsort(R->sid, n, sizeof(uint32_t), cmp_sorted);
+  for (uint64_t s = 0; s < n; s++) {
+    uint32_t u = R->sid[s];
+    R->spos[u] = (uint32_t)s;
+    R->sw[s] = w[u];
+    for (int k = 0; k < d; k++) R->sx[s * d + k] = x[u * (uint64_t)d + k];
+  }
+  uint64_t acc = 0;
+  for (int i = 0; i < R->L; i++) { R->lstart[i] = acc; acc += (uint64_t)R->count[i]; }
+  R->lstart[R->L] = acc;
+  /* prefix sums P_C per bucket at its insertion level (Lemma 1, App. A) */
+  for (int i = 0; i < R->L; i++) {
+    if (!R->count[i]) continue;
+    uint64_t ncell = (uint64_t)1 << (d * R->I[i]);
+    R->P[i] = (uint32_t*)calloc(ncell + 1, sizeof(uint32_t));
+    if (!R->P[i]) { orc_free(R); set_err("out of memory (cell offsets)"); return NULL; }
+    for (uint64_t s = R->lstart[i]; s < R->lstart[i + 1]; s++) R->P[i][cell_of_sorted(R, s, R->I[i]) + 1]++;
+    R->P[i][0] = (uint32_t)R->lstart[i];
+    for (uint64_t cidx = 1; cidx <= ncell; cidx++) R->P[i][cidx] += R->P[i][cidx - 1];
+  }
+
+  recur(R, 0, 0, 0, 1, p->filter_mod == 0 || p->filter_level > 0);
+  if (R->failed) { orc_free(R); set_err("out of memory (edges)"); return NULL; }
+  return R;
+}
+
+uint64_t orc_num_edges(const orc_run* r) { return r->edges.n / 2; }
+void orc_copy_edges(const orc_run* r, uint32_t* out) { memcpy(out, r->edges.a, r->edges.n * sizeof(uint32_t)); }
+uint64_t orc_num_near(const orc_run* r) { return r->near.n / 2; }
+void orc_copy_near(const orc_run* r, uint32_t* out) { memcpy(out, r->near.a, r->near.n * sizeof(uint32_t)); }
+uint64_t orc_num_ties(const orc_run* r) { return r->ties.n / 4; }
+void orc_copy_ties(const orc_run* r, uint64_t* out) { memcpy(out, r->ties.a, r->ties.n * sizeof(uint64_t)); }
+void orc_copy_sorted_ids(const orc_run* r, uint32_t* out) { memcpy(out, r->sid, r->p.n * sizeof(uint32_t)); }
+
+void orc_stats(const orc_run* r, double* out) {
+  for (int k = 0; k < ORC_NSTATS; k++) out[k] = (double)r->ctr[k];
+  out[0] = r->W; out[1] = r->w0; out[2] = r->L; out[3] = r->D; out[4] = r->Dmax;
+  out[16] = r->p.model == 0 ? r->kappa : r->coshR;
+}
+
+void orc_level_counts(const orc_run* r, uint64_t* nb, uint64_t* dist) {
+  for (int l = 0; l < 40; l++) { nb[l] = r->lvl_nb[l]; dist[l] = r->lvl_dist[l]; }
+}
+
+void orc_tables(const orc_run* r, int32_t* CL, int32_t* I, int64_t* count, double* ext) {
+  for (int i = 0; i < ORC_MAX_LAYERS; i++) {
+    for (int j = 0; j < ORC_MAX_LAYERS; j++) CL[i * ORC_MAX_LAYERS + j] = r->CL[i][j];
+    I[i] = i < r->L ? r->I[i] : -1;
+    count[i] = r->count[i];
+    ext[i] = r->ext[i];
+  }
+}
+
+void orc_pair_item(const orc_run* r, uint32_t u, uint32_t v, int64_t* out) {
+  int d = r->p.d;
+  int i = r->layer[u], j = r->layer[v];
+  int cl = r->CL[i][j];
+  int level = cl, type = 0;
+  for (int l = 2; l <= cl; l++) {
+    uint64_t A = r->morton[u] >> (d * (r->Dmax - l)), B = r->morton[v] >> (d * (r->Dmax - l));
+    if (!are_neighbours(r, A, B, l)) { level = l; type = 1; break; }
+  }
+  uint64_t A = r->morton[u] >> (d * (r->Dmax - level)), B = r->morton[v] >> (d * (r->Dmax - level));
+  int swapped = 0;
+  if (A > B) swapped = 1;
+  else if (A == B && j < i) swapped = 1;
+  else if (A == B && i == j) {
+    /* local order a < b inside V_i^A: sorted position */
+    swapped = r->spos[u] > r->spos[v];
+  }
+  out[0] = level;
+  out[1] = (int64_t)(swapped ? B : A);
+  out[2] = (int64_t)(swapped ? A : B);
+  out[3] = swapped ? j : i;
+  out[4] = swapped ? i : j;
+  out[5] = type;
+  out[6] = swapped;
+}
