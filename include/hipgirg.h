@@ -1,0 +1,152 @@
+/*
+ * hipgirg.h -- C ABI of the MI355X (gfx950) sampler for geometric
+ * inhomogeneous random graphs (GIRGs) and hyperbolic random graphs (HRGs)
+ * after Blaesius, Friedrich, Katzmann, Meyer, Penschuck, Weyand,
+ * "Efficiently Generating Geometric Inhomogeneous and Hyperbolic Random
+ * Graphs" (arXiv:1905.06706).
+ *
+ * Conventions shared by every call
+ *  - Every call returns a girg_status; no C++ exception crosses the ABI.  On
+ *    an error girg_last_error() returns a message (thread-local, valid until
+ *    the next call on that thread).
+ *  - "device pointer" arguments are HIP device allocations on the current
+ *    device; the caller owns them.  The library owns only internal scratch
+ *    memory, cached per device and grown on demand (freed by girg_release).
+ *  - `stream` is a hipStream_t (passed as void*; NULL = the null stream).
+ *    Calls are stream-ordered but synchronise that stream before returning
+ *    (they read small results, such as the edge count, back to the host).
+ *  - Positions are stored dimension-major: x[k * n + v] is coordinate k of
+ *    vertex v.  Vertex ids are 0..n-1 in generation order.
+ *  - Edges are written as uint32 pairs (u, v), edges[2e], edges[2e+1], with
+ *    u != v and every unordered pair at most once.  Their order is
+ *    deterministic: a pure function of the parameters and the seed.
+ *  - Randomness: Philox4x32-10 (Salmon et al., SC 2011) keyed by the seed;
+ *    the counter packs (level, cell pair, layer pair, kind, index).  Two calls
+ *    with equal parameters and seed return identical edge arrays.
+ */
+#ifndef HIPGIRG_H
+#define HIPGIRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GIRG_OK = 0,
+  GIRG_EINVAL = -1,    /* invalid parameter (message says which) */
+  GIRG_ENOMEM = -2,    /* device or host allocation failed */
+  GIRG_EDEVICE = -3,   /* a HIP call failed (no device, launch failure) */
+  GIRG_EOVERFLOW = -4, /* edge capacity too small: *m_out holds the edge count
+                          needed; the edge buffer contents are undefined */
+  GIRG_ENOCONV = -5    /* the c or R solve found no bracket */
+} girg_status;
+
+/* Model parameters.
+ *  GIRG (model 0), Eq. (1) of Sec. 2.1: p_uv = min(1, c ((w_u w_v / W) /
+ *    ||x_u - x_v||^d)^(1/T)) for 0 < T < 1; threshold variant at T = 0: edge
+ *    iff ||x_u - x_v|| <= c (w_u w_v / W)^(1/d).  ||.|| is the L-infinity
+ *    distance on the torus [0,1)^d.
+ *  HRG (model 1), Sec. 2.2: radii r in [0,R) with density
+ *    alpha sinh(alpha r) / (cosh(alpha R) - 1), angles uniform; threshold
+ *    variant: edge iff the hyperbolic distance is below R; binomial variant:
+ *    p_T(d) = 1 / (exp((d - R) / (2T)) + 1).
+ * Validation: n in [2, 2^32-1]; GIRG: d in [1, 4], beta > 2, 0 <= T < 1,
+ * exactly one of avg_deg > 0 (solve c, Sec. 4.1 / App. B.2) or c > 0;
+ * HRG: alpha > 1/2, 0 <= T < 1, R > 0 given or avg_deg > 0 (solve R). */
+typedef struct {
+  uint64_t n;
+  int32_t d;          /* GIRG dimension (HRG: ignored, 1) */
+  int32_t model;      /* 0 = GIRG, 1 = HRG */
+  double beta;        /* GIRG power-law exponent of the weights (w_min = 1) */
+  double T;           /* temperature */
+  double avg_deg;     /* expected average degree (0 = use c / R) */
+  double c;           /* GIRG constant (0 = solve from avg_deg) */
+  double alpha;       /* HRG radial dispersion */
+  double R;           /* HRG disk radius (0 = solve from avg_deg) */
+  uint64_t seed;
+  int32_t precision;  /* 0 = FP64; 1 = FP32 filter with FP64 recheck */
+  int32_t max_depth;  /* debug knob, -1 = none: caps the comparison levels */
+  int32_t cl_bias;    /* debug knob, 0 = none: shifts the comparison levels
+                         (> 0 only for T > 0); every value samples exactly */
+  int32_t reserved;
+} girg_params;
+
+/* Diagnostics of one call. */
+typedef struct {
+  uint64_t m;            /* edges */
+  uint64_t type1_edges, type2_edges;
+  uint64_t tests;        /* type-I pair tests */
+  uint64_t draws;        /* type-II geometric draws */
+  uint64_t candidates;   /* type-II candidates tested */
+  uint64_t rechecks;     /* mixed precision: decisions re-done in FP64 */
+  uint64_t sources;      /* (layer, level, cell) runs */
+  uint64_t heavy_items;  /* type-II items split into segments */
+  uint64_t cells;        /* prefix-sum entries */
+  double c, W, R;        /* constants used */
+  int32_t L, D;          /* layers, deepest level */
+  int32_t reserved[2];
+} girg_info;
+
+/* girg_generate: points (Sec. 2.1 weights and positions), constant c
+ * (App. B.2) when avg_deg > 0, then the sampler of Sec. 3 (Algorithm 1 with
+ * type-I tests and type-II geometric jumps).  edges: device pointer to
+ * 2*cap uint32.  m_out: host pointer.  info: host pointer or NULL. */
+girg_status girg_generate(const girg_params* p, uint32_t* edges, uint64_t cap, uint64_t* m_out,
+                          girg_info* info, void* stream);
+
+/* girg_hrg: HRG of Sec. 2.2 through the GIRG mapping of Sec. 2.3 (w =
+ * exp((R - r)/2), x = theta / 2 pi) with the HRG decisions of Sec. 4.3.  R
+ * (> 0) is used as given; R = 0 solves it from avg_deg. */
+girg_status girg_hrg(uint64_t n, double alpha, double T, double R, double avg_deg, uint64_t seed,
+                     uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info, void* stream);
+
+/* girg_from_points: the sampler alone over caller-provided points (device
+ * pointers).  GIRG: w = weights (> 0), x = positions in [0,1), dimension-
+ * major [d][n]; c given or solved from avg_deg over these weights.  HRG:
+ * w = radii in [0, R], x = angle / (2 pi) in [0,1); R must be given. */
+girg_status girg_from_points(const girg_params* p, const double* w, const double* x,
+                             uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
+                             void* stream);
+
+/* girg_points: only the point generation (GIRG: w[n], x[d][n]; HRG: r[n],
+ * x[n] with R required).  Device pointers. */
+girg_status girg_points(const girg_params* p, double* w, double* x, void* stream);
+
+/* girg_solve_c: c for a target average degree over given weights (host
+ * pointer), App. B.2: exponential then binary search on the monotone
+ * expected average degree f(c). */
+girg_status girg_solve_c(const double* w_host, uint64_t n, int32_t d, double T, double avg_deg,
+                         double* c_out);
+
+/* girg_expected_degree: f(c) of App. B.2 for given weights (host pointer). */
+girg_status girg_expected_degree(const double* w_host, uint64_t n, int32_t d, double T, double c,
+                                 double* deg_out);
+
+/* hrg_solve_R: radius R with the given expected average degree (numerical
+ * integration over the model of Sec. 2.2; the paper gives no formula). */
+girg_status hrg_solve_R(uint64_t n, double alpha, double T, double avg_deg, double* R_out);
+
+/* hrg_expected_degree: expected average degree of an HRG with radius R. */
+girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, double* deg_out);
+
+/* girg_generate_batch: `count` independent GIRGs p[0..count-1]; graph b's
+ * edges occupy edges[2*offsets[b] .. 2*offsets[b+1]) and carry its own vertex
+ * ids.  offsets: host pointer to count+1 entries; infos: host array of count
+ * or NULL.  GIRG_EOVERFLOW leaves offsets[count] = edges needed. */
+girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
+                                uint64_t* offsets, girg_info* infos, void* stream);
+
+/* Frees the scratch memory cached for the current device. */
+girg_status girg_release(void);
+
+const char* girg_last_error(void);
+
+/* Library version string. */
+const char* girg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,863 @@
+// api.hip -- host driver and C ABI of the gfx950 GIRG / HRG sampler.
+//
+// One call runs, on one stream:
+//   points (optional) -> exact sums and min/max -> layer + Morton keys ->
+//   stable radix sort -> sorted SoA -> constant c (App. B.2, when asked) ->
+//   level tables -> prefix sums per layer (Lemma 1) -> run sources ->
+//   count passes (type-I, type-II, heavy type-II segments) -> one scan of the
+//   per-wave counts -> write passes.
+// The host only orchestrates and solves the scalar parameter equations (c by
+// bisection over sums reduced on the device; R by quadrature).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hipgirg.h"
+#include "sampler.h"
+
+namespace hg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+static girg_status fail(girg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(e_ == hipErrorOutOfMemory ? GIRG_ENOMEM : GIRG_EDEVICE,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+void* Arena::raw(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes == 0) bytes = 256;
+  for (size_t c = cur_; c < chunks_.size(); ++c) {
+    Chunk& ch = chunks_[c];
+    if (ch.size - ch.used >= bytes) {
+      void* p = ch.base + ch.used;
+      ch.used += bytes;
+      cur_ = c;
+      return p;
+    }
+  }
+  const size_t sz = std::max(bytes, (size_t)64 << 20);
+  void* p = nullptr;
+  if (hipMalloc(&p, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    failed_ = true;
+    return nullptr;
+  }
+  chunks_.push_back(Chunk{static_cast<char*>(p), sz, bytes});
+  cur_ = chunks_.size() - 1;
+  return p;
+}
+void Arena::release() {
+  for (auto& c : chunks_) (void)hipFree(c.base);
+  chunks_.clear();
+  cur_ = 0;
+}
+
+// ---------------------------------------------------------------------------
+// per-device context
+// ---------------------------------------------------------------------------
+struct Ctx {
+  int device = -1;
+  Arena ar;
+  Graph* gd = nullptr;       // device Graph
+  double* red = nullptr;     // 6 doubles
+  uint32_t* flag = nullptr;
+  unsigned long long* stats = nullptr;  // 8
+  unsigned int* hcount = nullptr;
+  std::mutex mu;
+  ~Ctx() {
+    if (gd) (void)hipFree(gd);
+    if (red) (void)hipFree(red);
+    if (flag) (void)hipFree(flag);
+    if (stats) (void)hipFree(stats);
+    if (hcount) (void)hipFree(hcount);
+  }
+};
+
+static std::mutex g_ctx_mu;
+static std::map<int, std::unique_ptr<Ctx>> g_ctx;
+
+static girg_status get_ctx(Ctx** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) {
+    *out = it->second.get();
+    return GIRG_OK;
+  }
+  std::unique_ptr<Ctx> c(new Ctx());
+  c->device = dev;
+  HIPCHK(hipMalloc(&c->gd, sizeof(Graph)));
+  HIPCHK(hipMalloc(&c->red, 8 * sizeof(double)));
+  HIPCHK(hipMalloc(&c->flag, sizeof(uint32_t)));
+  HIPCHK(hipMalloc(&c->stats, 8 * sizeof(unsigned long long)));
+  HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
+  *out = c.get();
+  g_ctx[dev] = std::move(c);
+  return GIRG_OK;
+}
+
+static int bitlen(uint64_t v) {
+  int b = 0;
+  while (v) { ++b; v >>= 1; }
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// constant c from the average degree (Sec. 4.1, App. B.2).  f(c) = E[avg
+// degree] is monotone in c; its closed form has an error term over E_R, the
+// ordered pairs whose saturation radius k exceeds 1/2.  E_R only involves the
+// heaviest vertices: with weights sorted in descending order, the partners of
+// u form a prefix whose length shrinks as u gets lighter, so prefix sums of w
+// and w^(1/T) give each vertex's term in O(1) (the O(|R|) evaluation).
+// ---------------------------------------------------------------------------
+struct CSolve {
+  uint64_t n;
+  int d;
+  double T, W, s1, s2;     // s1 = sum_{u != v} w_u w_v / W ; s2 = same with (.)^(1/T)
+  std::vector<double> h;   // heaviest weights, descending
+  std::vector<double> pw, pp;  // prefix sums of h and h^(1/T)
+  double wcut;             // every weight not in h is <= wcut
+  bool incomplete = false;
+
+  void prepare() {
+    std::sort(h.begin(), h.end(), [](double a, double b) { return a > b; });
+    pw.assign(h.size() + 1, 0.0);
+    pp.assign(h.size() + 1, 0.0);
+    for (size_t i = 0; i < h.size(); ++i) {
+      pw[i + 1] = pw[i] + h[i];
+      pp[i + 1] = pp[i] + (T > 0.0 ? std::pow(h[i], 1.0 / T) : 0.0);
+    }
+  }
+
+  double f(double c) {
+    const double th = T > 0.0 ? std::ldexp(W / std::pow(c, T), -d)
+                              : W / std::ldexp(std::pow(c, (double)d), d);
+    // a pair (u, v) is in E_R iff w_u w_v > th
+    if (!h.empty() && h[0] * wcut > th) incomplete = true;
+    double A, B = 0.0;
+    if (T > 0.0) {
+      A = std::pow(c, T) * std::ldexp(1.0, d) / (1.0 - T);
+      B = c * std::pow(2.0, d / T) / (1.0 / T - 1.0);
+    } else {
+      A = std::ldexp(std::pow(c, (double)d), d);
+    }
+    double err = 0.0;
+    size_t m = h.size();
+    for (size_t u = 0; u < h.size(); ++u) {
+      const double wu = h[u];
+      while (m > 0 && !(wu * h[m - 1] > th)) --m;
+      if (m == 0) break;
+      const bool self = u < m;
+      const double sw = pw[m] - (self ? wu : 0.0);
+      const double cntv = (double)m - (self ? 1.0 : 0.0);
+      double term = A * (wu / W) * sw - cntv;
+      if (T > 0.0) {
+        const double sp = pp[m] - (self ? std::pow(wu, 1.0 / T) : 0.0);
+        term -= B * std::pow(wu / W, 1.0 / T) * sp;
+      }
+      err += term;
+    }
+    return (A * s1 - B * s2 - err) / (double)n;
+  }
+
+  // bracket by doubling / halving, then bisection on log c down to adjacent doubles
+  int solve(double target, double* out) {
+    double lo = 1.0, hi = 1.0;
+    int it = 0;
+    if (f(1.0) < target) {
+      while (f(hi) < target) { lo = hi; hi *= 2.0; if (++it > 2000) return -1; }
+    } else {
+      while (!(f(lo) < target)) { hi = lo; lo *= 0.5; if (++it > 2000) return -1; }
+    }
+    for (it = 0; it < 300; ++it) {
+      const double mid = std::exp(0.5 * (std::log(lo) + std::log(hi)));
+      if (!(mid > lo && mid < hi)) break;
+      if (f(mid) < target) lo = mid; else hi = mid;
+    }
+    *out = hi;
+    return 0;
+  }
+};
+
+// sums over all weights (device) -> s1, s2
+static girg_status csolve_sums(Ctx& cx, const double* w, uint64_t n, double T, double W,
+                               CSolve* cs, hipStream_t st) {
+  const double invT = T > 0.0 ? 1.0 / T : 0.0;
+  const int nterms = T > 0.0 ? 3 : 1;
+  HIPCHK(reduce_terms(cx.ar, w, n, nterms, 1, W, invT, cx.red, st));
+  double r[6];
+  HIPCHK(hipMemcpyAsync(r, cx.red, sizeof(r), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  cs->s1 = W - r[0];
+  if (T > 0.0) cs->s2 = r[1] / std::pow(W, invT) * r[1] - r[2];
+  else cs->s2 = 0.0;
+  return GIRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HRG radius from the average degree (not in the paper).  E[deg] =
+// (n-1) E[p] over two independent points; with s = R - r the radial density
+// is alpha sinh(alpha (R - s)) / (cosh(alpha R) - 1), and for a fixed pair of
+// radii the angular average of p is (1/pi) int_0^pi p dphi, where
+// cosh d = cosh(r1 - r2) + 2 sinh r1 sinh r2 sin^2(phi / 2).  Gauss-Legendre
+// on panels in s (split where r1 + r2 = R) and in log phi around the angle
+// at which d = R.
+// ---------------------------------------------------------------------------
+namespace rsolve {
+constexpr int kN = 12;
+static double X[kN], Wt[kN];
+static bool ready = false;
+static void init() {
+  if (ready) return;
+  for (int i = 0; i < kN; ++i) {
+    double z = std::cos(3.141592653589793 * (i + 0.75) / (kN + 0.5));
+    for (int it = 0; it < 60; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= kN; ++k) { double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k; p0 = p1; p1 = p2; }
+      const double dp = kN * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        p0 = 1.0; p1 = z;
+        for (int k = 2; k <= kN; ++k) { double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k; p0 = p1; p1 = p2; }
+        const double dq = kN * (z * p1 - p0) / (z * z - 1.0);
+        X[i] = z;
+        Wt[i] = 2.0 / ((1.0 - z * z) * dq * dq);
+        break;
+      }
+    }
+  }
+  ready = true;
+}
+struct Q {
+  double alpha, T, R, coshR, norm;
+  double dens(double r) const { return alpha * std::sinh(alpha * r) / norm; }
+  double p(double ch) const {
+    if (T == 0.0) return ch < coshR ? 1.0 : 0.0;
+    const double d = std::acosh(ch < 1.0 ? 1.0 : ch);
+    return 1.0 / (std::exp((d - R) / (2.0 * T)) + 1.0);
+  }
+  double ang_panel(double base, double amp, double a, double b) const {
+    double t = 0.0;
+    const double hm = 0.5 * (b - a), mid = 0.5 * (a + b);
+    for (int k = 0; k < kN; ++k) {
+      const double s = std::sin(0.5 * (mid + hm * X[k]));
+      t += Wt[k] * p(base + amp * s * s);
+    }
+    return t * hm;
+  }
+  double angular(double r1, double r2) const {
+    const double base = std::cosh(r1 - r2), amp = 2.0 * std::sinh(r1) * std::sinh(r2);
+    const double pi = 3.141592653589793;
+    double s2 = amp > 0.0 ? (coshR - base) / amp : (base < coshR ? 2.0 : -1.0);
+    double phs = s2 >= 1.0 ? pi : (s2 <= 0.0 ? 0.0 : 2.0 * std::asin(std::sqrt(s2)));
+    if (T == 0.0) return phs / pi;
+    double t = 0.0;
+    if (phs <= 0.0 || phs >= pi) {
+      for (int q = 0; q < 6; ++q) t += ang_panel(base, amp, pi * q / 6.0, pi * (q + 1) / 6.0);
+      return t / pi;
+    }
+    // below phi*: panels shrinking towards phi*
+    double a = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const double b = phs * (1.0 - std::ldexp(1.0, -(q + 1)));
+      t += ang_panel(base, amp, a, b);
+      a = b;
+    }
+    t += ang_panel(base, amp, a, phs);
+    // above phi*: geometric panels (ratio 1.6)
+    a = phs;
+    while (a < pi) {
+      const double b = std::min(pi, a * 1.6);
+      t += ang_panel(base, amp, a, b);
+      a = b;
+    }
+    return t / pi;
+  }
+};
+
+static double inner(const Q& q, double r1, double a, double b) {
+  if (b <= a) return 0.0;
+  const int np = std::max(1, (int)std::ceil((b - a) / 0.75));
+  double t = 0.0;
+  for (int k = 0; k < np; ++k) {
+    const double pa = a + (b - a) * k / np, pb = a + (b - a) * (k + 1) / np;
+    const double hm = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+    for (int i = 0; i < kN; ++i) {
+      const double r2 = mid + hm * X[i];
+      t += hm * Wt[i] * q.dens(r2) * q.angular(r1, r2);
+    }
+  }
+  return t;
+}
+
+static double expected_degree(uint64_t n, double alpha, double T, double R) {
+  init();
+  Q q{alpha, T, R, std::cosh(R), std::cosh(alpha * R) - 1.0};
+  const int np = std::max(1, (int)std::ceil(R / 0.75));
+  double t = 0.0;
+  for (int k = 0; k < np; ++k) {
+    const double pa = R * k / np, pb = R * (k + 1) / np;
+    const double hm = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+    for (int i = 0; i < kN; ++i) {
+      const double r1 = mid + hm * X[i];
+      const double kink = R - r1;
+      t += hm * Wt[i] * q.dens(r1) * (inner(q, r1, 0.0, kink) + inner(q, r1, kink, R));
+    }
+  }
+  return (double)(n - 1) * t;
+}
+
+// secant steps on log E[deg] inside a bisection bracket
+static int solve(uint64_t n, double alpha, double T, double target, double* out) {
+  double lo = std::log((double)n), hi = 2.0 * lo;
+  double flo = std::log(expected_degree(n, alpha, T, lo) / target);
+  double fhi = std::log(expected_degree(n, alpha, T, hi) / target);
+  int it = 0;
+  while (flo < 0.0) { hi = lo; fhi = flo; lo *= 0.5; flo = std::log(expected_degree(n, alpha, T, lo) / target); if (++it > 100) return -1; }
+  while (fhi > 0.0) { lo = hi; flo = fhi; hi *= 1.5; fhi = std::log(expected_degree(n, alpha, T, hi) / target); if (++it > 200) return -1; }
+  for (it = 0; it < 100 && hi - lo > 1e-12 * hi; ++it) {
+    double mid = lo + (hi - lo) * flo / (flo - fhi);
+    const double span = hi - lo;
+    if (!(mid > lo + 0.01 * span && mid < hi - 0.01 * span)) mid = 0.5 * (lo + hi);
+    const double fm = std::log(expected_degree(n, alpha, T, mid) / target);
+    if (fm == 0.0) { lo = hi = mid; break; }
+    if (fm > 0.0) { lo = mid; flo = fm; } else { hi = mid; fhi = fm; }
+  }
+  *out = 0.5 * (lo + hi);
+  return 0;
+}
+}  // namespace rsolve
+
+// memo of solved radii: R is a pure function of (n, alpha, T, avg_deg)
+static std::mutex g_rmemo_mu;
+static std::map<std::vector<double>, double> g_rmemo;
+
+static girg_status solve_R_cached(uint64_t n, double alpha, double T, double deg, double* R) {
+  const std::vector<double> key{(double)n, alpha, T, deg};
+  {
+    std::lock_guard<std::mutex> lk(g_rmemo_mu);
+    auto it = g_rmemo.find(key);
+    if (it != g_rmemo.end()) { *R = it->second; return GIRG_OK; }
+  }
+  if (rsolve::solve(n, alpha, T, deg, R) != 0) return fail(GIRG_ENOCONV, "hrg_solve_R: no bracket");
+  std::lock_guard<std::mutex> lk(g_rmemo_mu);
+  g_rmemo[key] = *R;
+  return GIRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static girg_status validate(const girg_params& p, bool need_beta) {
+  if (p.n < 2 || p.n > 0xFFFFFFFFull) return fail(GIRG_EINVAL, "n must be in [2, 2^32-1]");
+  if (!(p.T >= 0.0 && p.T < 1.0)) return fail(GIRG_EINVAL, "T must be in [0, 1)");
+  if (p.precision != 0 && p.precision != 1) return fail(GIRG_EINVAL, "precision must be 0 or 1");
+  if (p.model == 0) {
+    if (p.d < 1 || p.d > 4) return fail(GIRG_EINVAL, "d must be in [1, 4]");
+    if (need_beta && !(p.beta > 2.0)) return fail(GIRG_EINVAL, "beta must be > 2");
+    const bool hasc = p.c > 0.0, hasd = p.avg_deg > 0.0;
+    if (hasc == hasd) return fail(GIRG_EINVAL, "exactly one of c > 0 and avg_deg > 0 is required");
+    if (p.T > 0.0 && p.avg_deg > 0.0 && p.T < 0.05)
+      return fail(GIRG_EINVAL, "solving c needs T = 0 or T >= 0.05; pass c instead");
+  } else if (p.model == 1) {
+    if (!(p.alpha > 0.5)) return fail(GIRG_EINVAL, "alpha must be > 1/2");
+    if (!(p.R > 0.0) && !(p.avg_deg > 0.0)) return fail(GIRG_EINVAL, "R > 0 or avg_deg > 0 is required");
+  } else {
+    return fail(GIRG_EINVAL, "model must be 0 (GIRG) or 1 (HRG)");
+  }
+  if (p.T == 0.0 && p.cl_bias > 0) return fail(GIRG_EINVAL, "cl_bias > 0 is inexact at T = 0");
+  if (p.cl_bias < -64 || p.cl_bias > 64) return fail(GIRG_EINVAL, "cl_bias out of range");
+  return GIRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the sampler over resident points
+// ---------------------------------------------------------------------------
+static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, const double* x,
+                             uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
+                             hipStream_t st) {
+  Arena& ar = cx.ar;
+  Graph g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = (uint32_t)p.n;
+  g.model = p.model;
+  g.d = p.model == 1 ? 1 : p.d;
+  g.Dmax = 32 / g.d;
+  g.bits = g.d * g.Dmax;
+  g.cl_bias = p.cl_bias;
+  g.max_depth = p.max_depth;
+  g.precision = p.precision;
+  g.T = p.T;
+  g.inv_T = p.T > 0.0 ? 1.0 / p.T : 0.0;
+  g.alpha = p.alpha;
+  g.R = p.R;
+  g.coshR = p.model == 1 ? std::cosh(p.R) : 0.0;
+  g.seed_lo = (uint32_t)p.seed;
+  g.seed_hi = (uint32_t)(p.seed >> 32);
+  const uint64_t n = p.n;
+  const int d = g.d;
+
+  // exact sum W and min / max of w (GIRG) or r (HRG)
+  HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
+  double red[6];
+  HIPCHK(hipMemcpyAsync(red, cx.red, sizeof(red), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (p.model == 0) {
+    if (!(red[4] > 0.0) || !std::isfinite(red[5]))
+      return fail(GIRG_EINVAL, "weights must be finite and > 0");
+    g.W = red[0];
+    g.w0 = red[4];
+    if (bitlen((uint64_t)std::min(red[5] / red[4], 1e19)) > kMaxLayers)
+      return fail(GIRG_EINVAL, "weight range exceeds 2^64");
+  } else {
+    if (!(red[4] >= 0.0) || !(red[5] <= p.R)) return fail(GIRG_EINVAL, "radii must lie in [0, R]");
+  }
+
+  // layer + Morton keys
+  for (int i = 0; i < kMaxLayers; ++i) {
+    g.ext[i] = p.model == 0 ? 0.0 : __builtin_inf();
+  }
+  HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(cx.flag, 0, sizeof(uint32_t), st));
+  uint64_t* keys = ar.get<uint64_t>(n);
+  uint32_t* ids = ar.get<uint32_t>(n);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (keys)");
+  HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
+  uint32_t flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, cx.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(g.count, cx.gd->count, sizeof(g.count), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(g.ext, cx.gd->ext, sizeof(g.ext), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flag & 1u) return fail(GIRG_EINVAL, p.model == 0 ? "weights must be finite and > 0" : "radii must lie in [0, R]");
+  if (flag & 2u) return fail(GIRG_EINVAL, "more than 64 weight layers");
+  if (flag & 4u) return fail(GIRG_EINVAL, "positions must lie in [0,1)");
+  g.L = 0;
+  uint32_t acc = 0;
+  for (int i = 0; i < kMaxLayers; ++i) {
+    g.lstart[i] = acc;
+    acc += (uint32_t)g.count[i];
+    if (g.count[i] > 0) g.L = i + 1;
+  }
+  g.lstart[kMaxLayers] = acc;
+  const int lbits = bitlen((uint64_t)(g.L > 0 ? g.L - 1 : 0));
+
+  // stable sort by (layer, Morton code); ties keep id order
+  HIPCHK(radix_sort(ar, keys, ids, n, g.bits + lbits, st));
+  double* sw = ar.get<double>(n);
+  double* sx = ar.get<double>(n * d);
+  uint32_t* smort = ar.get<uint32_t>(n);
+  uint8_t* slayer = ar.get<uint8_t>(n);
+  double* aux = p.model == 1 ? ar.get<double>(3 * n) : nullptr;
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, sx, smort, slayer, aux, st));
+
+  // constant c (App. B.2)
+  if (p.model == 0) {
+    double c = p.c;
+    if (!(c > 0.0)) {
+      CSolve cs;
+      cs.n = n; cs.d = d; cs.T = p.T; cs.W = g.W;
+      girg_status s = csolve_sums(cx, w, n, p.T, g.W, &cs, st);
+      if (s != GIRG_OK) return s;
+      // heaviest layers first; grow the tail until E_R is complete
+      int i0 = g.L;
+      uint64_t tail = 0;
+      while (i0 > 0 && tail < 4096) { --i0; tail += (uint64_t)g.count[i0]; }
+      for (;;) {
+        cs.h.resize(n - g.lstart[i0]);
+        HIPCHK(hipMemcpyAsync(cs.h.data(), sw + g.lstart[i0], cs.h.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        cs.wcut = 0.0;
+        for (int i = i0 - 1; i >= 0; --i)
+          if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
+        cs.prepare();
+        cs.incomplete = false;
+        if (cs.solve(p.avg_deg, &c) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
+        if (!cs.incomplete || i0 == 0) break;
+        // take layers until the tail at least doubles
+        const uint64_t want = 2 * cs.h.size();
+        while (i0 > 0 && n - g.lstart[i0] < want) --i0;
+      }
+    }
+    g.c = c;
+    g.kappa = p.T > 0.0 ? std::pow(c, p.T) : std::pow(c, (double)d);
+  }
+
+  // level tables
+  const int Dcap = std::min(g.Dmax, (bitlen(n) + 3) / d);
+  const int nlev = Dcap + 1;
+  Pbar* pbt = nullptr;
+  if (p.T > 0.0) {
+    pbt = ar.get<Pbar>((uint64_t)std::max(g.L, 1) * std::max(g.L, 1) * nlev * 2);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (pbar)");
+  }
+  HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_tables(cx.gd, Dcap, pbt, st));
+  HIPCHK(hipMemcpyAsync(&g, cx.gd, sizeof(Graph), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  // prefix sums per layer at its insertion level
+  uint64_t cells = 0;
+  for (int i = 0; i < kMaxLayers; ++i) {
+    g.pbase[i] = cells;
+    if (g.count[i] > 0) cells += (1ull << (d * g.I[i])) + 1;
+  }
+  g.cells = cells;
+  if (cells >= 0xFFFFFFFFull * 4) return fail(GIRG_ENOMEM, "too many cells");
+  HIPCHK(hipMemcpyAsync(cx.gd->pbase, g.pbase, sizeof(g.pbase), hipMemcpyHostToDevice, st));
+  uint32_t* P = ar.get<uint32_t>(cells);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (cells)");
+  HIPCHK(hipMemsetAsync(P, 0, cells * sizeof(uint32_t), st));
+  HIPCHK(launch_cell_count(g, cx.gd, smort, slayer, P, st));
+  HIPCHK(scan_u32(ar, P, P, cells, nullptr, st));
+
+  // run sources
+  uint32_t* scnt = ar.get<uint32_t>(n + 1);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, scnt, nullptr, nullptr, false, st));
+  HIPCHK(scan_u32(ar, scnt, scnt, n, scnt + n, st));
+  uint32_t nsrc = 0;
+  HIPCHK(hipMemcpyAsync(&nsrc, scnt + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  uint64_t* src = ar.get<uint64_t>(std::max<uint64_t>(nsrc, 1));
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, nullptr, scnt, src, true, st));
+
+  Verts v{sw, sx, ids, smort, slayer, aux, nullptr};
+
+  // count passes
+  const int NW = kSampleWaves;
+  uint32_t* wcount = ar.get<uint32_t>(3 * NW);
+  uint64_t* wbase = ar.get<uint64_t>(3 * NW + 1);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (wave counts)");
+  HIPCHK(hipMemsetAsync(wcount, 0, 3 * NW * sizeof(uint32_t), st));
+  HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
+  HIPCHK(hipMemsetAsync(cx.hcount, 0, sizeof(unsigned int), st));
+  WaveOut wo1{wcount, nullptr, nullptr, cx.stats};
+  WaveOut wo2{wcount + NW, nullptr, nullptr, cx.stats};
+  WaveOut wo3{wcount + 2 * NW, nullptr, nullptr, cx.stats};
+  const bool binomial = p.T > 0.0;
+  if (nsrc) HIPCHK(launch_type1(g, cx.gd, v, P, src, nsrc, false, wo1, st));
+  const uint32_t hcap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(n / 4, 1u << 16), 1u << 26);
+  HeavyRec* hrec = nullptr;
+  uint64_t* hkey = nullptr;
+  if (binomial) {
+    hrec = ar.get<HeavyRec>(hcap);
+    hkey = ar.get<uint64_t>(hcap);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (heavy items)");
+  }
+  HeavyOut ho{hrec, hkey, cx.hcount, hcap};
+  if (binomial && nsrc) HIPCHK(launch_type2(g, cx.gd, v, P, src, nsrc, pbt, nlev, false, wo2, ho, st));
+  unsigned int nh = 0;
+  HIPCHK(hipMemcpyAsync(&nh, cx.hcount, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (nh > hcap) return fail(GIRG_ENOMEM, "too many heavy type-II items");
+  HeavyRec* hsorted = nullptr;
+  uint64_t* segoff = nullptr;
+  uint64_t nseg_total = 0;
+  if (nh) {
+    // deterministic order of the heavy items
+    uint32_t* perm = ar.get<uint32_t>(nh);
+    hsorted = ar.get<HeavyRec>(nh);
+    segoff = ar.get<uint64_t>(nh + 1);
+    uint64_t* tmp = ar.get<uint64_t>(nh);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (heavy sort)");
+    std::vector<uint32_t> iota(nh);
+    for (uint32_t i = 0; i < nh; ++i) iota[i] = i;
+    HIPCHK(hipMemcpyAsync(perm, iota.data(), nh * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(tmp, hkey, nh * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(radix_sort(ar, tmp, perm, nh, 40, st));
+    HIPCHK(launch_heavy_gather(hrec, perm, nh, hsorted, st));
+    HIPCHK(launch_heavy_prep(hsorted, nh, segoff, st));
+    HIPCHK(scan_u64(ar, segoff, segoff, nh, segoff + nh, st));
+    HIPCHK(hipMemcpyAsync(&nseg_total, segoff + nh, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(launch_heavy(g, cx.gd, v, hsorted, segoff, nh, nseg_total, pbt, nlev, false, wo3, st));
+  }
+
+  // offsets of every wave's edges; total
+  // (the counts are u32; widen into the u64 base array, then scan)
+  {
+    std::vector<uint32_t> hc(3 * NW);
+    HIPCHK(hipMemcpyAsync(hc.data(), wcount, 3 * NW * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<uint64_t> hb(3 * NW + 1);
+    uint64_t accm = 0;
+    for (int i = 0; i < 3 * NW; ++i) { hb[i] = accm; accm += hc[i]; }
+    hb[3 * NW] = accm;
+    uint64_t m1 = hb[NW], m2 = hb[2 * NW] - hb[NW];
+    *m_out = accm;
+    if (info) {
+      info->m = accm;
+      info->type1_edges = m1;
+      info->type2_edges = accm - m1;
+      (void)m2;
+    }
+    if (accm > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
+    HIPCHK(hipMemcpyAsync(wbase, hb.data(), hb.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  }
+
+  // write passes
+  uint2* out = reinterpret_cast<uint2*>(edges);
+  WaveOut ww1{nullptr, wbase, out, cx.stats};
+  WaveOut ww2{nullptr, wbase + NW, out, cx.stats};
+  WaveOut ww3{nullptr, wbase + 2 * NW, out, cx.stats};
+  if (nsrc) HIPCHK(launch_type1(g, cx.gd, v, P, src, nsrc, true, ww1, st));
+  if (binomial && nsrc) HIPCHK(launch_type2(g, cx.gd, v, P, src, nsrc, pbt, nlev, true, ww2, ho, st));
+  if (nh) HIPCHK(launch_heavy(g, cx.gd, v, hsorted, segoff, nh, nseg_total, pbt, nlev, true, ww3, st));
+
+  unsigned long long stt[8];
+  HIPCHK(hipMemcpyAsync(stt, cx.stats, sizeof(stt), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info) {
+    info->tests = stt[0];
+    info->draws = stt[1];
+    info->candidates = stt[2];
+    info->rechecks = stt[3];
+    info->sources = nsrc;
+    info->heavy_items = nh;
+    info->cells = cells;
+    info->c = g.c;
+    info->W = g.W;
+    info->R = g.R;
+    info->L = g.L;
+    info->D = g.D;
+  }
+  return GIRG_OK;
+}
+
+static girg_status with_ctx(Ctx** cx) {
+  girg_status s = get_ctx(cx);
+  if (s != GIRG_OK) return s;
+  (*cx)->ar.reset_all();
+  (*cx)->ar.clear_failure();
+  return GIRG_OK;
+}
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" {
+
+const char* girg_last_error(void) { return g_err.c_str(); }
+const char* girg_version(void) { return "hipgirg 0.1 (gfx950)"; }
+
+girg_status girg_release(void) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  g_ctx.erase(dev);
+  return GIRG_OK;
+}
+
+girg_status girg_points(const girg_params* p, double* w, double* x, void* stream) {
+  if (!p || !w || !x) return fail(GIRG_EINVAL, "null argument");
+  girg_params q = *p;
+  if (q.model == 0) {
+    if (q.n < 1 || q.n > 0xFFFFFFFFull) return fail(GIRG_EINVAL, "n must be in [1, 2^32-1]");
+    if (q.d < 1 || q.d > 4) return fail(GIRG_EINVAL, "d must be in [1, 4]");
+    if (!(q.beta > 2.0)) return fail(GIRG_EINVAL, "beta must be > 2");
+  } else {
+    if (!(q.alpha > 0.5) || !(q.R > 0.0)) return fail(GIRG_EINVAL, "alpha > 1/2 and R > 0 required");
+  }
+  Graph g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = (uint32_t)q.n;
+  g.d = q.model == 1 ? 1 : q.d;
+  g.model = q.model;
+  g.alpha = q.alpha;
+  g.R = q.R;
+  g.seed_lo = (uint32_t)q.seed;
+  g.seed_hi = (uint32_t)(q.seed >> 32);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(launch_points(g, q.beta, w, x, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return GIRG_OK;
+}
+
+girg_status girg_from_points(const girg_params* p, const double* w, const double* x,
+                             uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
+                             void* stream) {
+  if (!p || !w || !x || !m_out || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
+  girg_status s = validate(*p, false);
+  if (s != GIRG_OK) return s;
+  if (p->model == 1 && !(p->R > 0.0)) return fail(GIRG_EINVAL, "girg_from_points needs R > 0 for an HRG");
+  Ctx* cx = nullptr;
+  if ((s = with_ctx(&cx)) != GIRG_OK) return s;
+  std::lock_guard<std::mutex> lk(cx->mu);
+  if (info) std::memset(info, 0, sizeof(*info));
+  return run_graph(*cx, *p, w, x, edges, cap, m_out, info, static_cast<hipStream_t>(stream));
+}
+
+static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t cap,
+                                 uint64_t* m_out, girg_info* info, void* stream) {
+  girg_params q = *p;
+  girg_status s = validate(q, q.model == 0);
+  if (s != GIRG_OK) return s;
+  if (q.model == 1 && !(q.R > 0.0)) {
+    s = solve_R_cached(q.n, q.alpha, q.T, q.avg_deg, &q.R);
+    if (s != GIRG_OK) return s;
+  }
+  Ctx* cx = nullptr;
+  if ((s = with_ctx(&cx)) != GIRG_OK) return s;
+  std::lock_guard<std::mutex> lk(cx->mu);
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int d = q.model == 1 ? 1 : q.d;
+  double* w = cx->ar.get<double>(q.n);
+  double* x = cx->ar.get<double>(q.n * d);
+  if (cx->ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (points)");
+  Graph g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = (uint32_t)q.n;
+  g.d = d;
+  g.model = q.model;
+  g.alpha = q.alpha;
+  g.R = q.R;
+  g.seed_lo = (uint32_t)q.seed;
+  g.seed_hi = (uint32_t)(q.seed >> 32);
+  HIPCHK(launch_points(g, q.beta, w, x, st));
+  return run_graph(*cx, q, w, x, edges, cap, m_out, info, st);
+}
+
+girg_status girg_generate(const girg_params* p, uint32_t* edges, uint64_t cap, uint64_t* m_out,
+                          girg_info* info, void* stream) {
+  if (!p || !m_out || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
+  return generate_impl(p, edges, cap, m_out, info, stream);
+}
+
+girg_status girg_hrg(uint64_t n, double alpha, double T, double R, double avg_deg, uint64_t seed,
+                     uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
+                     void* stream) {
+  if (!m_out || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
+  girg_params q;
+  std::memset(&q, 0, sizeof(q));
+  q.n = n;
+  q.d = 1;
+  q.model = 1;
+  q.alpha = alpha;
+  q.T = T;
+  q.R = R;
+  q.avg_deg = R > 0.0 ? 0.0 : avg_deg;
+  q.seed = seed;
+  q.max_depth = -1;
+  return generate_impl(&q, edges, cap, m_out, info, stream);
+}
+
+girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
+                                uint64_t* offsets, girg_info* infos, void* stream) {
+  if (!p || count < 0 || !offsets || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
+  uint64_t used = 0;
+  offsets[0] = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    uint64_t m = 0;
+    girg_status s = generate_impl(&p[b], edges ? edges + 2 * used : nullptr, cap - used, &m,
+                                  infos ? &infos[b] : nullptr, stream);
+    if (s == GIRG_EOVERFLOW) {
+      // count the rest so that the caller learns the total
+      uint64_t need = used + m;
+      for (int32_t r = b + 1; r < count; ++r) {
+        uint64_t mr = 0;
+        girg_status sr = generate_impl(&p[r], nullptr, 0, &mr, nullptr, stream);
+        if (sr != GIRG_OK && sr != GIRG_EOVERFLOW) return sr;
+        need += mr;
+      }
+      offsets[count] = need;
+      return fail(GIRG_EOVERFLOW, "edge capacity too small");
+    }
+    if (s != GIRG_OK) return s;
+    used += m;
+    offsets[b + 1] = used;
+  }
+  return GIRG_OK;
+}
+
+girg_status girg_solve_c(const double* w_host, uint64_t n, int32_t d, double T, double avg_deg,
+                         double* c_out) {
+  if (!w_host || !c_out || n < 2) return fail(GIRG_EINVAL, "null argument or n < 2");
+  if (d < 1 || d > 4 || !(T >= 0.0 && T < 1.0) || !(avg_deg > 0.0))
+    return fail(GIRG_EINVAL, "invalid d, T or avg_deg");
+  CSolve cs;
+  cs.n = n; cs.d = d; cs.T = T;
+  long double W = 0.0L, q1 = 0.0L, q2 = 0.0L, q3 = 0.0L;
+  for (uint64_t i = 0; i < n; ++i) W += w_host[i];
+  cs.W = (double)W;
+  for (uint64_t i = 0; i < n; ++i) {
+    q1 += w_host[i] * w_host[i] / cs.W;
+    if (T > 0.0) {
+      q2 += std::pow(w_host[i], 1.0 / T);
+      q3 += std::pow(w_host[i] * w_host[i] / cs.W, 1.0 / T);
+    }
+  }
+  cs.s1 = cs.W - (double)q1;
+  cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
+  cs.h.assign(w_host, w_host + n);
+  cs.wcut = 0.0;
+  cs.prepare();
+  if (cs.solve(avg_deg, c_out) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
+  return GIRG_OK;
+}
+
+girg_status girg_expected_degree(const double* w_host, uint64_t n, int32_t d, double T, double c,
+                                 double* deg_out) {
+  if (!w_host || !deg_out || n < 2 || !(c > 0.0)) return fail(GIRG_EINVAL, "invalid argument");
+  CSolve cs;
+  cs.n = n; cs.d = d; cs.T = T;
+  long double W = 0.0L, q1 = 0.0L, q2 = 0.0L, q3 = 0.0L;
+  for (uint64_t i = 0; i < n; ++i) W += w_host[i];
+  cs.W = (double)W;
+  for (uint64_t i = 0; i < n; ++i) {
+    q1 += w_host[i] * w_host[i] / cs.W;
+    if (T > 0.0) {
+      q2 += std::pow(w_host[i], 1.0 / T);
+      q3 += std::pow(w_host[i] * w_host[i] / cs.W, 1.0 / T);
+    }
+  }
+  cs.s1 = cs.W - (double)q1;
+  cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
+  cs.h.assign(w_host, w_host + n);
+  cs.wcut = 0.0;
+  cs.prepare();
+  *deg_out = cs.f(c);
+  return GIRG_OK;
+}
+
+girg_status hrg_solve_R(uint64_t n, double alpha, double T, double avg_deg, double* R_out) {
+  if (!R_out || n < 2 || !(alpha > 0.5) || !(T >= 0.0 && T < 1.0) || !(avg_deg > 0.0))
+    return fail(GIRG_EINVAL, "invalid argument");
+  return solve_R_cached(n, alpha, T, avg_deg, R_out);
+}
+
+girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, double* deg_out) {
+  if (!deg_out || n < 2 || !(alpha > 0.5) || !(T >= 0.0 && T < 1.0) || !(R > 0.0))
+    return fail(GIRG_EINVAL, "invalid argument");
+  *deg_out = rsolve::expected_degree(n, alpha, T, R);
+  return GIRG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// internal.h -- host-side declarations shared by the library's translation
+// units (scratch arena, primitives, sampler stages).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <vector>
+
+#include "device_common.h"
+
+namespace hg {
+
+// Bump allocator over device chunks.  Allocations never move; reset() returns
+// everything above a mark; chunks are kept (cached) until release().
+class Arena {
+ public:
+  struct Mark {
+    size_t chunk;
+    size_t used;
+  };
+  ~Arena() { release(); }
+
+  Mark mark() const { return Mark{cur_, chunks_.empty() ? 0 : chunks_[cur_].used}; }
+  void reset(Mark m) {
+    for (size_t c = m.chunk + 1; c < chunks_.size(); ++c) chunks_[c].used = 0;
+    cur_ = m.chunk;
+    if (!chunks_.empty()) chunks_[cur_].used = m.used;
+  }
+  void reset_all() {
+    for (auto& c : chunks_) c.used = 0;
+    cur_ = 0;
+  }
+  template <typename T>
+  T* get(uint64_t count) {
+    void* p = raw(count * sizeof(T));
+    return static_cast<T*>(p);
+  }
+  void* raw(size_t bytes);  // nullptr on allocation failure (sets failed())
+  bool failed() const { return failed_; }
+  void clear_failure() { failed_ = false; }
+  void release();
+
+ private:
+  struct Chunk {
+    char* base;
+    size_t size;
+    size_t used;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+  bool failed_ = false;
+};
+
+hipError_t scan_u32(Arena& ar, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                    hipStream_t st);
+hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* total,
+                    hipStream_t st);
+// out6 (device): sums of terms mode0..mode0+nterms-1, then min, max of w
+hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
+                        double invT, double* out6, hipStream_t st);
+hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
+                      hipStream_t st);
+
+}  // namespace hg

@@ -1,0 +1,325 @@
+// prims.hip -- deterministic parallel primitives for gfx950 (wave64):
+// exclusive scans, double-double sum and min/max reductions, and a stable LSD
+// radix sort of 64-bit keys with 32-bit payloads (LDS-ranked, 8-bit digits).
+#include "internal.h"
+
+namespace hg {
+
+// ---------------------------------------------------------------------------
+// exclusive scan (u32 / u64), tiles of 256 threads x 8 items
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* total) {
+  __shared__ T wsum[kScanThreads / 64];
+  const int w = threadIdx.x / 64, lane = lane_id();
+  T inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) base += wsum[k];
+    tot += wsum[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const T* __restrict__ in,
+                                                             T* __restrict__ out,
+                                                             T* __restrict__ sums, uint64_t n) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    v[k] = i < n ? in[i] : (T)0;
+    acc += v[k];
+  }
+  T total;
+  T run = block_excl_scan(acc, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(T* __restrict__ out,
+                                                           const T* __restrict__ offs, uint64_t n) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  const T o = offs[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < n) out[i] += o;
+  }
+}
+
+// Exclusive scan of n elements (in may equal out).  Returns the total through
+// `total_dev` (device pointer, may be null).  Scratch comes from the arena.
+template <typename T>
+static hipError_t scan_impl(Arena& ar, const T* in, T* out, uint64_t n, T* total_dev, hipStream_t st) {
+  if (n == 0) {
+    if (total_dev) return hipMemsetAsync(total_dev, 0, sizeof(T), st);
+    return hipSuccess;
+  }
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  T* sums = ar.get<T>(tiles + 1);
+  hipLaunchKernelGGL(k_scan_tiles<T>, dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, out, sums, n);
+  if (tiles == 1) {
+    if (total_dev) return hipMemcpyAsync(total_dev, sums, sizeof(T), hipMemcpyDeviceToDevice, st);
+    return hipGetLastError();
+  }
+  // sums[tiles] <- total of the block sums (exclusive scan writes offsets in place)
+  hipError_t e = scan_impl<T>(ar, sums, sums, tiles, total_dev, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)tiles), dim3(kScanThreads), 0, st, out, sums, n);
+  return hipGetLastError();
+}
+
+hipError_t scan_u32(Arena& ar, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                    hipStream_t st) {
+  Arena::Mark m = ar.mark();
+  hipError_t e = scan_impl<uint32_t>(ar, in, out, n, total, st);
+  ar.reset(m);
+  return e;
+}
+hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* total,
+                    hipStream_t st) {
+  Arena::Mark m = ar.mark();
+  hipError_t e = scan_impl<uint64_t>(ar, in, out, n, total, st);
+  ar.reset(m);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// reductions: fixed grid, fixed order => bitwise reproducible
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// error-free transformation (Knuth TwoSum)
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double x) {
+  double s, e;
+  two_sum(hi, x, s, e);
+  hi = s;
+  lo += e;
+}
+__device__ __forceinline__ void dd_merge(double& hi, double& lo, double h2, double l2) {
+  double s, e;
+  two_sum(hi, h2, s, e);
+  hi = s;
+  lo = lo + l2 + e;
+}
+
+// mode: per-vertex terms.  0 = w; 1 = w^2 / W; 2 = w^(1/T); 3 = (w^2 / W)^(1/T)
+__device__ __forceinline__ double red_term(int mode, double w, double W, double invT) {
+  switch (mode) {
+    case 0: return w;
+    case 1: return w * w / W;
+    case 2: return pow(w, invT);
+    default: return pow(w * w / W, invT);
+  }
+}
+
+// out layout per block: [hi, lo] for each of nterms sums, then min, max
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ w,
+                                                                 uint64_t n, int nterms,
+                                                                 int mode0, double W, double invT,
+                                                                 double* __restrict__ part) {
+  __shared__ double shi[4][kRedThreads], slo[4][kRedThreads], smin[kRedThreads], smax[kRedThreads];
+  const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = per * blockIdx.x, b1 = b0 + per < n ? b0 + per : n;
+  double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
+  double mn = __builtin_inf(), mx = -__builtin_inf();
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    const double v = w[i];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+    for (int t = 0; t < nterms; ++t) dd_add(hi[t], lo[t], red_term(mode0 + t, v, W, invT));
+  }
+  for (int t = 0; t < nterms; ++t) {
+    shi[t][threadIdx.x] = hi[t];
+    slo[t][threadIdx.x] = lo[t];
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int t = 0; t < nterms; ++t) {
+        double h = shi[t][threadIdx.x], l = slo[t][threadIdx.x];
+        dd_merge(h, l, shi[t][threadIdx.x + s], slo[t][threadIdx.x + s]);
+        shi[t][threadIdx.x] = h;
+        slo[t][threadIdx.x] = l;
+      }
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = part + (uint64_t)blockIdx.x * 10;
+    for (int t = 0; t < 4; ++t) {
+      o[2 * t] = t < nterms ? shi[t][0] : 0.0;
+      o[2 * t + 1] = t < nterms ? slo[t][0] : 0.0;
+    }
+    o[8] = smin[0];
+    o[9] = smax[0];
+  }
+}
+
+// one thread folds the block partials in order: out = [sum_0..sum_3, min, max]
+__global__ void k_reduce_final(const double* __restrict__ part, int nblocks,
+                               double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
+  double mn = __builtin_inf(), mx = -__builtin_inf();
+  for (int b = 0; b < nblocks; ++b) {
+    const double* o = part + (uint64_t)b * 10;
+    for (int t = 0; t < 4; ++t) dd_merge(hi[t], lo[t], o[2 * t], o[2 * t + 1]);
+    mn = fmin(mn, o[8]);
+    mx = fmax(mx, o[9]);
+  }
+  for (int t = 0; t < 4; ++t) out[t] = hi[t] + lo[t];
+  out[4] = mn;
+  out[5] = mx;
+}
+
+hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
+                        double invT, double* out6, hipStream_t st) {
+  Arena::Mark m = ar.mark();
+  double* part = ar.get<double>((uint64_t)kRedBlocks * 10);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, n, nterms,
+                     mode0, W, invT, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, part, kRedBlocks, out6);
+  ar.reset(m);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, tiles of 256 threads x 16 keys
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __restrict__ keys,
+                                                          uint64_t n, int shift, uint32_t ntiles,
+                                                          uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint64_t n, int shift, uint32_t ntiles,
+    const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[kSortThreads / 64][256];
+  const int t = threadIdx.x, w = t / 64;
+  run[t] = offs[(uint64_t)t * ntiles + blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    for (int q = 0; q < kSortThreads / 64; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const uint64_t i = base + (uint64_t)r * kSortThreads + t;
+    const bool valid = i < n;
+    const uint64_t key = valid ? kin[i] : 0;
+    const uint32_t val = valid ? vin[i] : 0;
+    const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+    // lanes of this wave holding the same digit
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((dig >> b) & 1u);
+      same &= ((dig >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = lanes_below(same);
+    if (valid && rank == 0) wc[w][dig] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[dig] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][dig];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < kSortThreads / 64; ++q) add += wc[q][t];
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// Sorts (keys, vals) by the low `bits` bits of the key, stably.  Results end
+// in (keys, vals); tmp buffers come from the arena.
+hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
+                      hipStream_t st) {
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  Arena::Mark m = ar.mark();
+  const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  uint64_t* k2 = ar.get<uint64_t>(n);
+  uint32_t* v2 = ar.get<uint32_t>(n);
+  uint32_t* hist = ar.get<uint32_t>((uint64_t)ntiles * 256);
+  uint64_t* ka = keys;
+  uint32_t* va = vals;
+  uint64_t* kb = k2;
+  uint32_t* vb = v2;
+  const int passes = (bits + 7) / 8;
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kSortThreads), 0, st, ka, n, 8 * p, ntiles, hist);
+    e = scan_u32(ar, hist, hist, (uint64_t)ntiles * 256, nullptr, st);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, st, ka, va, kb, vb, n,
+                       8 * p, ntiles, hist);
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
+  if (e == hipSuccess && ka != keys) {
+    e = hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+  }
+  ar.reset(m);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace hg

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same
+seeded inputs.  Edge sets must match except for the pairs the oracle logs as
+near the decision boundary; indices, layers and level tables bit-exactly."""
+import numpy as np
+import pytest
+
+from tests import synth
+from tests.parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_06706_amd as hg
+    hg.load()
+    return hg
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_both(hg, orc, w, x, *, T, c, seed, model=0, R=0.0, alpha=0.0, **kw):
+    print(f"[parity] n={len(w)} d={x.shape[1]} T={T} c={c} seed={seed} model={model} {kw}", flush=True)
+    res = hg.from_points(dev(w), dev(x.T), T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, **kw)
+    ge = res.edges.cpu().numpy().view(np.uint32)
+    run = orc.run(w, x, T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, keep=True, **kw)
+    return ge, res.info, run
+
+
+def test_points_match_oracle(hg, orc):
+    for d in (1, 2, 3, 4):
+        w, x = hg.points(20000, d, 2.3, seed=7)
+        ow, ox = orc.points_girg(20000, d, 2.3, 7)
+        assert np.array_equal(x.cpu().numpy(), ox.T)  # positions: pure integer arithmetic
+        rel = np.abs(w.cpu().numpy() - ow) / ow
+        assert rel.max() <= 4.5e-16                     # weights: pow within 2 ulp
+    r, x = hg.points(20000, model=1, alpha=0.75, R=20.0, seed=3)
+    orr, ox = orc.points_hrg(20000, 0.75, 20.0, 3)
+    assert np.array_equal(x.cpu().numpy()[0], ox[:, 0])
+    assert np.max(np.abs(r.cpu().numpy() - orr)) <= 1e-13
+
+
+@pytest.mark.parametrize("d,n,beta,seed", [(1, 10000, 2.5, 1), (2, 20000, 2.7, 2), (3, 20000, 2.3, 4), (4, 8000, 2.6, 5)])
+def test_threshold_from_points(hg, orc, d, n, beta, seed):
+    w = synth.pareto_weights(n, beta, seed)
+    x = synth.positions(n, d, seed)
+    c = orc.solve_c(w, d, 0.0, 10.0)
+    ge, info, run = run_both(hg, orc, w, x, T=0.0, c=c, seed=seed)
+    rep = compare(ge, run)
+    assert info["L"] == run.stats["L"] and info["D"] == run.stats["D"]
+    assert rep["gpu"] > n
+
+
+@pytest.mark.parametrize("d,n,T,seed", [(1, 8000, 0.5, 3), (2, 12000, 0.5, 2), (3, 6000, 0.8, 4), (2, 6000, 0.3, 9), (1, 5000, 0.9, 11)])
+def test_binomial_from_points(hg, orc, d, n, T, seed):
+    w = synth.pareto_weights(n, 2.5, seed)
+    x = synth.positions(n, d, seed)
+    c = orc.solve_c(w, d, T, 12.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=seed)
+    rep = compare(ge, run)
+    assert info["tests"] == run.stats["tests"]
+    assert info["draws"] == run.stats["draws"]
+    assert info["candidates"] == run.stats["candidates"]
+    assert info["type2_edges"] == run.stats["type2_edges"]
+
+
+@pytest.mark.parametrize("bias,depth", [(2, -1), (-2, -1), (0, 1), (0, 0), (3, 4)])
+def test_binomial_level_knobs(hg, orc, bias, depth):
+    n, d, T = 3000, 2, 0.5
+    w = synth.pareto_weights(n, 2.2, 5)
+    x = synth.clustered_positions(n, d, 5)
+    c = orc.solve_c(w, d, T, 14.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=5, cl_bias=bias, max_depth=depth)
+    compare(ge, run)
+
+
+def test_heavy_items_split_into_segments(hg, orc):
+    # coarse levels for low weights: type-II items with many expected candidates
+    n, d, T = 20000, 1, 0.9
+    w = synth.pareto_weights(n, 2.8, 6)
+    x = synth.positions(n, d, 6)
+    c = orc.solve_c(w, d, T, 20.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=6)
+    assert info["heavy_items"] > 0
+    compare(ge, run)
+    assert info["draws"] == run.stats["draws"]
+
+
+@pytest.mark.parametrize("T", [0.0, 0.5])
+def test_hrg_from_points(hg, orc, T):
+    n, alpha = 20000, 0.75
+    R = orc.hrg_solve_R(n, alpha, T, 10.0)
+    r = synth.hrg_radii(n, alpha, R, 3)
+    x = synth.positions(n, 1, 3)
+    ge, info, run = run_both(hg, orc, r, x, T=T, c=0.0, seed=3, model=1, R=R, alpha=alpha)
+    compare(ge, run)
+
+
+def test_generate_end_to_end_config1(hg, orc):
+    """n = 10^4, d = 1, beta = 2.5, T = 0, average degree 10, seed 1: the GPU
+    generates points, solves c and samples; the oracle does the same on its
+    own; edge sets agree."""
+    res = hg.generate(10**4, d=1, beta=2.5, T=0.0, avg_deg=10.0, seed=1)
+    ge = res.edges.cpu().numpy().view(np.uint32)
+    w, x = orc.points_girg(10**4, 1, 2.5, 1)
+    c = orc.solve_c(w, 1, 0.0, 10.0)
+    assert res.info["c"] == pytest.approx(c, rel=1e-12)
+    run = orc.run(w, x, T=0.0, c=c, seed=1, keep=True)
+    compare(ge, run)
+
+
+def test_generate_end_to_end_binomial(hg, orc):
+    n, d, beta, T, deg, seed = 2**15, 2, 2.7, 0.5, 16.0, 2
+    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
+    ge = res.edges.cpu().numpy().view(np.uint32)
+    w, x = orc.points_girg(n, d, beta, seed)
+    c = orc.solve_c(w, d, T, deg)
+    assert res.info["c"] == pytest.approx(c, rel=1e-12)
+    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True)
+    compare(ge, run)
+
+
+def test_deterministic_output(hg):
+    a = hg.generate(50000, d=2, beta=2.5, T=0.5, avg_deg=12.0, seed=9).edges.cpu().numpy()
+    b = hg.generate(50000, d=2, beta=2.5, T=0.5, avg_deg=12.0, seed=9).edges.cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_overflow_reports_needed_capacity(hg):
+    import ctypes
+    import torch
+    L = hg.load()
+    p = hg.make_params(20000, 2, 2.5, 0.5, 10.0, 0.0, 3)
+    buf = torch.empty((10, 2), dtype=torch.int32, device="cuda")
+    m = ctypes.c_uint64(0)
+    st = L.girg_generate(ctypes.byref(p), ctypes.c_void_p(buf.data_ptr()), 10, ctypes.byref(m), None,
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == hg.GIRG_EOVERFLOW
+    full = hg.generate(20000, d=2, beta=2.5, T=0.5, avg_deg=10.0, seed=3)
+    assert m.value == full.edges.shape[0]
+
+
+def test_invalid_parameters(hg):
+    with pytest.raises(hg.GirgError):
+        hg.generate(1000, d=5, beta=2.5, avg_deg=10)
+    with pytest.raises(hg.GirgError):
+        hg.generate(1000, d=2, beta=1.9, avg_deg=10)
+    with pytest.raises(hg.GirgError):
+        hg.generate(1000, d=2, beta=2.5, T=1.0, avg_deg=10)
+    with pytest.raises(hg.GirgError):
+        hg.generate(1000, d=2, beta=2.5, avg_deg=10, c=1.0)
+
+
+def test_empty_and_tiny_graphs(hg, orc):
+    for n in (2, 3, 17):
+        w = synth.pareto_weights(n, 2.5, n)
+        x = synth.positions(n, 2, n)
+        ge, info, run = run_both(hg, orc, w, x, T=0.5, c=0.05, seed=1)
+        compare(ge, run)
+    # a graph with no edges at all
+    w = np.ones(64)
+    x = synth.positions(64, 3, 1)
+    ge, info, run = run_both(hg, orc, w, x, T=0.0, c=1e-9, seed=1)
+    assert len(ge) == 0 and len(run.edges) == 0
