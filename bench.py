@@ -1,0 +1,201 @@
+"""Throughput benchmark of the gfx950 GIRG / HRG sampler.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One step is one full call of the C ABI (points, constant, layers, sort, level
+tables, prefix sums, enumeration, type-I tests, type-II geometric jumps, edge
+compaction) for one graph of the workload; the inputs are synthetic and drawn
+on the device from the seed.  Prints ONE JSON line on stdout; diagnostics go
+to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "edges/sec on 1 MI355X (+% HBM peak), mixed vs plain FP64, at oracle match"
+
+# name: (description, generate kwargs)
+WORKLOADS = {
+    "girg_d1_n1e4": ("GIRG d=1 n=10^4 beta=2.5 T=0 avg_deg=10 seed=1 FP64",
+                     dict(model=0, n=10**4, d=1, beta=2.5, T=0.0, avg_deg=10.0, seed=1, precision=0)),
+    "girg_d2_n2p20": ("GIRG d=2 n=2^20 beta=2.7 T=0.5 avg_deg=16 seed=2 FP64",
+                      dict(model=0, n=2**20, d=2, beta=2.7, T=0.5, avg_deg=16.0, seed=2, precision=0)),
+    "hrg_n2p20": ("HRG n=2^20 alpha=0.75 T=0.5 avg_deg=10 (R solved) seed=3 FP64",
+                  dict(model=1, n=2**20, d=1, alpha=0.75, T=0.5, avg_deg=10.0, seed=3, precision=0)),
+    "girg_d3_n1e7": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4 FP64",
+                     dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=0)),
+    "girg_d3_n1e7_mixed": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4 FP32 filter + FP64 recheck",
+                           dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=1)),
+}
+DEFAULT = "girg_d2_n2p20"
+
+# Peak figures (MI355X): HBM3E 8 TB/s; VALU 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-operations per second, in T
+
+# algorithmic VALU lane-operations per unit of work (derivation in the design doc)
+OPS_TEST_T0 = 15.0      # threshold test: torus distance, product, compare
+OPS_TEST_BINOM = 120.0  # binomial test: distance, pow (log + exp), half a Philox block, compare
+OPS_DRAW = 80.0         # geometric draw: one Philox block, one log, divide, compare
+OPS_CAND = 70.0         # candidate: distance, pow, compare
+
+
+def _stage_ops(stage: str, info: dict, T: float) -> float | None:
+    if stage.startswith("type1"):
+        return info["tests"] * (OPS_TEST_T0 if T == 0.0 else OPS_TEST_BINOM)
+    if stage.startswith("type2") or stage.startswith("heavy"):
+        return None  # draws of a pass are split between type-II and heavy kernels
+    return None
+
+
+def make_call(hg, wl: dict):
+    L = hg.load()
+    if wl["model"] == 1:
+        def call(buf, cap, m, info, stream):
+            return L.girg_hrg(wl["n"], wl["alpha"], wl["T"], 0.0, wl["avg_deg"], wl["seed"], buf, cap,
+                              m, info, stream)
+        return call
+    p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"],
+                       wl["precision"])
+
+    def call(buf, cap, m, info, stream):
+        return L.girg_generate(ctypes.byref(p), buf, cap, m, info, stream)
+    return call
+
+
+def cpu_baseline(wl: dict) -> dict:
+    """The oracle as it stands, single-threaded, on one full graph of the
+    workload (points, constant and sampling), when that is about 10-30 s of
+    CPU work; otherwise on a sampled share of its cell pairs."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    n = wl["n"]
+    t0 = time.perf_counter()
+    if wl["model"] == 1:
+        R = oracle.hrg_solve_R(n, wl["alpha"], wl["T"], wl["avg_deg"])
+        r, x = oracle.points_hrg(n, wl["alpha"], R, wl["seed"])
+        kw = dict(T=wl["T"], model=1, R=R, alpha=wl["alpha"], seed=wl["seed"])
+        w = r
+    else:
+        w, x = oracle.points_girg(n, wl["d"], wl["beta"], wl["seed"])
+        c = oracle.solve_c(w, wl["d"], wl["T"], wl["avg_deg"])
+        kw = dict(T=wl["T"], c=c, seed=wl["seed"])
+    sample = "one full graph (points, constant, sampling)"
+    if n > 2**21:
+        # sampled: cell pairs whose level-3 A-side ancestor is 0 mod 16
+        kw.update(filter_level=3, filter_mod=16, filter_rem=0)
+        sample = "points + constant for the full graph; sampling restricted to 1/16 of the level-3 subtrees"
+    run = oracle.run(w, x, **kw)
+    dt = time.perf_counter() - t0
+    m = len(run.edges)
+    return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {m} edges in {dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this sampler has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1905_06706_amd as hg
+
+    desc, wl = WORKLOADS[args.workload]
+    L = hg.load()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    call = make_call(hg, wl)
+
+    # first call sizes the output exactly (the sampler is deterministic)
+    m = ctypes.c_uint64(0)
+    info = hg.Info()
+    st = call(None, 0, ctypes.byref(m), ctypes.byref(info), sp)
+    if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
+        hg._check(st)
+    cap = int(m.value)
+    buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+    bp = ctypes.c_void_p(buf.data_ptr())
+    for _ in range(args.warmup):
+        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
+    hg.set_profiling(True)
+    stage_sum: dict = {}
+    edges = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
+        edges += m.value
+        for name, ms in hg.stage_times():
+            stage_sum[name] = stage_sum.get(name, 0.0) + ms
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hg.set_profiling(False)
+    dt = t1 - t0
+    info_d = info.as_dict()
+    stages = {k: v / args.steps for k, v in stage_sum.items()}
+    print(f"[bench] {desc}: m={m.value} steps={args.steps} {dt / args.steps * 1e3:.3f} ms/step",
+          file=sys.stderr)
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
+        print(f"[bench]   {k:>14s} {v:9.4f} ms", file=sys.stderr)
+    print(f"[bench] info {info_d}", file=sys.stderr)
+
+    # dominant kernel and its roofline (VALU-bound: lane-operations)
+    kernel_stages = {k: v for k, v in stages.items() if k.startswith(("type1", "type2", "heavy"))}
+    dom = max(kernel_stages, key=kernel_stages.get) if kernel_stages else max(stages, key=stages.get)
+    dom_ms = stages[dom]
+    if dom.startswith("type1"):
+        ops = info_d["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
+    else:
+        # type-II count and write passes each repeat all light draws; the
+        # heavy kernel's share is reported within the same counters
+        ops = info_d["draws"] * OPS_DRAW + info_d["candidates"] * OPS_CAND
+    achieved = ops / (dom_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS,
+            "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+            "launch_ms": dom_ms}
+    value = edges / dt
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl["precision"] == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, **{k: wl[k] for k in wl}},
+        "edges_per_step": int(m.value),
+        "hbm_frac_edge_output": value * 8 / (HBM_PEAK_GBS * 1e9),
+        "roofline": roof,
+        "stages_ms": stages,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

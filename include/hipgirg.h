@@ -138,6 +138,14 @@ girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, do
 girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
                                 uint64_t* offsets, girg_info* infos, void* stream);
 
+/* Profiling: with girg_set_profiling(1), every later call on this device
+ * records HIP events around its stages on the call's own stream.
+ * girg_stage_times copies the durations (milliseconds) and names of the last
+ * call's stages (at most `max`; either array may be NULL) and returns how many
+ * there were, or -1 on error.  Names stay valid until the next call. */
+girg_status girg_set_profiling(int32_t on);
+int32_t girg_stage_times(double* ms, const char** names, int32_t max);
+
 /* Frees the scratch memory cached for the current device. */
 girg_status girg_release(void);
 

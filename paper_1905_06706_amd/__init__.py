@@ -25,7 +25,7 @@ _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ENOC
 EXPORTS = (
     "girg_generate", "girg_hrg", "girg_from_points", "girg_points", "girg_solve_c",
     "girg_expected_degree", "hrg_solve_R", "hrg_expected_degree", "girg_generate_batch",
-    "girg_release", "girg_last_error", "girg_version",
+    "girg_release", "girg_last_error", "girg_version", "girg_set_profiling", "girg_stage_times",
 )
 
 
@@ -83,8 +83,12 @@ def load() -> ctypes.CDLL:
     L.hrg_expected_degree.argtypes = [u64, dbl, dbl, dbl, P(dbl)]
     L.girg_generate_batch.argtypes = [P(Params), ctypes.c_int32, vp, u64, P(u64), P(Info), vp]
     L.girg_release.argtypes = []
+    L.girg_set_profiling.argtypes = [ctypes.c_int32]
+    L.girg_stage_times.argtypes = [P(dbl), P(ctypes.c_char_p), ctypes.c_int32]
     for name in EXPORTS:
-        if name in ("girg_last_error", "girg_version"):
+        if name == "girg_stage_times":
+            L.girg_stage_times.restype = ctypes.c_int32
+        elif name in ("girg_last_error", "girg_version"):
             getattr(L, name).restype = ctypes.c_char_p
         else:
             getattr(L, name).restype = st
@@ -249,6 +253,19 @@ def generate_batch(params: list, cap: int | None = None, stream=None, device="cu
         _check(st)
         return buf[: offs[cnt]], list(offs), [i.as_dict() for i in infos]
     _check(GIRG_EOVERFLOW)
+
+
+def set_profiling(on: bool):
+    _check(load().girg_set_profiling(1 if on else 0))
+
+
+def stage_times() -> list:
+    """[(stage name, milliseconds)] of the last call (profiling on)."""
+    L = load()
+    ms = (ctypes.c_double * 64)()
+    names = (ctypes.c_char_p * 64)()
+    k = L.girg_stage_times(ms, names, 64)
+    return [(names[i].decode(), ms[i]) for i in range(max(k, 0))]
 
 
 def release():

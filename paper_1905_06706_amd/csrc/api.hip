@@ -85,12 +85,42 @@ struct Ctx {
   unsigned long long* stats = nullptr;  // 8
   unsigned int* hcount = nullptr;
   std::mutex mu;
+  // stage timing (HIP events on the call's stream), enabled by girg_set_profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<std::string> ev_name;
+  std::vector<double> last_ms;
+  std::vector<std::string> last_name;
+  void mark(const char* name, hipStream_t st) {
+    if (!profiling) return;
+    if (ev.size() <= ev_name.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { profiling = false; return; }
+      ev.push_back(e);
+    }
+    (void)hipEventRecord(ev[ev_name.size()], st);
+    ev_name.push_back(name);
+  }
+  void collect() {
+    last_ms.clear();
+    last_name.clear();
+    if (!profiling || ev_name.empty()) return;
+    (void)hipEventSynchronize(ev[ev_name.size() - 1]);
+    for (size_t k = 1; k < ev_name.size(); ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k - 1], ev[k]);
+      last_ms.push_back(ms);
+      last_name.push_back(ev_name[k]);
+    }
+    ev_name.clear();
+  }
   ~Ctx() {
     if (gd) (void)hipFree(gd);
     if (red) (void)hipFree(red);
     if (flag) (void)hipFree(flag);
     if (stats) (void)hipFree(stats);
     if (hcount) (void)hipFree(hcount);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -419,6 +449,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   g.seed_hi = (uint32_t)(p.seed >> 32);
   const uint64_t n = p.n;
   const int d = g.d;
+  if (cx.ev_name.empty()) cx.mark("-", st);
 
   // exact sum W and min / max of w (GIRG) or r (HRG)
   HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
@@ -445,7 +476,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint64_t* keys = ar.get<uint64_t>(n);
   uint32_t* ids = ar.get<uint32_t>(n);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (keys)");
+  cx.mark("-", st);
   HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
+  cx.mark("layer_key", st);
   uint32_t flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, cx.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(g.count, cx.gd->count, sizeof(g.count), hipMemcpyDeviceToHost, st));
@@ -465,7 +498,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   const int lbits = bitlen((uint64_t)(g.L > 0 ? g.L - 1 : 0));
 
   // stable sort by (layer, Morton code); ties keep id order
+  cx.mark("-", st);
   HIPCHK(radix_sort(ar, keys, ids, n, g.bits + lbits, st));
+  cx.mark("sort", st);
   double* sw = ar.get<double>(n);
   double* sx = ar.get<double>(n * d);
   uint32_t* smort = ar.get<uint32_t>(n);
@@ -473,6 +508,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   double* aux = p.model == 1 ? ar.get<double>(3 * n) : nullptr;
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
   HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, sx, smort, slayer, aux, st));
+  cx.mark("gather", st);
 
   // constant c (App. B.2)
   if (p.model == 0) {
@@ -516,7 +552,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (pbar)");
   }
   HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
+  cx.mark("-", st);
   HIPCHK(launch_tables(cx.gd, Dcap, pbt, st));
+  cx.mark("tables", st);
   HIPCHK(hipMemcpyAsync(&g, cx.gd, sizeof(Graph), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
 
@@ -531,115 +569,180 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(hipMemcpyAsync(cx.gd->pbase, g.pbase, sizeof(g.pbase), hipMemcpyHostToDevice, st));
   uint32_t* P = ar.get<uint32_t>(cells);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (cells)");
+  cx.mark("-", st);
   HIPCHK(hipMemsetAsync(P, 0, cells * sizeof(uint32_t), st));
   HIPCHK(launch_cell_count(g, cx.gd, smort, slayer, P, st));
   HIPCHK(scan_u32(ar, P, P, cells, nullptr, st));
+  cx.mark("cells", st);
 
   // run sources
   uint32_t* scnt = ar.get<uint32_t>(n + 1);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
-  HIPCHK(launch_sources(g, cx.gd, smort, slayer, scnt, nullptr, nullptr, false, st));
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, scnt, nullptr, nullptr, false, st));
   HIPCHK(scan_u32(ar, scnt, scnt, n, scnt + n, st));
+  cx.mark("sources_count", st);
   uint32_t nsrc = 0;
   HIPCHK(hipMemcpyAsync(&nsrc, scnt + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  uint64_t* src = ar.get<uint64_t>(std::max<uint64_t>(nsrc, 1));
+  Src* src = ar.get<Src>(std::max<uint64_t>(nsrc, 1));
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
-  HIPCHK(launch_sources(g, cx.gd, smort, slayer, nullptr, scnt, src, true, st));
+  cx.mark("-", st);
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, true, st));
+  cx.mark("sources_fill", st);
 
   Verts v{sw, sx, ids, smort, slayer, aux, nullptr};
-
-  // count passes
-  const int NW = kSampleWaves;
-  uint32_t* wcount = ar.get<uint32_t>(3 * NW);
-  uint64_t* wbase = ar.get<uint64_t>(3 * NW + 1);
-  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (wave counts)");
-  HIPCHK(hipMemsetAsync(wcount, 0, 3 * NW * sizeof(uint32_t), st));
-  HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
-  HIPCHK(hipMemsetAsync(cx.hcount, 0, sizeof(unsigned int), st));
-  WaveOut wo1{wcount, nullptr, nullptr, cx.stats};
-  WaveOut wo2{wcount + NW, nullptr, nullptr, cx.stats};
-  WaveOut wo3{wcount + 2 * NW, nullptr, nullptr, cx.stats};
   const bool binomial = p.T > 0.0;
-  if (nsrc) HIPCHK(launch_type1(g, cx.gd, v, P, src, nsrc, false, wo1, st));
-  const uint32_t hcap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(n / 4, 1u << 16), 1u << 26);
-  HeavyRec* hrec = nullptr;
-  uint64_t* hkey = nullptr;
-  if (binomial) {
-    hrec = ar.get<HeavyRec>(hcap);
-    hkey = ar.get<uint64_t>(hcap);
-    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (heavy items)");
+  uint64_t n1 = 1, n2 = 1;
+  for (int k = 0; k < d; ++k) { n1 *= 3; n2 *= 6; }
+
+  // pass bookkeeping: 0 type-I, 1 split type-I, 2 type-II, 3 segmented type-II
+  unsigned int* tickets = ar.get<unsigned int>(8);
+  unsigned int* dcount = ar.get<unsigned int>(2);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (tickets)");
+  HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));
+  HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
+  auto make_sched = [&](uint64_t nunits, int slot) {
+    uint64_t ch = (nunits + 16383) / 16384;
+    ch = ((ch + 63) / 64) * 64;
+    ch = std::max<uint64_t>(64, std::min<uint64_t>(4096, ch));
+    Sched sc{tickets + slot, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch)};
+    return sc;
+  };
+  Sched sch[4];
+  uint64_t* pcnt[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool live[4] = {false, false, false, false};
+  sch[0] = make_sched(nsrc ? nsrc * n1 : 0, 0);
+  sch[2] = make_sched(binomial && nsrc ? nsrc * n2 : 0, 2);
+  for (int q : {0, 2}) {
+    live[q] = sch[q].nchunks > 0;
+    pcnt[q] = ar.get<uint64_t>(sch[q].nchunks + 1);
   }
-  HeavyOut ho{hrec, hkey, cx.hcount, hcap};
-  if (binomial && nsrc) HIPCHK(launch_type2(g, cx.gd, v, P, src, nsrc, pbt, nlev, false, wo2, ho, st));
-  unsigned int nh = 0;
-  HIPCHK(hipMemcpyAsync(&nh, cx.hcount, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (nh > hcap) return fail(GIRG_ENOMEM, "too many heavy type-II items");
-  HeavyRec* hsorted = nullptr;
-  uint64_t* segoff = nullptr;
-  uint64_t nseg_total = 0;
-  if (nh) {
-    // deterministic order of the heavy items
-    uint32_t* perm = ar.get<uint32_t>(nh);
-    hsorted = ar.get<HeavyRec>(nh);
-    segoff = ar.get<uint64_t>(nh + 1);
-    uint64_t* tmp = ar.get<uint64_t>(nh);
-    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (heavy sort)");
-    std::vector<uint32_t> iota(nh);
-    for (uint32_t i = 0; i < nh; ++i) iota[i] = i;
-    HIPCHK(hipMemcpyAsync(perm, iota.data(), nh * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(tmp, hkey, nh * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    HIPCHK(radix_sort(ar, tmp, perm, nh, 40, st));
-    HIPCHK(launch_heavy_gather(hrec, perm, nh, hsorted, st));
-    HIPCHK(launch_heavy_prep(hsorted, nh, segoff, st));
-    HIPCHK(scan_u64(ar, segoff, segoff, nh, segoff + nh, st));
-    HIPCHK(hipMemcpyAsync(&nseg_total, segoff + nh, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (chunk counts)");
+
+  // count passes with deferred lists (grown once if too small)
+  uint32_t dcap[2] = {(uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024),
+                      (uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024)};
+  ItemRec* drec[2] = {nullptr, nullptr};
+  uint64_t* dkey[2] = {nullptr, nullptr};
+  unsigned int dn[2] = {0, 0};
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    Arena::Mark mk = ar.mark();
+    for (int q = 0; q < 2; ++q) {
+      drec[q] = ar.get<ItemRec>(dcap[q]);
+      dkey[q] = ar.get<uint64_t>(dcap[q]);
+    }
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
+    HIPCHK(hipMemsetAsync(dcount, 0, 2 * sizeof(unsigned int), st));
+    HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));
+    HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
+    PassOut po0{pcnt[0], nullptr, 0, nullptr, cx.stats};
+    PassOut po2{pcnt[2], nullptr, 0, nullptr, cx.stats};
+    DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
+    DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
+    cx.mark("-", st);
+    if (live[0]) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], false, po0, df0, st));
+    cx.mark("type1_count", st);
+    if (live[2]) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, false, po2, df1, st));
+    cx.mark("type2_count", st);
+    HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(launch_heavy(g, cx.gd, v, hsorted, segoff, nh, nseg_total, pbt, nlev, false, wo3, st));
+    if (dn[0] <= dcap[0] && dn[1] <= dcap[1]) break;
+    if (attempt == 1) return fail(GIRG_ENOMEM, "deferred item lists overflowed");
+    ar.reset(mk);
+    dcap[0] = std::max(dcap[0], dn[0]);
+    dcap[1] = std::max(dcap[1], dn[1]);
   }
 
-  // offsets of every wave's edges; total
-  // (the counts are u32; widen into the u64 base array, then scan)
-  {
-    std::vector<uint32_t> hc(3 * NW);
-    HIPCHK(hipMemcpyAsync(hc.data(), wcount, 3 * NW * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  // deferred items in a deterministic order, their units and count passes
+  ItemRec* dsorted[2] = {nullptr, nullptr};
+  uint64_t* uoff[2] = {nullptr, nullptr};
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t nd = dn[q];
+    if (!nd) continue;
+    uint32_t* perm = ar.get<uint32_t>(nd);
+    uint64_t* kt = ar.get<uint64_t>(nd);
+    dsorted[q] = ar.get<ItemRec>(nd);
+    uoff[q] = ar.get<uint64_t>(nd + 1);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred sort)");
+    cx.mark("-", st);
+    HIPCHK(launch_iota(perm, nd, st));
+    HIPCHK(hipMemcpyAsync(kt, dkey[q], nd * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(radix_sort(ar, kt, perm, nd, 48, st));
+    HIPCHK(launch_rec_gather(drec[q], perm, nd, dsorted[q], st));
+    HIPCHK(launch_rec_units(dsorted[q], nd, q == 0 ? 1 : 2, uoff[q], st));
+    HIPCHK(scan_u64(ar, uoff[q], uoff[q], nd, uoff[q] + nd, st));
+    uint64_t nunits = 0;
+    HIPCHK(hipMemcpyAsync(&nunits, uoff[q] + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    std::vector<uint64_t> hb(3 * NW + 1);
-    uint64_t accm = 0;
-    for (int i = 0; i < 3 * NW; ++i) { hb[i] = accm; accm += hc[i]; }
-    hb[3 * NW] = accm;
-    uint64_t m1 = hb[NW], m2 = hb[2 * NW] - hb[NW];
-    *m_out = accm;
-    if (info) {
-      info->m = accm;
-      info->type1_edges = m1;
-      info->type2_edges = accm - m1;
-      (void)m2;
+    cx.mark(q == 0 ? "split_prep" : "segment_prep", st);
+    const int pq = q == 0 ? 1 : 3;
+    sch[pq] = make_sched(nunits, pq);
+    live[pq] = sch[pq].nchunks > 0;
+    pcnt[pq] = ar.get<uint64_t>(sch[pq].nchunks + 1);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (chunk counts)");
+    PassOut pc{pcnt[pq], nullptr, 0, nullptr, cx.stats};
+    if (q == 0) {
+      HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], nd, sch[1], false, pc, st));
+      cx.mark("split1_count", st);
+    } else {
+      HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], nd, sch[3], pbt, nlev, false, pc, st));
+      cx.mark("heavy2_count", st);
     }
-    if (accm > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
-    HIPCHK(hipMemcpyAsync(wbase, hb.data(), hb.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   }
+
+  // chunk offsets within each pass, pass offsets, total
+  uint64_t ptot[4] = {0, 0, 0, 0};
+  cx.mark("-", st);
+  for (int q = 0; q < 4; ++q) {
+    if (!live[q]) continue;
+    HIPCHK(scan_u64(ar, pcnt[q], pcnt[q], sch[q].nchunks, pcnt[q] + sch[q].nchunks, st));
+  }
+  for (int q = 0; q < 4; ++q)
+    if (live[q])
+      HIPCHK(hipMemcpyAsync(&ptot[q], pcnt[q] + sch[q].nchunks, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  cx.mark("offsets", st);
+  const uint64_t padd[4] = {0, ptot[0], ptot[0] + ptot[1], ptot[0] + ptot[1] + ptot[2]};
+  const uint64_t mtot = ptot[0] + ptot[1] + ptot[2] + ptot[3];
+  *m_out = mtot;
+  if (info) {
+    info->m = mtot;
+    info->type1_edges = ptot[0] + ptot[1];
+    info->type2_edges = ptot[2] + ptot[3];
+  }
+  if (mtot > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
 
   // write passes
   uint2* out = reinterpret_cast<uint2*>(edges);
-  WaveOut ww1{nullptr, wbase, out, cx.stats};
-  WaveOut ww2{nullptr, wbase + NW, out, cx.stats};
-  WaveOut ww3{nullptr, wbase + 2 * NW, out, cx.stats};
-  if (nsrc) HIPCHK(launch_type1(g, cx.gd, v, P, src, nsrc, true, ww1, st));
-  if (binomial && nsrc) HIPCHK(launch_type2(g, cx.gd, v, P, src, nsrc, pbt, nlev, true, ww2, ho, st));
-  if (nh) HIPCHK(launch_heavy(g, cx.gd, v, hsorted, segoff, nh, nseg_total, pbt, nlev, true, ww3, st));
+  DeferOut none{nullptr, nullptr, dcount, 0};
+  PassOut pw[4];
+  for (int q = 0; q < 4; ++q) pw[q] = PassOut{nullptr, pcnt[q], padd[q], out, cx.stats};
+  HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));  // fresh tickets for the write passes
+  cx.mark("-", st);
+  if (live[0]) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], true, pw[0], none, st));
+  cx.mark("type1_write", st);
+  if (live[1]) {
+    HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], true, pw[1], st));
+    cx.mark("split1_write", st);
+  }
+  if (live[2]) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, true, pw[2], none, st));
+  cx.mark("type2_write", st);
+  if (live[3]) {
+    HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], dn[1], sch[3], pbt, nlev, true, pw[3], st));
+    cx.mark("heavy2_write", st);
+  }
 
   unsigned long long stt[8];
   HIPCHK(hipMemcpyAsync(stt, cx.stats, sizeof(stt), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  cx.collect();
   if (info) {
     info->tests = stt[0];
     info->draws = stt[1];
     info->candidates = stt[2];
     info->rechecks = stt[3];
     info->sources = nsrc;
-    info->heavy_items = nh;
+    info->heavy_items = dn[1];
     info->cells = cells;
     info->c = g.c;
     info->W = g.W;
@@ -711,6 +814,7 @@ girg_status girg_from_points(const girg_params* p, const double* w, const double
   if ((s = with_ctx(&cx)) != GIRG_OK) return s;
   std::lock_guard<std::mutex> lk(cx->mu);
   if (info) std::memset(info, 0, sizeof(*info));
+  cx->ev_name.clear();
   return run_graph(*cx, *p, w, x, edges, cap, m_out, info, static_cast<hipStream_t>(stream));
 }
 
@@ -741,7 +845,10 @@ static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t
   g.R = q.R;
   g.seed_lo = (uint32_t)q.seed;
   g.seed_hi = (uint32_t)(q.seed >> 32);
+  cx->ev_name.clear();
+  cx->mark("-", st);
   HIPCHK(launch_points(g, q.beta, w, x, st));
+  cx->mark("points", st);
   return run_graph(*cx, q, w, x, edges, cap, m_out, info, st);
 }
 
@@ -795,6 +902,29 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
     offsets[b + 1] = used;
   }
   return GIRG_OK;
+}
+
+girg_status girg_set_profiling(int32_t on) {
+  Ctx* cx = nullptr;
+  girg_status s = get_ctx(&cx);
+  if (s != GIRG_OK) return s;
+  std::lock_guard<std::mutex> lk(cx->mu);
+  cx->profiling = on != 0;
+  return GIRG_OK;
+}
+
+int32_t girg_stage_times(double* ms, const char** names, int32_t max) {
+  Ctx* cx = nullptr;
+  if (get_ctx(&cx) != GIRG_OK) return -1;
+  std::lock_guard<std::mutex> lk(cx->mu);
+  int32_t k = 0;
+  for (size_t i = 0; i < cx->last_ms.size() && k < max; ++i) {
+    if (cx->last_name[i] == "-") continue;
+    if (ms) ms[k] = cx->last_ms[i];
+    if (names) names[k] = cx->last_name[i].c_str();
+    ++k;
+  }
+  return k;
 }
 
 girg_status girg_solve_c(const double* w_host, uint64_t n, int32_t d, double T, double avg_deg,

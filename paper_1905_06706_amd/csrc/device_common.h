@@ -153,6 +153,22 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 }
 
 // ---------------------------------------------------------------------------
+// cells
+// ---------------------------------------------------------------------------
+// Morton code of the cell at level lvl of a code at level Dmax (bits wide)
+__device__ __forceinline__ uint32_t cell_at(uint32_t m, int lvl, int d, int bits) {
+  return lvl == 0 ? 0u : (m >> (bits - d * lvl));
+}
+
+__device__ __forceinline__ int bitlen64(uint64_t v) { return v ? 64 - __clzll((long long)v) : 0; }
+
+template <int D>
+struct Offs {
+  static constexpr int n1 = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;      // neighbour offsets
+  static constexpr int n2 = D == 1 ? 6 : D == 2 ? 36 : D == 3 ? 216 : 1296;  // parent-neighbour children
+};
+
+// ---------------------------------------------------------------------------
 // Per-graph description, built on the device by the table kernel and read by
 // every sampling kernel.
 // ---------------------------------------------------------------------------

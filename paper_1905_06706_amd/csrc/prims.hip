@@ -225,6 +225,17 @@ hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int 
   return hipGetLastError();
 }
 
+__global__ void k_iota(uint32_t* __restrict__ p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // stable LSD radix sort, 8-bit digits, tiles of 256 threads x 16 keys
 // ---------------------------------------------------------------------------

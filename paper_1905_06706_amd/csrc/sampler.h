@@ -1,29 +1,50 @@
-// sampler.h -- launchers of the sampler kernels (sampler.hip) and the small
-// structures they share with the host driver.
+// sampler.h -- launchers of the preprocessing kernels (prep.hip) and of the
+// sampling kernels (sample.hip), and the records they exchange with the host
+// driver.
 #pragma once
 
 #include "internal.h"
 
 namespace hg {
 
-constexpr int kSampleBlocks = 2048;                 // fixed grid: 8192 waves
-constexpr int kSampleWaves = kSampleBlocks * 4;
+constexpr int kPersistBlocks = 1024;  // persistent grids: 4096 waves
+constexpr uint32_t kBigTests = 256;   // type-I items with more tests are split
+constexpr uint32_t kTestChunk = 64;   // tests per unit of a split type-I item
 
-struct WaveOut {
-  uint32_t* count;             // per-wave edge counts (count pass)
-  const uint64_t* base;        // per-wave output offsets (write pass)
+// one run of a layer's cell: sorted position s of its first vertex, its cell
+// A at the level, |V_i^A|, and meta = level | layer << 8
+struct Src {
+  uint32_t s, A, na, meta;
+};
+
+// a deferred item: type-I with more than kBigTests tests, or type-II with
+// more than one segment.  meta = level | i << 8 | j << 16 | gap << 24 |
+// tri << 31; e = segment exponent (type-II)
+struct ItemRec {
+  uint32_t a0, na, b0, nb, A, B, meta, e;
+};
+
+// dynamic chunk scheduling: waves take chunks of `chunk` units by ticket
+struct Sched {
+  unsigned int* next;  // ticket counter (zeroed before each launch)
+  uint64_t nunits;
+  uint32_t chunk;
+  uint32_t nchunks;
+};
+
+// per-chunk edge counts (count pass) / exclusive offsets (write pass)
+struct PassOut {
+  uint64_t* count;             // count pass: edges of chunk c
+  const uint64_t* base;        // write pass: offset of chunk c within the pass
+  uint64_t add;                // write pass: offset of the pass
   uint2* edges;
   unsigned long long* stats;   // 0 tests, 1 draws, 2 candidates, 3 rechecks
 };
 
-// a type-II item whose candidate range spans more than one segment
-struct HeavyRec {
-  uint32_t a0, na, b0, nb, A, B, meta, e;  // meta = level | i << 8 | j << 16 | gap << 24
-};
-
-struct HeavyOut {
-  HeavyRec* rec;
-  uint64_t* key;         // (wave << 24) | sequence within the wave
+// deferred items (count pass only): key = chunk << 24 | sequence in chunk
+struct DeferOut {
+  ItemRec* rec;
+  uint64_t* key;
   unsigned int* count;
   uint32_t cap;
 };
@@ -38,20 +59,26 @@ hipError_t launch_tables(Graph* gd, int Dcap, Pbar* pb, hipStream_t st);
 hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* smort,
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
-                          const uint8_t* slayer, uint32_t* cnt, const uint32_t* off, uint64_t* src,
-                          bool fill, hipStream_t st);
+                          const uint8_t* slayer, const uint32_t* P, uint32_t* cnt,
+                          const uint32_t* off, Src* src, bool fill, hipStream_t st);
+
+// sampling passes
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const uint64_t* src, uint64_t nsrc, bool write, const WaveOut& wo,
-                        hipStream_t st);
+                        const Src* src, const Sched& sc, bool write, const PassOut& po,
+                        const DeferOut& dfo, hipStream_t st);
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const uint64_t* src, uint64_t nsrc, const Pbar* pbt, int nlev, bool write,
-                        const WaveOut& wo, const HeavyOut& ho, hipStream_t st);
-hipError_t launch_heavy_prep(const void* rec, uint32_t nh, uint64_t* nseg, hipStream_t st);
-hipError_t launch_heavy_gather(const void* in, const uint32_t* perm, uint32_t nh, void* out,
-                               hipStream_t st);
-hipError_t launch_heavy(const Graph& g, const Graph* gd, const Verts& v, const void* rec,
-                        const uint64_t* segoff, uint32_t nh, uint64_t nseg, const Pbar* pbt,
-                        int nlev, bool write, const WaveOut& wo, hipStream_t st);
-size_t heavy_rec_size();
+                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev, bool write,
+                        const PassOut& po, const DeferOut& dfo, hipStream_t st);
+// deferred items: units per record (kind 1: test chunks, kind 2: segments)
+hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
+                            hipStream_t st);
+hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
+                             hipStream_t st);
+hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
+                       const uint64_t* uoff, uint32_t nrec, const Sched& sc, bool write,
+                       const PassOut& po, hipStream_t st);
+hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
+                         const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
+                         int nlev, bool write, const PassOut& po, hipStream_t st);
 
 }  // namespace hg

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     with open(os.path.join(ROOT, "include", "hipgirg.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:girg_status|const char\*)\s+(\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:girg_status|const char\*|int32_t)\s+(\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
