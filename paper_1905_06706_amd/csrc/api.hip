@@ -511,6 +511,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   cx.mark("gather", st);
 
   // constant c (App. B.2)
+  cx.mark("-", st);
   if (p.model == 0) {
     double c = p.c;
     if (!(c > 0.0)) {
@@ -542,6 +543,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     g.c = c;
     g.kappa = p.T > 0.0 ? std::pow(c, p.T) : std::pow(c, (double)d);
   }
+  cx.mark("c_solve", st);
 
   // level tables
   const int Dcap = std::min(g.Dmax, (bitlen(n) + 3) / d);

@@ -268,14 +268,150 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-wave LDS buffers of the sampling passes.  A wave first decodes units
+// and appends the valid (run, cell B) pairs to `vb` (phase A), then takes 64
+// of them, one per lane, and walks the layers j of each pair (phase B,
+// converged: the pairs of one run share their layer masks); non-empty items
+// go to an item ring.  The rings are consumed in converged steps: type-I
+// takes 64 Philox blocks (two tests each) per step flat across the queued
+// items; type-II lanes own one item each and make one geometric draw per
+// step, pushing candidates into a candidate ring that is evaluated 64 at a
+// time.  Every append and dequeue is a ballot in converged code, so the order
+// of the emitted edges is a pure function of the chunk.
+// ---------------------------------------------------------------------------
+constexpr int kVCap = 128;  // valid-unit buffer (>= 2 x 64)
+constexpr int kQCap = 128;  // item ring (power of two, >= 2 x 64)
+constexpr int kCCap = 128;  // candidate ring (power of two, >= 2 x 64)
+
+struct VUnit {
+  uint32_t sidx, B, gap, pad;
+};
+
+// type-I item; cs = index of its first Philox block in the wave's block stream
+struct QItem1 {
+  uint32_t A, B, w3, a0, b0, nb, na, tri, cs;
+};
+
+// type-II item (one segment, k and N < 2^32)
+struct QItem2 {
+  uint32_t A, B, w3, a0, b0, nb, t, k, N, pad;
+  double pb, lg;
+};
+
+// type-II candidate: sorted indices and Acc * pbar
+struct Cand {
+  uint32_t su, sv;
+  double apb;
+};
+
+// phase A: decode units until 64 valid pairs are buffered or the chunk ends
+template <int D, bool DISTANT>
+__device__ __forceinline__ void fill_units(const Graph* __restrict__ g, const Src* __restrict__ src,
+                                           uint64_t& u, uint64_t ue, VUnit* __restrict__ vb,
+                                           uint32_t& vn) {
+  constexpr int NOFF = DISTANT ? Offs<D>::n2 : Offs<D>::n1;
+  while (vn < 64 && __any(u < ue)) {
+    bool valid = false;
+    uint32_t B = 0;
+    int gap = 0;
+    uint64_t sidx = 0;
+    if (u < ue) {
+      sidx = u / NOFF;
+      const uint32_t off = (uint32_t)(u - sidx * NOFF);
+      u += kWave;
+      const Src sr = src[sidx];
+      const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
+      if constexpr (DISTANT) {
+        if (g->jII[li][lvl]) valid = distant_cell<D>(sr.A, lvl, off, &B, &gap) && B > sr.A;
+      } else {
+        if (g->jI[li][lvl]) valid = neighbour_cell<D>(sr.A, lvl, off, &B) && B >= sr.A;
+      }
+    }
+    const uint64_t mv = __ballot(valid);
+    if (valid) vb[vn + lanes_below(mv)] = VUnit{(uint32_t)sidx, B, (uint32_t)gap, 0u};
+    vn += (uint32_t)__popcll(mv);
+  }
+}
+
+// phase B helper: lane takes buffered pair `lane` (if any) and shifts the rest
+__device__ __forceinline__ bool take_unit(VUnit* __restrict__ vb, uint32_t& vn, VUnit& mine) {
+  const uint32_t lane = lane_id();
+  const uint32_t take = vn < 64 ? vn : 64;
+  const bool have = lane < take;
+  if (have) mine = vb[lane];
+  const uint32_t rest = vn - take;
+  VUnit tmp{};
+  if (lane < rest) tmp = vb[take + lane];
+  if (lane < rest) vb[lane] = tmp;
+  vn = rest;
+  return have;
+}
+
+// ---------------------------------------------------------------------------
 // type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3)
 // ---------------------------------------------------------------------------
+struct Ring1 {
+  uint32_t qh, qt;   // items [qh, qt) are queued (logical indices)
+  uint32_t bc, bt;   // next Philox block to process / end of the queued blocks
+};
+
+// one converged step over up to 64 queued Philox blocks (two tests each)
+template <int D, int MODEL, bool T0, bool WRITE>
+__device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& v,
+                                      const QItem1* __restrict__ q, Ring1& r,
+                                      uint2* __restrict__ edges, uint64_t& running,
+                                      uint64_t& ntests) {
+  const uint32_t lane = lane_id();
+  const uint32_t avail = r.bt - r.bc;
+  const uint32_t take = avail < 64 ? avail : 64;
+  bool e0 = false, e1 = false;
+  uint2 p0 = make_uint2(0, 0), p1 = make_uint2(0, 0);
+  if (lane < take) {
+    const uint32_t gb = r.bc + lane;
+    // last queued item whose first block is <= gb
+    uint32_t lo = r.qh, hi = r.qt;
+    while (hi - lo > 1) {
+      const uint32_t mid = lo + (hi - lo) / 2;
+      if (q[mid & (kQCap - 1)].cs <= gb) lo = mid; else hi = mid;
+    }
+    const QItem1 it = q[lo & (kQCap - 1)];
+    const bool tri = it.tri != 0;
+    const uint64_t tot = tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
+    uint64_t k = 2ull * (gb - it.cs);
+    uint32_t a, b;
+    if (tri) {
+      uint32_t bb = (uint32_t)(0.5 * (1.0 + sqrt(1.0 + 8.0 * (double)k)));
+      while ((uint64_t)bb * (bb - 1) / 2 > k) --bb;
+      while ((uint64_t)(bb + 1) * bb / 2 <= k) ++bb;
+      b = bb;
+      a = (uint32_t)(k - (uint64_t)bb * (bb - 1) / 2);
+    } else {
+      a = (uint32_t)k / it.nb;
+      b = (uint32_t)k - a * it.nb;
+    }
+    type1_step<D, MODEL, T0, WRITE>(g, v, it.A, it.B, it.w3, it.a0, it.b0, it.nb, tri, a, b, k,
+                                    tot, e0, e1, p0, p1, ntests);
+  }
+  append2(WRITE, e0, e1, p0, p1, edges, running);
+  r.bc += take;
+  // retire the items whose blocks are all done
+  while (r.qh < r.qt) {
+    const uint32_t nxt = r.qh + 1 < r.qt ? q[(r.qh + 1) & (kQCap - 1)].cs : r.bt;
+    if (nxt > r.bc) break;
+    ++r.qh;
+  }
+}
+
 template <int D, int MODEL, bool T0, bool WRITE>
 __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
                                                const Src* __restrict__ src, Sched sc, PassOut po,
                                                DeferOut dfo) {
-  constexpr int NOFF = Offs<D>::n1;
+  __shared__ VUnit vbs[4][kVCap];
+  __shared__ QItem1 qs[4][kQCap];
+  const uint32_t wv = threadIdx.x / kWave;
+  VUnit* vb = vbs[wv];
+  QItem1* q = qs[wv];
   const uint32_t lane = lane_id();
   uint64_t ntests = 0;
   for (;;) {
@@ -284,75 +420,267 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
     const uint64_t ub = (uint64_t)c * sc.chunk;
     const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
     uint64_t u = ub + lane;
-    uint64_t jm = 0;
-    uint32_t A = 0, B = 0, a0 = 0, na = 0, lvl = 0, li = 0;
-    bool same = false, act = false, tri = false, big = false;
-    uint32_t b0 = 0, nb = 0, a = 0, b = 0, w3 = 0;
-    uint64_t k = 0, tot = 0;
-    ItemRec rec{};
+    uint32_t vn = 0, dseq = 0;
+    Ring1 r{0, 0, 0, 0};
     uint64_t running = WRITE ? po.add + po.base[c] : 0;
-    uint32_t dseq = 0;
     for (;;) {
-      while (!act && !big) {
-        if (jm == 0) {
-          if (u >= ue) break;
-          const uint64_t sidx = u / NOFF;
-          const uint32_t off = (uint32_t)(u - sidx * NOFF);
-          u += kWave;
-          const Src sr = src[sidx];
-          lvl = sr.meta & 255u;
-          li = sr.meta >> 8;
-          jm = g->jI[li][lvl];
-          if (!jm) continue;
-          A = sr.A;
-          if (!neighbour_cell<D>(A, lvl, off, &B) || B < A) { jm = 0; continue; }
-          same = (B == A);
-          if (same) jm &= ~((1ull << li) - 1ull);  // j >= i when A = B
-          a0 = sr.s;
-          na = sr.na;
-          continue;
-        }
-        const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
-        jm &= jm - 1;
-        cell_range(g, P, lj, lvl, B, &b0, &nb);
-        if (!nb) continue;
-        tri = same && lj == li;
-        if (tri) {
-          if (na < 2) continue;
-          tot = (uint64_t)na * (na - 1) / 2;
-          a = 0; b = 1;
-        } else {
-          tot = (uint64_t)na * nb;
-          a = 0; b = 0;
-        }
-        w3 = ctr_word3(lvl, li, lj, kKindType1, 0);
-        if (tot > kBigTests) {
-          rec = ItemRec{a0, na, b0, nb, A, B, lvl | (li << 8) | (lj << 16) | (tri ? 1u << 31 : 0u), 0u};
-          big = true;
-          continue;
-        }
-        k = 0;
-        act = true;
+      fill_units<D, false>(g, src, u, ue, vb, vn);
+      if (vn == 0) break;
+      VUnit mu{};
+      const bool have = take_unit(vb, vn, mu);
+      uint64_t jm = 0;
+      uint32_t A = 0, a0 = 0, na = 0, lvl = 0, li = 0;
+      if (have) {
+        const Src sr = src[mu.sidx];
+        lvl = sr.meta & 255u;
+        li = sr.meta >> 8;
+        A = sr.A;
+        a0 = sr.s;
+        na = sr.na;
+        jm = g->jI[li][lvl];
+        if (mu.B == A) jm &= ~((1ull << li) - 1ull);  // j >= i when A = B
       }
-      const bool anyb = __any(big);
-      if (!anyb && !__any(act)) break;
-      if (anyb) {
-        defer_item(WRITE, big, rec, c, dseq, dfo);
-        big = false;
+      while (__any(jm != 0)) {
+        // keep room for 64 more items; consume blocks when there is a full step of them
+        while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
+          step1<D, MODEL, T0, WRITE>(g, v, q, r, po.edges, running, ntests);
+        bool enq = false, big = false;
+        QItem1 it{};
+        ItemRec rec{};
+        uint32_t nblk = 0;
+        if (jm) {
+          const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
+          jm &= jm - 1;
+          uint32_t b0, nb;
+          cell_range(g, P, lj, lvl, mu.B, &b0, &nb);
+          const bool tri = mu.B == A && lj == li;
+          const uint64_t tot = tri ? (uint64_t)na * (na - 1) / 2 : (uint64_t)na * nb;
+          if (nb && tot) {
+            const uint32_t w3 = ctr_word3(lvl, li, lj, kKindType1, 0);
+            if (tot > kBigTests) {
+              rec = ItemRec{a0, na, b0, nb, A, mu.B, lvl | (li << 8) | (lj << 16) | (tri ? 1u << 31 : 0u), 0u};
+              big = true;
+            } else {
+              it = QItem1{A, mu.B, w3, a0, b0, nb, na, tri ? 1u : 0u, 0u};
+              nblk = (uint32_t)((tot + 1) / 2);
+              enq = true;
+            }
+          }
+        }
+        if (__any(big)) defer_item(WRITE, big, rec, c, dseq, dfo);
+        // enqueue with first-block indices from a wave prefix sum of the block counts
+        const uint64_t me = __ballot(enq);
+        uint32_t pre = nblk;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t t = __shfl_up(pre, o, 64);
+          if ((int)lane >= o) pre += t;
+        }
+        const uint32_t total = __shfl(pre, 63, 64);
+        if (enq) {
+          it.cs = r.bt + pre - nblk;
+          q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
+        }
+        r.qt += (uint32_t)__popcll(me);
+        r.bt += total;
       }
-      bool e0 = false, e1 = false;
-      uint2 p0 = make_uint2(0, 0), p1 = make_uint2(0, 0);
-      if (act) {
-        type1_step<D, MODEL, T0, WRITE>(g, v, A, B, w3, a0, b0, nb, tri, a, b, k, tot, e0, e1, p0, p1, ntests);
-        if (k >= tot) act = false;
-      }
-      append2(WRITE, e0, e1, p0, p1, po.edges, running);
     }
+    while (r.bc < r.bt) step1<D, MODEL, T0, WRITE>(g, v, q, r, po.edges, running, ntests);
     if (!WRITE && lane == 0) po.count[c] = running;
   }
   if (!WRITE) {
     ntests = wave_sum(ntests);
     if (lane == 0) atomicAdd(&po.stats[0], (unsigned long long)ntests);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// type-II pass: distant cell pairs with neighbouring parents at levels
+// l <= CL(i,j).  Candidates of V_i^A x V_j^B are drawn by geometric jumps
+// under pbar and accepted with p_uv / pbar (Sec. 3.2).  The candidate range is
+// cut into segments of G = 2^e (e = 5 - ilogb(pbar), raised to keep at most
+// 2^12 segments); segment s draws from counter (t, A, B, l|i|j|1|s).  Items
+// with one segment are sampled here, the others are deferred to the segment
+// kernel.
+// ---------------------------------------------------------------------------
+struct Ring2 {
+  uint32_t qh, qt;  // queued items
+  uint32_t ch, ct;  // queued candidates
+};
+
+// one geometric draw without the candidate test: advances k; returns true
+// and the candidate's sorted indices and Acc * pbar when there is one
+__device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, bool& done,
+                                         Cand& cd) {
+  const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
+  ++it.t;
+  const double S = u53_open(o.x, o.y);
+  const double q = it.pb >= 1.0 ? 0.0 : log(S) / it.lg;
+  if (q >= (double)(it.N - it.k)) {
+    done = true;
+    return false;
+  }
+  it.k += (uint32_t)q;
+  const uint32_t aa = it.k / it.nb;
+  const uint32_t bb = it.k - aa * it.nb;
+  cd.su = it.a0 + aa;
+  cd.sv = it.b0 + bb;
+  cd.apb = u53(o.z, o.w) * it.pb;
+  ++it.k;
+  done = it.k >= it.N;
+  return true;
+}
+
+// evaluate up to 64 queued candidates (accept iff Acc * pbar < p_uv)
+template <int D, int MODEL, bool WRITE>
+__device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Verts& v,
+                                           const Cand* __restrict__ cq, Ring2& r,
+                                           uint2* __restrict__ edges, uint64_t& running) {
+  const uint32_t lane = lane_id();
+  const uint32_t avail = r.ct - r.ch;
+  const uint32_t take = avail < 64 ? avail : 64;
+  bool e0 = false;
+  uint2 p0 = make_uint2(0, 0);
+  if (lane < take) {
+    const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
+    e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
+    if (WRITE && e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
+  }
+  append2(WRITE, e0, false, p0, p0, edges, running);
+  r.ch += take;
+}
+
+// draw steps: lanes own items (dequeued from the ring), one draw per step;
+// runs while at least `need` items are queued or held, or to the end if
+// need == 0
+template <int D, int MODEL, bool WRITE>
+__device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts& v,
+                                       const QItem2* __restrict__ q, Cand* __restrict__ cq,
+                                       Ring2& r, bool& act, QItem2& it, uint32_t need,
+                                       uint2* __restrict__ edges, uint64_t& running,
+                                       uint64_t& ndraws, uint64_t& ncand) {
+  const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
+  for (;;) {
+    const uint64_t mi = __ballot(!act);
+    const uint32_t avail = r.qt - r.qh;
+    const uint32_t held = 64u - (uint32_t)__popcll(mi);
+    if (need && held + avail < need) break;
+    if (!act) {
+      const uint32_t rk = lanes_below(mi);
+      if (rk < avail) {
+        it = q[(r.qh + rk) & (kQCap - 1)];
+        act = true;
+      }
+    }
+    const uint32_t got = (uint32_t)__popcll(mi);
+    r.qh += got < avail ? got : avail;
+    if (!__any(act)) break;
+    bool hc = false;
+    Cand cd{0, 0, 0.0};
+    if (act) {
+      bool done = false;
+      hc = geo_draw(k0s, k1s, it, done, cd);
+      ++ndraws;
+      if (done) act = false;
+    }
+    const uint64_t mc = __ballot(hc);
+    if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
+    r.ct += (uint32_t)__popcll(mc);
+    ncand += hc ? 1 : 0;
+    if (r.ct - r.ch >= 64) eval_cands<D, MODEL, WRITE>(g, v, cq, r, edges, running);
+  }
+}
+
+template <int D, int MODEL, bool WRITE>
+__global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
+                                               const uint32_t* __restrict__ P,
+                                               const Src* __restrict__ src, Sched sc,
+                                               const Pbar* __restrict__ pbt, int nlev, PassOut po,
+                                               DeferOut dfo) {
+  __shared__ VUnit vbs[4][kVCap];
+  __shared__ QItem2 qs[4][kQCap];
+  __shared__ Cand cqs[4][kCCap];
+  const uint32_t wv = threadIdx.x / kWave;
+  VUnit* vb = vbs[wv];
+  QItem2* q = qs[wv];
+  Cand* cq = cqs[wv];
+  const uint32_t lane = lane_id();
+  const int L = g->L;
+  uint64_t ndraws = 0, ncand = 0;
+  for (;;) {
+    const uint32_t c = next_chunk(sc.next);
+    if (c >= sc.nchunks) break;
+    const uint64_t ub = (uint64_t)c * sc.chunk;
+    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
+    uint64_t u = ub + lane;
+    uint32_t vn = 0, dseq = 0;
+    Ring2 r{0, 0, 0, 0};
+    bool act = false;
+    QItem2 cur{};
+    uint64_t running = WRITE ? po.add + po.base[c] : 0;
+    for (;;) {
+      fill_units<D, true>(g, src, u, ue, vb, vn);
+      if (vn == 0) break;
+      VUnit mu{};
+      const bool have = take_unit(vb, vn, mu);
+      uint64_t jm = 0;
+      uint32_t A = 0, a0 = 0, na = 0, lvl = 0, li = 0;
+      if (have) {
+        const Src sr = src[mu.sidx];
+        lvl = sr.meta & 255u;
+        li = sr.meta >> 8;
+        A = sr.A;
+        a0 = sr.s;
+        na = sr.na;
+        jm = g->jII[li][lvl];
+      }
+      const uint32_t gp = mu.gap;
+      while (__any(jm != 0)) {
+        if (r.qt - r.qh > (uint32_t)(kQCap - 64))
+          draws2<D, MODEL, WRITE>(g, v, q, cq, r, act, cur, 64, po.edges, running, ndraws, ncand);
+        bool enq = false, hv = false;
+        QItem2 it{};
+        ItemRec rec{};
+        if (jm) {
+          const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
+          jm &= jm - 1;
+          uint32_t b0, nb;
+          cell_range(g, P, lj, lvl, mu.B, &b0, &nb);
+          if (nb) {
+            const Pbar pe = pbt[(((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1)];
+            if (pe.pbar > 0.0) {
+              const uint64_t N = (uint64_t)na * nb;
+              uint64_t G, nseg;
+              segment_size(N, pe.e, &G, &nseg);
+              if (nseg > 1 || N >= 0xFFFFFFFFull) {
+                rec = ItemRec{a0, na, b0, nb, A, mu.B,
+                              lvl | (li << 8) | (lj << 16) | (gp << 24), (uint32_t)pe.e};
+                hv = true;
+              } else {
+                it = QItem2{A, mu.B, ctr_word3(lvl, li, lj, kKindType2, 0), a0, b0, nb, 0u, 0u,
+                            (uint32_t)N, 0u, pe.pbar, pe.lg};
+                enq = true;
+              }
+            }
+          }
+        }
+        if (__any(hv)) defer_item(WRITE, hv, rec, c, dseq, dfo);
+        const uint64_t me = __ballot(enq);
+        if (enq) q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
+        r.qt += (uint32_t)__popcll(me);
+      }
+    }
+    draws2<D, MODEL, WRITE>(g, v, q, cq, r, act, cur, 0, po.edges, running, ndraws, ncand);
+    while (r.ct != r.ch) eval_cands<D, MODEL, WRITE>(g, v, cq, r, po.edges, running);
+    if (!WRITE && lane == 0) po.count[c] = running;
+  }
+  if (!WRITE) {
+    ndraws = wave_sum(ndraws);
+    ncand = wave_sum(ncand);
+    if (lane == 0) {
+      atomicAdd(&po.stats[1], (unsigned long long)ndraws);
+      atomicAdd(&po.stats[2], (unsigned long long)ncand);
+    }
   }
 }
 
@@ -416,111 +744,6 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
   if (!WRITE) {
     ntests = wave_sum(ntests);
     if (lane == 0) atomicAdd(&po.stats[0], (unsigned long long)ntests);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// type-II pass: distant cell pairs with neighbouring parents at levels
-// l <= CL(i,j).  Candidates of V_i^A x V_j^B are drawn by geometric jumps
-// under pbar and accepted with p_uv / pbar (Sec. 3.2).  The candidate range is
-// cut into segments of G = 2^e (e = 5 - ilogb(pbar), raised to keep at most
-// 2^12 segments); segment s draws from counter (t, A, B, l|i|j|1|s).  Items
-// with one segment are sampled here, the others are deferred.
-// ---------------------------------------------------------------------------
-template <int D, int MODEL, bool WRITE>
-__global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
-                                               const uint32_t* __restrict__ P,
-                                               const Src* __restrict__ src, Sched sc,
-                                               const Pbar* __restrict__ pbt, int nlev, PassOut po,
-                                               DeferOut dfo) {
-  constexpr int NOFF = Offs<D>::n2;
-  const uint32_t lane = lane_id();
-  const int L = g->L;
-  uint64_t ndraws = 0, ncand = 0;
-  for (;;) {
-    const uint32_t c = next_chunk(sc.next);
-    if (c >= sc.nchunks) break;
-    const uint64_t ub = (uint64_t)c * sc.chunk;
-    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
-    uint64_t u = ub + lane;
-    uint64_t jm = 0;
-    uint32_t A = 0, B = 0, a0 = 0, na = 0, lvl = 0, li = 0;
-    int gap = 1;
-    bool act = false, hv = false;
-    uint32_t b0 = 0, nb = 0, t = 0, w3 = 0;
-    uint64_t k = 0, N = 0;
-    double pb = 0.0, lg = 0.0;
-    ItemRec rec{};
-    uint64_t running = WRITE ? po.add + po.base[c] : 0;
-    uint32_t dseq = 0;
-    for (;;) {
-      while (!act && !hv) {
-        if (jm == 0) {
-          if (u >= ue) break;
-          const uint64_t sidx = u / NOFF;
-          const uint32_t off = (uint32_t)(u - sidx * NOFF);
-          u += kWave;
-          const Src sr = src[sidx];
-          lvl = sr.meta & 255u;
-          li = sr.meta >> 8;
-          jm = g->jII[li][lvl];
-          if (!jm) continue;
-          A = sr.A;
-          if (!distant_cell<D>(A, lvl, off, &B, &gap) || B < A) { jm = 0; continue; }
-          a0 = sr.s;
-          na = sr.na;
-          continue;
-        }
-        const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
-        jm &= jm - 1;
-        cell_range(g, P, lj, lvl, B, &b0, &nb);
-        if (!nb) continue;
-        const Pbar pe = pbt[(((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gap - 1)];
-        if (!(pe.pbar > 0.0)) continue;
-        N = (uint64_t)na * nb;
-        uint64_t G, nseg;
-        segment_size(N, pe.e, &G, &nseg);
-        if (nseg > 1) {
-          rec = ItemRec{a0, na, b0, nb, A, B, lvl | (li << 8) | (lj << 16) | ((uint32_t)gap << 24),
-                        (uint32_t)pe.e};
-          hv = true;
-          continue;
-        }
-        pb = pe.pbar;
-        lg = pe.lg;
-        w3 = ctr_word3(lvl, li, lj, kKindType2, 0);
-        k = 0;
-        t = 0;
-        act = true;
-      }
-      const bool anyh = __any(hv);
-      if (!anyh && !__any(act)) break;
-      if (anyh) {
-        defer_item(WRITE, hv, rec, c, dseq, dfo);
-        hv = false;
-      }
-      bool e0 = false;
-      uint2 p0 = make_uint2(0, 0);
-      if (act) {
-        uint32_t su, sv;
-        bool done;
-        e0 = type2_draw<D, MODEL>(g, v, A, B, w3, t, pb, lg, a0, b0, nb, k, N, done, su, sv, ncand);
-        ++t;
-        ++ndraws;
-        if (WRITE && e0) p0 = make_uint2(v.id[su], v.id[sv]);
-        if (done) act = false;
-      }
-      append2(WRITE, e0, false, p0, p0, po.edges, running);
-    }
-    if (!WRITE && lane == 0) po.count[c] = running;
-  }
-  if (!WRITE) {
-    ndraws = wave_sum(ndraws);
-    ncand = wave_sum(ncand);
-    if (lane == 0) {
-      atomicAdd(&po.stats[1], (unsigned long long)ndraws);
-      atomicAdd(&po.stats[2], (unsigned long long)ncand);
-    }
   }
 }
 
