@@ -49,14 +49,6 @@ OPS_DRAW = 80.0         # geometric draw: one Philox block, one log, divide, com
 OPS_CAND = 70.0         # candidate: distance, pow, compare
 
 
-def _stage_ops(stage: str, info: dict, T: float) -> float | None:
-    if stage.startswith("type1"):
-        return info["tests"] * (OPS_TEST_T0 if T == 0.0 else OPS_TEST_BINOM)
-    if stage.startswith("type2") or stage.startswith("heavy"):
-        return None  # draws of a pass are split between type-II and heavy kernels
-    return None
-
-
 def make_call(hg, wl: dict):
     L = hg.load()
     if wl["model"] == 1:
@@ -157,20 +149,22 @@ def main() -> int:
         print(f"[bench]   {k:>14s} {v:9.4f} ms", file=sys.stderr)
     print(f"[bench] info {info_d}", file=sys.stderr)
 
-    # dominant kernel and its roofline (VALU-bound: lane-operations)
-    kernel_stages = {k: v for k, v in stages.items() if k.startswith(("type1", "type2", "heavy"))}
-    dom = max(kernel_stages, key=kernel_stages.get) if kernel_stages else max(stages, key=stages.get)
+    # dominant sampling kernel and its roofline (VALU-bound: lane-operations)
+    kernel_pass = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
+    kstages = {k: v for k, v in stages.items() if k in kernel_pass}
+    dom = max(kstages, key=kstages.get)
     dom_ms = stages[dom]
-    if dom.startswith("type1"):
-        ops = info_d["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
+    q = kernel_pass[dom]
+    if q < 2:
+        units = {"tests": info_d["pass_work"][q]}
+        ops = units["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
     else:
-        # type-II count and write passes each repeat all light draws; the
-        # heavy kernel's share is reported within the same counters
-        ops = info_d["draws"] * OPS_DRAW + info_d["candidates"] * OPS_CAND
+        units = {"draws": info_d["pass_work"][q], "candidates": info_d["pass_cands"][q]}
+        ops = units["draws"] * OPS_DRAW + units["candidates"] * OPS_CAND
     achieved = ops / (dom_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS,
             "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-            "launch_ms": dom_ms}
+            "launch_ms": dom_ms, "units_per_launch": units}
     value = edges / dt
     out = {
         "metric": METRIC,

@@ -83,10 +83,15 @@ typedef struct {
   uint64_t rechecks;     /* mixed precision: decisions re-done in FP64 */
   uint64_t sources;      /* (layer, level, cell) runs */
   uint64_t heavy_items;  /* type-II items split into segments */
+  uint64_t split_items;  /* type-I items split into pieces of tests */
   uint64_t cells;        /* prefix-sum entries */
   double c, W, R;        /* constants used */
   int32_t L, D;          /* layers, deepest level */
   int32_t reserved[2];
+  /* per sampling pass (0 type-I, 1 split type-I items, 2 type-II, 3
+   * segmented type-II items): edges, work units (tests for 0-1, draws for
+   * 2-3) and type-II candidates */
+  uint64_t pass_edges[4], pass_work[4], pass_cands[4];
 } girg_info;
 
 /* girg_generate: points (Sec. 2.1 weights and positions), constant c

@@ -50,14 +50,22 @@ class Info(ctypes.Structure):
         ("m", ctypes.c_uint64), ("type1_edges", ctypes.c_uint64), ("type2_edges", ctypes.c_uint64),
         ("tests", ctypes.c_uint64), ("draws", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
         ("rechecks", ctypes.c_uint64), ("sources", ctypes.c_uint64),
-        ("heavy_items", ctypes.c_uint64), ("cells", ctypes.c_uint64), ("c", ctypes.c_double),
+        ("heavy_items", ctypes.c_uint64), ("split_items", ctypes.c_uint64),
+        ("cells", ctypes.c_uint64), ("c", ctypes.c_double),
         ("W", ctypes.c_double), ("R", ctypes.c_double), ("L", ctypes.c_int32),
         ("D", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+        ("pass_edges", ctypes.c_uint64 * 4), ("pass_work", ctypes.c_uint64 * 4),
+        ("pass_cands", ctypes.c_uint64 * 4),
     ]
 
     def as_dict(self) -> dict:
-        return {k: (getattr(self, k) if k != "reserved" else None) for k, _ in self._fields_
-                if k != "reserved"}
+        out = {}
+        for k, _ in self._fields_:
+            if k == "reserved":
+                continue
+            val = getattr(self, k)
+            out[k] = list(val) if k.startswith("pass_") else val
+        return out
 
 
 _lib = None

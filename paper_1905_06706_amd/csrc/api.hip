@@ -82,7 +82,7 @@ struct Ctx {
   Graph* gd = nullptr;       // device Graph
   double* red = nullptr;     // 6 doubles
   uint32_t* flag = nullptr;
-  unsigned long long* stats = nullptr;  // 8
+  unsigned long long* stats = nullptr;  // 16
   unsigned int* hcount = nullptr;
   std::mutex mu;
   // stage timing (HIP events on the call's stream), enabled by girg_set_profiling
@@ -141,7 +141,7 @@ static girg_status get_ctx(Ctx** out) {
   HIPCHK(hipMalloc(&c->gd, sizeof(Graph)));
   HIPCHK(hipMalloc(&c->red, 8 * sizeof(double)));
   HIPCHK(hipMalloc(&c->flag, sizeof(uint32_t)));
-  HIPCHK(hipMalloc(&c->stats, 8 * sizeof(unsigned long long)));
+  HIPCHK(hipMalloc(&c->stats, 16 * sizeof(unsigned long long)));
   HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
   *out = c.get();
   g_ctx[dev] = std::move(c);
@@ -171,13 +171,17 @@ struct CSolve {
   double wcut;             // every weight not in h is <= wcut
   bool incomplete = false;
 
+  std::vector<double> hp;  // h^(1/T)
+
+  // h must already be in descending order
   void prepare() {
-    std::sort(h.begin(), h.end(), [](double a, double b) { return a > b; });
     pw.assign(h.size() + 1, 0.0);
     pp.assign(h.size() + 1, 0.0);
+    hp.assign(h.size(), 0.0);
     for (size_t i = 0; i < h.size(); ++i) {
+      hp[i] = T > 0.0 ? std::pow(h[i], 1.0 / T) : 0.0;
       pw[i + 1] = pw[i] + h[i];
-      pp[i + 1] = pp[i] + (T > 0.0 ? std::pow(h[i], 1.0 / T) : 0.0);
+      pp[i + 1] = pp[i] + hp[i];
     }
   }
 
@@ -193,6 +197,7 @@ struct CSolve {
     } else {
       A = std::ldexp(std::pow(c, (double)d), d);
     }
+    const double WT = T > 0.0 ? std::pow(W, 1.0 / T) : 1.0;
     double err = 0.0;
     size_t m = h.size();
     for (size_t u = 0; u < h.size(); ++u) {
@@ -204,27 +209,47 @@ struct CSolve {
       const double cntv = (double)m - (self ? 1.0 : 0.0);
       double term = A * (wu / W) * sw - cntv;
       if (T > 0.0) {
-        const double sp = pp[m] - (self ? std::pow(wu, 1.0 / T) : 0.0);
-        term -= B * std::pow(wu / W, 1.0 / T) * sp;
+        const double sp = pp[m] - (self ? hp[u] : 0.0);
+        term -= B * (hp[u] / WT) * sp;
       }
       err += term;
     }
     return (A * s1 - B * s2 - err) / (double)n;
   }
 
-  // bracket by doubling / halving, then bisection on log c down to adjacent doubles
+  // bracket by doubling / halving, then regula falsi (Illinois) on log c
+  // until the bracket is a few ulps wide; returns its upper end
   int solve(double target, double* out) {
     double lo = 1.0, hi = 1.0;
+    double flo = f(1.0) - target, fhi = flo;
     int it = 0;
-    if (f(1.0) < target) {
-      while (f(hi) < target) { lo = hi; hi *= 2.0; if (++it > 2000) return -1; }
+    if (flo < 0.0) {
+      while (fhi < 0.0) { lo = hi; flo = fhi; hi *= 2.0; fhi = f(hi) - target; if (++it > 2000) return -1; }
     } else {
-      while (!(f(lo) < target)) { hi = lo; lo *= 0.5; if (++it > 2000) return -1; }
+      while (!(flo < 0.0)) { hi = lo; fhi = flo; lo *= 0.5; flo = f(lo) - target; if (++it > 2000) return -1; }
     }
-    for (it = 0; it < 300; ++it) {
-      const double mid = std::exp(0.5 * (std::log(lo) + std::log(hi)));
-      if (!(mid > lo && mid < hi)) break;
-      if (f(mid) < target) lo = mid; else hi = mid;
+    double a = std::log(lo), b = std::log(hi);
+    int side = 0;
+    for (it = 0; it < 200; ++it) {
+      if (!(hi > lo) || hi - lo <= 4.0 * std::ldexp(hi, -52)) break;
+      double x = (fhi == flo) ? 0.5 * (a + b) : b - fhi * (b - a) / (fhi - flo);
+      if (!(x > a && x < b)) x = 0.5 * (a + b);
+      double c = std::exp(x);
+      if (!(c > lo && c < hi)) {
+        c = lo + 0.5 * (hi - lo);
+        x = std::log(c);
+        if (!(c > lo && c < hi)) break;
+      }
+      const double fc = f(c) - target;
+      if (fc < 0.0) {
+        lo = c; a = x; flo = fc;
+        if (side == -1) fhi *= 0.5;
+        side = -1;
+      } else {
+        hi = c; b = x; fhi = fc;
+        if (side == 1) flo *= 0.5;
+        side = 1;
+      }
     }
     *out = hi;
     return 0;
@@ -524,10 +549,20 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
       uint64_t tail = 0;
       while (i0 > 0 && tail < 4096) { --i0; tail += (uint64_t)g.count[i0]; }
       for (;;) {
-        cs.h.resize(n - g.lstart[i0]);
-        HIPCHK(hipMemcpyAsync(cs.h.data(), sw + g.lstart[i0], cs.h.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
+        // the tail of the layer-sorted weights, sorted by value on the device
+        const uint64_t K = n - g.lstart[i0];
+        Arena::Mark mk = ar.mark();
+        uint64_t* tk = ar.get<uint64_t>(K);
+        uint32_t* tv = ar.get<uint32_t>(K);
+        if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
+        HIPCHK(hipMemcpyAsync(tk, sw + g.lstart[i0], K * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(launch_iota(tv, K, st));
+        HIPCHK(radix_sort(ar, tk, tv, K, 64, st));  // positive doubles order as integers
+        std::vector<double> asc(K);
+        HIPCHK(hipMemcpyAsync(asc.data(), tk, K * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        ar.reset(mk);
+        cs.h.assign(asc.rbegin(), asc.rend());
         cs.wcut = 0.0;
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
@@ -597,31 +632,32 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint64_t n1 = 1, n2 = 1;
   for (int k = 0; k < d; ++k) { n1 *= 3; n2 *= 6; }
 
-  // pass bookkeeping: 0 type-I, 1 split type-I, 2 type-II, 3 segmented type-II
+  // staging of the edges: capacity = the caller's; flush records
   unsigned int* tickets = ar.get<unsigned int>(8);
   unsigned int* dcount = ar.get<unsigned int>(2);
-  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (tickets)");
-  HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));
-  HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
-  auto make_sched = [&](uint64_t nunits, int slot) {
+  unsigned int* nrec_d = ar.get<unsigned int>(1);
+  unsigned long long* cursor = ar.get<unsigned long long>(1);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (counters)");
+  auto make_sched = [&](uint64_t nunits, int pass) {
     uint64_t ch = (nunits + 16383) / 16384;
     ch = ((ch + 63) / 64) * 64;
     ch = std::max<uint64_t>(64, std::min<uint64_t>(4096, ch));
-    Sched sc{tickets + slot, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch)};
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
     return sc;
   };
-  Sched sch[4];
-  uint64_t* pcnt[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool live[4] = {false, false, false, false};
-  sch[0] = make_sched(nsrc ? nsrc * n1 : 0, 0);
-  sch[2] = make_sched(binomial && nsrc ? nsrc * n2 : 0, 2);
-  for (int q : {0, 2}) {
-    live[q] = sch[q].nchunks > 0;
-    pcnt[q] = ar.get<uint64_t>(sch[q].nchunks + 1);
-  }
-  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (chunk counts)");
+  Sched sch[4] = {make_sched(nsrc ? nsrc * n1 : 0, 0), make_sched(0, 1),
+                  make_sched(binomial && nsrc ? nsrc * n2 : 0, 2), make_sched(0, 3)};
+  uint2* stage = cap ? ar.get<uint2>(cap) : nullptr;
+  // every flush but the last of a chunk holds more than 128 edges
+  const uint64_t rcap64 = cap / 128 + 2ull * (sch[0].nchunks + sch[2].nchunks) + (1u << 16);
+  const uint32_t rcap = (uint32_t)std::min<uint64_t>(rcap64, 0xFFFFFFF0ull);
+  uint64_t* rkey = ar.get<uint64_t>(rcap);
+  uint64_t* rpos = ar.get<uint64_t>(rcap);
+  uint32_t* rcnt = ar.get<uint32_t>(rcap);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge staging)");
+  Stage sg{stage, cap, cursor, rkey, rpos, rcnt, nrec_d, rcap, cx.stats};
 
-  // count passes with deferred lists (grown once if too small)
+  // type-I and type-II passes (deferred lists grown once if too small)
   uint32_t dcap[2] = {(uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024),
                       (uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024)};
   ItemRec* drec[2] = {nullptr, nullptr};
@@ -636,16 +672,16 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
     HIPCHK(hipMemsetAsync(dcount, 0, 2 * sizeof(unsigned int), st));
     HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));
-    HIPCHK(hipMemsetAsync(cx.stats, 0, 8 * sizeof(unsigned long long), st));
-    PassOut po0{pcnt[0], nullptr, 0, nullptr, cx.stats};
-    PassOut po2{pcnt[2], nullptr, 0, nullptr, cx.stats};
+    HIPCHK(hipMemsetAsync(nrec_d, 0, sizeof(unsigned int), st));
+    HIPCHK(hipMemsetAsync(cursor, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(cx.stats, 0, 16 * sizeof(unsigned long long), st));
     DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
     DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
     cx.mark("-", st);
-    if (live[0]) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], false, po0, df0, st));
-    cx.mark("type1_count", st);
-    if (live[2]) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, false, po2, df1, st));
-    cx.mark("type2_count", st);
+    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], sg, df0, st));
+    cx.mark("type1", st);
+    if (sch[2].nchunks) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, sg, df1, st));
+    cx.mark("type2", st);
     HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (dn[0] <= dcap[0] && dn[1] <= dcap[1]) break;
@@ -655,96 +691,86 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     dcap[1] = std::max(dcap[1], dn[1]);
   }
 
-  // deferred items in a deterministic order, their units and count passes
-  ItemRec* dsorted[2] = {nullptr, nullptr};
-  uint64_t* uoff[2] = {nullptr, nullptr};
+  // deferred items in a deterministic order, then their passes
   for (int q = 0; q < 2; ++q) {
     const uint32_t nd = dn[q];
     if (!nd) continue;
     uint32_t* perm = ar.get<uint32_t>(nd);
     uint64_t* kt = ar.get<uint64_t>(nd);
-    dsorted[q] = ar.get<ItemRec>(nd);
-    uoff[q] = ar.get<uint64_t>(nd + 1);
+    ItemRec* dsorted = ar.get<ItemRec>(nd);
+    uint64_t* uoff = ar.get<uint64_t>(nd + 1);
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred sort)");
     cx.mark("-", st);
     HIPCHK(launch_iota(perm, nd, st));
     HIPCHK(hipMemcpyAsync(kt, dkey[q], nd * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     HIPCHK(radix_sort(ar, kt, perm, nd, 48, st));
-    HIPCHK(launch_rec_gather(drec[q], perm, nd, dsorted[q], st));
-    HIPCHK(launch_rec_units(dsorted[q], nd, q == 0 ? 1 : 2, uoff[q], st));
-    HIPCHK(scan_u64(ar, uoff[q], uoff[q], nd, uoff[q] + nd, st));
+    HIPCHK(launch_rec_gather(drec[q], perm, nd, dsorted, st));
+    HIPCHK(launch_rec_units(dsorted, nd, q == 0 ? 1 : 2, uoff, st));
+    HIPCHK(scan_u64(ar, uoff, uoff, nd, uoff + nd, st));
     uint64_t nunits = 0;
-    HIPCHK(hipMemcpyAsync(&nunits, uoff[q] + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&nunits, uoff + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     cx.mark(q == 0 ? "split_prep" : "segment_prep", st);
-    const int pq = q == 0 ? 1 : 3;
-    sch[pq] = make_sched(nunits, pq);
-    live[pq] = sch[pq].nchunks > 0;
-    pcnt[pq] = ar.get<uint64_t>(sch[pq].nchunks + 1);
-    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (chunk counts)");
-    PassOut pc{pcnt[pq], nullptr, 0, nullptr, cx.stats};
     if (q == 0) {
-      HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], nd, sch[1], false, pc, st));
-      cx.mark("split1_count", st);
+      sch[1] = make_sched(nunits, 1);
+      if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted, uoff, nd, sch[1], sg, st));
+      cx.mark("split1", st);
     } else {
-      HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], nd, sch[3], pbt, nlev, false, pc, st));
-      cx.mark("heavy2_count", st);
+      sch[3] = make_sched(nunits, 3);
+      if (sch[3].nchunks)
+        HIPCHK(launch_heavy2(g, cx.gd, v, dsorted, uoff, nd, sch[3], pbt, nlev, sg, st));
+      cx.mark("segments2", st);
     }
   }
 
-  // chunk offsets within each pass, pass offsets, total
-  uint64_t ptot[4] = {0, 0, 0, 0};
-  cx.mark("-", st);
-  for (int q = 0; q < 4; ++q) {
-    if (!live[q]) continue;
-    HIPCHK(scan_u64(ar, pcnt[q], pcnt[q], sch[q].nchunks, pcnt[q] + sch[q].nchunks, st));
-  }
-  for (int q = 0; q < 4; ++q)
-    if (live[q])
-      HIPCHK(hipMemcpyAsync(&ptot[q], pcnt[q] + sch[q].nchunks, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  // total, capacity, records
+  unsigned long long mtot = 0;
+  unsigned int nrec = 0;
+  HIPCHK(hipMemcpyAsync(&mtot, cursor, sizeof(mtot), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&nrec, nrec_d, sizeof(nrec), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  cx.mark("offsets", st);
-  const uint64_t padd[4] = {0, ptot[0], ptot[0] + ptot[1], ptot[0] + ptot[1] + ptot[2]};
-  const uint64_t mtot = ptot[0] + ptot[1] + ptot[2] + ptot[3];
   *m_out = mtot;
-  if (info) {
-    info->m = mtot;
-    info->type1_edges = ptot[0] + ptot[1];
-    info->type2_edges = ptot[2] + ptot[3];
-  }
+  if (info) info->m = mtot;
   if (mtot > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
+  if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
 
-  // write passes
-  uint2* out = reinterpret_cast<uint2*>(edges);
-  DeferOut none{nullptr, nullptr, dcount, 0};
-  PassOut pw[4];
-  for (int q = 0; q < 4; ++q) pw[q] = PassOut{nullptr, pcnt[q], padd[q], out, cx.stats};
-  HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));  // fresh tickets for the write passes
-  cx.mark("-", st);
-  if (live[0]) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], true, pw[0], none, st));
-  cx.mark("type1_write", st);
-  if (live[1]) {
-    HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], true, pw[1], st));
-    cx.mark("split1_write", st);
-  }
-  if (live[2]) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, true, pw[2], none, st));
-  cx.mark("type2_write", st);
-  if (live[3]) {
-    HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], dn[1], sch[3], pbt, nlev, true, pw[3], st));
-    cx.mark("heavy2_write", st);
+  // staged blocks in (pass, chunk, flush) order
+  if (nrec) {
+    uint32_t* perm = ar.get<uint32_t>(nrec);
+    uint64_t* kt = ar.get<uint64_t>(nrec);
+    uint64_t* off = ar.get<uint64_t>(nrec + 1);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge order)");
+    cx.mark("-", st);
+    HIPCHK(launch_iota(perm, nrec, st));
+    HIPCHK(hipMemcpyAsync(kt, rkey, nrec * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(radix_sort(ar, kt, perm, nrec, 64, st));
+    HIPCHK(launch_stage_counts(rcnt, perm, nrec, off, st));
+    HIPCHK(scan_u64(ar, off, off, nrec, off + nrec, st));
+    HIPCHK(launch_stage_copy(stage, rpos, rcnt, perm, off, nrec, reinterpret_cast<uint2*>(edges), st));
+    cx.mark("order", st);
   }
 
-  unsigned long long stt[8];
+  unsigned long long stt[16];
   HIPCHK(hipMemcpyAsync(stt, cx.stats, sizeof(stt), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   cx.collect();
   if (info) {
-    info->tests = stt[0];
-    info->draws = stt[1];
-    info->candidates = stt[2];
-    info->rechecks = stt[3];
+    for (int q = 0; q < 4; ++q) info->pass_edges[q] = stt[8 + q];
+    info->pass_work[0] = stt[0];
+    info->pass_work[1] = stt[1];
+    info->pass_work[2] = stt[2];
+    info->pass_work[3] = stt[3];
+    info->pass_cands[2] = stt[4];
+    info->pass_cands[3] = stt[5];
+    info->type1_edges = stt[8] + stt[9];
+    info->type2_edges = stt[10] + stt[11];
+    info->tests = stt[0] + stt[1];
+    info->draws = stt[2] + stt[3];
+    info->candidates = stt[4] + stt[5];
+    info->rechecks = stt[6];
     info->sources = nsrc;
     info->heavy_items = dn[1];
+    info->split_items = dn[0];
     info->cells = cells;
     info->c = g.c;
     info->W = g.W;
@@ -949,6 +975,7 @@ girg_status girg_solve_c(const double* w_host, uint64_t n, int32_t d, double T, 
   cs.s1 = cs.W - (double)q1;
   cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
   cs.h.assign(w_host, w_host + n);
+  std::sort(cs.h.begin(), cs.h.end(), [](double a, double b) { return a > b; });
   cs.wcut = 0.0;
   cs.prepare();
   if (cs.solve(avg_deg, c_out) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
@@ -973,6 +1000,7 @@ girg_status girg_expected_degree(const double* w_host, uint64_t n, int32_t d, do
   cs.s1 = cs.W - (double)q1;
   cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
   cs.h.assign(w_host, w_host + n);
+  std::sort(cs.h.begin(), cs.h.end(), [](double a, double b) { return a > b; });
   cs.wcut = 0.0;
   cs.prepare();
   *deg_out = cs.f(c);

@@ -2,18 +2,23 @@
 // (arXiv:1905.06706, Sec. 3): fused cell-pair enumeration and sampling for
 // type-I (neighbouring cells, every pair tested) and type-II (distant cells,
 // geometric jumps under pbar, then rejection) cell pairs, plus the kernels for
-// items deferred because they are large.
+// items split because they are large.
 //
 // Work decomposition.  The unit of work is (run source, cell offset).  Waves
-// take chunks of consecutive units by atomic ticket (persistent grid); inside
-// a chunk the 64 lanes take interleaved units and each runs a small state
-// machine: fetch the next non-empty item (layer pair x cell pair), then one
-// test (type-I: two per Philox block) or one geometric draw (type-II) per
-// step.  The step loop is converged across the wave, so each step ends in a
-// ballot that appends the accepted edges in a fixed order.  A count pass
-// stores the edge count of every chunk; a scan gives each chunk its offset;
-// the write pass repeats the work and stores the edges.  The edge array is a
-// pure function of the inputs and the seed, whatever wave ran which chunk.
+// take chunks of consecutive units by atomic ticket (persistent grid).  Inside
+// a chunk a wave runs converged phases over small per-wave LDS buffers:
+//   A  lanes decode units and append the valid (run, cell B) pairs;
+//   B  lanes take 64 pairs and walk their layers j; non-empty items go to an
+//      item ring (large ones to a deferred list);
+//   C  type-I: 64 Philox blocks (two tests each) per step, flat across the
+//      queued items; type-II: lanes own one item each and draw once per step,
+//      candidates go to a ring that is evaluated 64 at a time.
+// Accepted edges are appended (wave ballots) to an LDS buffer that is flushed
+// in blocks of at least 128 edges to a staging array at an atomically reserved
+// position, with a record (pass, chunk, flush number) -> position.  Sorting
+// the records and copying the blocks in that order gives an edge array that
+// is a pure function of the inputs and the seed, whatever wave ran which
+// chunk, in one sampling pass.
 #include "sampler.h"
 
 namespace hg {
@@ -22,6 +27,12 @@ __device__ __forceinline__ uint32_t next_chunk(unsigned int* next) {
   uint32_t c = 0;
   if (lane_id() == 0) c = atomicAdd(next, 1u);
   return __builtin_amdgcn_readfirstlane(c);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -161,123 +172,64 @@ __device__ __forceinline__ void segment_size(uint64_t N, int e, uint64_t* G, uin
   *nseg = (N + *G - 1) / *G;
 }
 
-// one geometric draw of an item / segment; returns true when an edge is accepted
-template <int D, int MODEL>
-__device__ __forceinline__ bool type2_draw(const Graph* __restrict__ g, const Verts& v,
-                                           uint32_t A, uint32_t B, uint32_t w3, uint32_t t,
-                                           double pb, double lg, uint32_t a0, uint32_t b0,
-                                           uint32_t nb, uint64_t& k, uint64_t kend, bool& done,
-                                           uint32_t& su, uint32_t& sv, uint64_t& ncand) {
-  const U4 o = philox(t, A, B, w3, g->seed_lo, g->seed_hi);
-  const double S = u53_open(o.x, o.y);
-  const double q = pb >= 1.0 ? 0.0 : log(S) / lg;
-  if (q >= (double)(kend - k)) {
-    done = true;
-    return false;
-  }
-  k += (uint64_t)q;
-  uint64_t aa, bb;
-  if (k < 0xFFFFFFFFull) {
-    const uint32_t k32 = (uint32_t)k;
-    aa = k32 / nb;
-    bb = k32 - (uint32_t)aa * nb;
-  } else {
-    aa = k / nb;
-    bb = k - aa * nb;
-  }
-  su = a0 + (uint32_t)aa;
-  sv = b0 + (uint32_t)bb;
-  ++ncand;
-  const double p = pair_prob<D, MODEL>(g, v, su, sv);
-  const bool e = u53(o.z, o.w) * pb < p;
-  ++k;
-  done = k >= kend;
-  return e;
-}
-
-
 // ---------------------------------------------------------------------------
-// type-I step: up to two tests of the current item sharing one Philox block.
-// Pair index k = a * |V_j^B| + b, or for A = B and i = j (only a < b)
-// k = b (b - 1) / 2 + a (App. B.1); tests k and k + 1 use words 0-1 and 2-3
-// of block k / 2 (k is even at every step).
+// per-wave edge buffer and its flushes to the staging array
 // ---------------------------------------------------------------------------
-template <int D, int MODEL, bool T0, bool WRITE>
-__device__ __forceinline__ void type1_step(const Graph* __restrict__ g, const Verts& v, uint32_t A,
-                                           uint32_t B, uint32_t w3base, uint32_t a0, uint32_t b0,
-                                           uint32_t nb, bool tri, uint32_t& a, uint32_t& b,
-                                           uint64_t& k, uint64_t kend, bool& e0, bool& e1,
-                                           uint2& p0, uint2& p1, uint64_t& ntests) {
-  U4 o{0, 0, 0, 0};
-  if constexpr (!T0)
-    o = philox((uint32_t)(k >> 1), A, B, w3base | ((uint32_t)(k >> 33) << 20), g->seed_lo, g->seed_hi);
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (k < kend) {
-      const uint32_t su = a0 + a, sv = (tri ? a0 : b0) + b;
-      bool e;
-      if constexpr (T0) {
-        e = pair_thresh<D, MODEL>(g, v, su, sv);
-      } else {
-        const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
-        e = U < pair_prob<D, MODEL>(g, v, su, sv);
-      }
-      if (WRITE && e) {
-        if (h == 0) p0 = make_uint2(v.id[su], v.id[sv]);
-        else p1 = make_uint2(v.id[su], v.id[sv]);
-      }
-      if (h == 0) e0 = e; else e1 = e;
-      ++ntests;
-      ++k;
-      if (tri) {
-        if (++a == b) { a = 0; ++b; }
-      } else {
-        if (++b == nb) { b = 0; ++a; }
-      }
+constexpr uint32_t kEdgeBuf = 256;  // LDS edges per wave; flushed above 128
+
+struct Out {
+  uint2* lb;      // LDS buffer of this wave
+  uint32_t bn;    // edges in it
+  uint32_t seq;   // flushes of the current chunk
+  uint64_t key;   // pass << 58 | chunk << 26
+};
+
+__device__ __forceinline__ void flush(const Stage& sg, Out& o) {
+  if (o.bn == 0) return;
+  const uint32_t lane = lane_id();
+  unsigned long long pos = 0;
+  if (lane == 0) pos = atomicAdd(sg.cursor, (unsigned long long)o.bn);
+  pos = __shfl(pos, 0, 64);
+  for (uint32_t i = lane; i < o.bn; i += kWave)
+    if (pos + i < sg.cap) sg.buf[pos + i] = o.lb[i];
+  if (lane == 0) {
+    atomicAdd(&sg.stats[8 + (o.key >> 58)], (unsigned long long)o.bn);  // edges per pass
+    const unsigned int slot = atomicAdd(sg.nrec, 1u);
+    if (slot < sg.rcap) {
+      sg.rkey[slot] = o.key | o.seq;
+      sg.rpos[slot] = pos;
+      sg.rcnt[slot] = o.bn;
     }
   }
+  ++o.seq;
+  o.bn = 0;
 }
 
-__device__ __forceinline__ void append2(bool WRITE, bool e0, bool e1, uint2 p0, uint2 p1,
-                                        uint2* __restrict__ edges, uint64_t& running) {
+// append up to two edges per lane (order: all first edges, then all second)
+__device__ __forceinline__ void emit(bool e0, bool e1, uint2 p0, uint2 p1, const Stage& sg,
+                                     Out& o) {
   const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
-  if (WRITE) {
-    if (e0) edges[running + lanes_below(m0)] = p0;
-    if (e1) edges[running + __popcll(m0) + lanes_below(m1)] = p1;
-  }
-  running += __popcll(m0) + __popcll(m1);
+  if (e0) o.lb[o.bn + lanes_below(m0)] = p0;
+  if (e1) o.lb[o.bn + __popcll(m0) + lanes_below(m1)] = p1;
+  o.bn += (uint32_t)(__popcll(m0) + __popcll(m1));
+  if (o.bn > kEdgeBuf - 128) flush(sg, o);
 }
 
-__device__ __forceinline__ void defer_item(bool WRITE, bool pending, const ItemRec& rec,
-                                           uint32_t chunk, uint32_t& seq, const DeferOut& dfo) {
+__device__ __forceinline__ void defer_item(bool pending, const ItemRec& rec, uint32_t chunk,
+                                           uint32_t& seq, const DeferOut& dfo) {
   const uint64_t mb = __ballot(pending);
-  if (!WRITE && pending) {
+  if (pending) {
     const unsigned int slot = atomicAdd(dfo.count, 1u);
     if (slot < dfo.cap) {
       dfo.rec[slot] = rec;
       dfo.key[slot] = ((uint64_t)chunk << 24) | (seq + lanes_below(mb));
     }
   }
-  seq += __popcll(mb);
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-  return x;
+  seq += (uint32_t)__popcll(mb);
 }
 
 // ---------------------------------------------------------------------------
-// Per-wave LDS buffers of the sampling passes.  A wave first decodes units
-// and appends the valid (run, cell B) pairs to `vb` (phase A), then takes 64
-// of them, one per lane, and walks the layers j of each pair (phase B,
-// converged: the pairs of one run share their layer masks); non-empty items
-// go to an item ring.  The rings are consumed in converged steps: type-I
-// takes 64 Philox blocks (two tests each) per step flat across the queued
-// items; type-II lanes own one item each and make one geometric draw per
-// step, pushing candidates into a candidate ring that is evaluated 64 at a
-// time.  Every append and dequeue is a ballot in converged code, so the order
-// of the emitted edges is a pure function of the chunk.
+// per-wave LDS buffers: valid units, item rings, candidate ring
 // ---------------------------------------------------------------------------
 constexpr int kVCap = 128;  // valid-unit buffer (>= 2 x 64)
 constexpr int kQCap = 128;  // item ring (power of two, >= 2 x 64)
@@ -287,14 +239,16 @@ struct VUnit {
   uint32_t sidx, B, gap, pad;
 };
 
-// type-I item; cs = index of its first Philox block in the wave's block stream
+// type-I item (or a piece of a split one): Philox blocks [kb, kb + nbk) of
+// the item; cs = index of its first block in the wave's stream of blocks
 struct QItem1 {
-  uint32_t A, B, w3, a0, b0, nb, na, tri, cs;
+  uint32_t A, B, w3, a0, b0, nb, na, tri, cs, kb, nbk, pad;
 };
 
-// type-II item (one segment, k and N < 2^32)
+// type-II item (or one segment of a segmented one): candidates [k, N)
 struct QItem2 {
-  uint32_t A, B, w3, a0, b0, nb, t, k, N, pad;
+  uint32_t A, B, w3, a0, b0, nb, t, pad;
+  uint64_t k, N;
   double pb, lg;
 };
 
@@ -348,19 +302,70 @@ __device__ __forceinline__ bool take_unit(VUnit* __restrict__ vb, uint32_t& vn, 
 }
 
 // ---------------------------------------------------------------------------
-// type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3)
+// type-I tests.  Pair index k = a * |V_j^B| + b, or for A = B and i = j (only
+// a < b) k = b (b - 1) / 2 + a (App. B.1); tests k and k + 1 use words 0-1 and
+// 2-3 of Philox block k / 2.
 // ---------------------------------------------------------------------------
 struct Ring1 {
-  uint32_t qh, qt;   // items [qh, qt) are queued (logical indices)
-  uint32_t bc, bt;   // next Philox block to process / end of the queued blocks
+  uint32_t qh, qt;  // items [qh, qt) are queued (logical indices)
+  uint32_t bc, bt;  // next Philox block to process / end of the queued blocks
 };
 
-// one converged step over up to 64 queued Philox blocks (two tests each)
-template <int D, int MODEL, bool T0, bool WRITE>
+template <int D, int MODEL, bool T0>
+__device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Verts& v,
+                                           const QItem1& it, uint64_t k, uint64_t kend, bool& e0,
+                                           bool& e1, uint2& p0, uint2& p1, uint64_t& ntests) {
+  const bool tri = it.tri != 0;
+  uint32_t a, b;
+  if (tri) {
+    uint32_t bb = (uint32_t)(0.5 * (1.0 + sqrt(1.0 + 8.0 * (double)k)));
+    while ((uint64_t)bb * (bb - 1) / 2 > k) --bb;
+    while ((uint64_t)(bb + 1) * bb / 2 <= k) ++bb;
+    b = bb;
+    a = (uint32_t)(k - (uint64_t)bb * (bb - 1) / 2);
+  } else if (k < 0xFFFFFFFFull) {
+    a = (uint32_t)k / it.nb;
+    b = (uint32_t)k - a * it.nb;
+  } else {
+    a = (uint32_t)(k / it.nb);
+    b = (uint32_t)(k - (uint64_t)a * it.nb);
+  }
+  U4 o{0, 0, 0, 0};
+  if constexpr (!T0)
+    o = philox((uint32_t)(k >> 1), it.A, it.B, it.w3 | ((uint32_t)(k >> 33) << 20), g->seed_lo,
+               g->seed_hi);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (k < kend) {
+      const uint32_t su = it.a0 + a, sv = (tri ? it.a0 : it.b0) + b;
+      bool e;
+      if constexpr (T0) {
+        e = pair_thresh<D, MODEL>(g, v, su, sv);
+      } else {
+        const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
+        e = U < pair_prob<D, MODEL>(g, v, su, sv);
+      }
+      if (e) {
+        if (h == 0) p0 = make_uint2(v.id[su], v.id[sv]);
+        else p1 = make_uint2(v.id[su], v.id[sv]);
+      }
+      if (h == 0) e0 = e; else e1 = e;
+      ++ntests;
+      ++k;
+      if (tri) {
+        if (++a == b) { a = 0; ++b; }
+      } else {
+        if (++b == it.nb) { b = 0; ++a; }
+      }
+    }
+  }
+}
+
+// one converged step over up to 64 queued Philox blocks
+template <int D, int MODEL, bool T0>
 __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& v,
-                                      const QItem1* __restrict__ q, Ring1& r,
-                                      uint2* __restrict__ edges, uint64_t& running,
-                                      uint64_t& ntests) {
+                                      const QItem1* __restrict__ q, Ring1& r, const Stage& sg,
+                                      Out& out, uint64_t& ntests) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.bt - r.bc;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -375,24 +380,12 @@ __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& 
       if (q[mid & (kQCap - 1)].cs <= gb) lo = mid; else hi = mid;
     }
     const QItem1 it = q[lo & (kQCap - 1)];
-    const bool tri = it.tri != 0;
-    const uint64_t tot = tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
-    uint64_t k = 2ull * (gb - it.cs);
-    uint32_t a, b;
-    if (tri) {
-      uint32_t bb = (uint32_t)(0.5 * (1.0 + sqrt(1.0 + 8.0 * (double)k)));
-      while ((uint64_t)bb * (bb - 1) / 2 > k) --bb;
-      while ((uint64_t)(bb + 1) * bb / 2 <= k) ++bb;
-      b = bb;
-      a = (uint32_t)(k - (uint64_t)bb * (bb - 1) / 2);
-    } else {
-      a = (uint32_t)k / it.nb;
-      b = (uint32_t)k - a * it.nb;
-    }
-    type1_step<D, MODEL, T0, WRITE>(g, v, it.A, it.B, it.w3, it.a0, it.b0, it.nb, tri, a, b, k,
-                                    tot, e0, e1, p0, p1, ntests);
+    const uint64_t tot = it.tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
+    const uint64_t kb = (uint64_t)it.kb + (gb - it.cs);
+    const uint64_t kend = 2ull * ((uint64_t)it.kb + it.nbk) < tot ? 2ull * ((uint64_t)it.kb + it.nbk) : tot;
+    test_block<D, MODEL, T0>(g, v, it, 2ull * kb, kend, e0, e1, p0, p1, ntests);
   }
-  append2(WRITE, e0, e1, p0, p1, edges, running);
+  emit(e0, e1, p0, p1, sg, out);
   r.bc += take;
   // retire the items whose blocks are all done
   while (r.qh < r.qt) {
@@ -402,13 +395,35 @@ __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& 
   }
 }
 
-template <int D, int MODEL, bool T0, bool WRITE>
+// enqueue one item per lane (enq) with its first-block index from a wave
+// prefix sum of the block counts
+__device__ __forceinline__ void enqueue1(bool enq, QItem1& it, QItem1* __restrict__ q, Ring1& r) {
+  const uint32_t lane = lane_id();
+  const uint64_t me = __ballot(enq);
+  uint32_t pre = enq ? it.nbk : 0u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(pre, o, 64);
+    if ((int)lane >= o) pre += t;
+  }
+  const uint32_t total = __shfl(pre, 63, 64);
+  if (enq) {
+    it.cs = r.bt + pre - it.nbk;
+    q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
+  }
+  r.qt += (uint32_t)__popcll(me);
+  r.bt += total;
+}
+
+// type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3)
+template <int D, int MODEL, bool T0>
 __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
-                                               const Src* __restrict__ src, Sched sc, PassOut po,
+                                               const Src* __restrict__ src, Sched sc, Stage sg,
                                                DeferOut dfo) {
   __shared__ VUnit vbs[4][kVCap];
   __shared__ QItem1 qs[4][kQCap];
+  __shared__ uint2 ebs[4][kEdgeBuf];
   const uint32_t wv = threadIdx.x / kWave;
   VUnit* vb = vbs[wv];
   QItem1* q = qs[wv];
@@ -422,7 +437,7 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
     uint64_t u = ub + lane;
     uint32_t vn = 0, dseq = 0;
     Ring1 r{0, 0, 0, 0};
-    uint64_t running = WRITE ? po.add + po.base[c] : 0;
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (;;) {
       fill_units<D, false>(g, src, u, ue, vb, vn);
       if (vn == 0) break;
@@ -441,13 +456,12 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
         if (mu.B == A) jm &= ~((1ull << li) - 1ull);  // j >= i when A = B
       }
       while (__any(jm != 0)) {
-        // keep room for 64 more items; consume blocks when there is a full step of them
+        // room for 64 more items; consume blocks when there are several steps of them
         while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-          step1<D, MODEL, T0, WRITE>(g, v, q, r, po.edges, running, ntests);
+          step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
         bool enq = false, big = false;
         QItem1 it{};
         ItemRec rec{};
-        uint32_t nblk = 0;
         if (jm) {
           const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
           jm &= jm - 1;
@@ -461,55 +475,87 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
               rec = ItemRec{a0, na, b0, nb, A, mu.B, lvl | (li << 8) | (lj << 16) | (tri ? 1u << 31 : 0u), 0u};
               big = true;
             } else {
-              it = QItem1{A, mu.B, w3, a0, b0, nb, na, tri ? 1u : 0u, 0u};
-              nblk = (uint32_t)((tot + 1) / 2);
+              it = QItem1{A, mu.B, w3, a0, b0, nb, na, tri ? 1u : 0u, 0u, 0u, (uint32_t)((tot + 1) / 2), 0u};
               enq = true;
             }
           }
         }
-        if (__any(big)) defer_item(WRITE, big, rec, c, dseq, dfo);
-        // enqueue with first-block indices from a wave prefix sum of the block counts
-        const uint64_t me = __ballot(enq);
-        uint32_t pre = nblk;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t t = __shfl_up(pre, o, 64);
-          if ((int)lane >= o) pre += t;
-        }
-        const uint32_t total = __shfl(pre, 63, 64);
-        if (enq) {
-          it.cs = r.bt + pre - nblk;
-          q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
-        }
-        r.qt += (uint32_t)__popcll(me);
-        r.bt += total;
+        if (__any(big)) defer_item(big, rec, c, dseq, dfo);
+        enqueue1(enq, it, q, r);
       }
     }
-    while (r.bc < r.bt) step1<D, MODEL, T0, WRITE>(g, v, q, r, po.edges, running, ntests);
-    if (!WRITE && lane == 0) po.count[c] = running;
+    while (r.bc < r.bt) step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+    flush(sg, out);
   }
-  if (!WRITE) {
-    ntests = wave_sum(ntests);
-    if (lane == 0) atomicAdd(&po.stats[0], (unsigned long long)ntests);
+  ntests = wave_sum(ntests);
+  if (lane == 0) atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
+}
+
+// split type-I items: pieces of kTestChunk tests (kTestChunk / 2 blocks)
+template <int D, int MODEL, bool T0>
+__global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts v,
+                                              const ItemRec* __restrict__ rec,
+                                              const uint64_t* __restrict__ uoff, uint32_t nrec,
+                                              Sched sc, Stage sg) {
+  __shared__ QItem1 qs[4][kQCap];
+  __shared__ uint2 ebs[4][kEdgeBuf];
+  const uint32_t wv = threadIdx.x / kWave;
+  QItem1* q = qs[wv];
+  const uint32_t lane = lane_id();
+  uint64_t ntests = 0;
+  for (;;) {
+    const uint32_t c = next_chunk(sc.next);
+    if (c >= sc.nchunks) break;
+    const uint64_t ub = (uint64_t)c * sc.chunk;
+    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
+    Ring1 r{0, 0, 0, 0};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
+      while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
+        step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+      const uint64_t u = u0 + lane;
+      bool enq = false;
+      QItem1 it{};
+      if (u < ue) {
+        uint32_t lo = 0, hi = nrec;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (uoff[mid] <= u) lo = mid; else hi = mid;
+        }
+        const ItemRec rr = rec[lo];
+        const bool tri = (rr.meta >> 31) != 0;
+        const uint64_t tot = tri ? (uint64_t)rr.na * (rr.na - 1) / 2 : (uint64_t)rr.na * rr.nb;
+        const uint64_t nbt = (tot + 1) / 2;  // blocks of the item
+        const uint64_t kb = (u - uoff[lo]) * (kTestChunk / 2);
+        const uint64_t nbk = kb + kTestChunk / 2 < nbt ? kTestChunk / 2 : nbt - kb;
+        it = QItem1{rr.A, rr.B,
+                    ctr_word3(rr.meta & 255u, (rr.meta >> 8) & 255u, (rr.meta >> 16) & 255u, kKindType1, 0),
+                    rr.a0, rr.b0, rr.nb, rr.na, tri ? 1u : 0u, 0u, (uint32_t)kb, (uint32_t)nbk, 0u};
+        enq = true;
+      }
+      enqueue1(enq, it, q, r);
+    }
+    while (r.bc < r.bt) step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+    flush(sg, out);
   }
+  ntests = wave_sum(ntests);
+  if (lane == 0) atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
 }
 
 // ---------------------------------------------------------------------------
-// type-II pass: distant cell pairs with neighbouring parents at levels
-// l <= CL(i,j).  Candidates of V_i^A x V_j^B are drawn by geometric jumps
+// type-II draws.  Candidates of V_i^A x V_j^B are drawn by geometric jumps
 // under pbar and accepted with p_uv / pbar (Sec. 3.2).  The candidate range is
 // cut into segments of G = 2^e (e = 5 - ilogb(pbar), raised to keep at most
-// 2^12 segments); segment s draws from counter (t, A, B, l|i|j|1|s).  Items
-// with one segment are sampled here, the others are deferred to the segment
-// kernel.
+// 2^12 segments); draw t of segment s uses counter (t, A, B, l|i|j|1|s).
 // ---------------------------------------------------------------------------
 struct Ring2 {
   uint32_t qh, qt;  // queued items
   uint32_t ch, ct;  // queued candidates
 };
 
-// one geometric draw without the candidate test: advances k; returns true
-// and the candidate's sorted indices and Acc * pbar when there is one
+// one geometric draw without the candidate test: X ~ Geom_0(pbar) candidates
+// are skipped (X = floor(ln S / ln(1 - pbar))); returns true with the
+// candidate's sorted indices and Acc * pbar when it lies in the range
 __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, bool& done,
                                          Cand& cd) {
   const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
@@ -520,9 +566,15 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
     done = true;
     return false;
   }
-  it.k += (uint32_t)q;
-  const uint32_t aa = it.k / it.nb;
-  const uint32_t bb = it.k - aa * it.nb;
+  it.k += (uint64_t)q;
+  uint32_t aa, bb;
+  if (it.k < 0xFFFFFFFFull) {
+    aa = (uint32_t)it.k / it.nb;
+    bb = (uint32_t)it.k - aa * it.nb;
+  } else {
+    aa = (uint32_t)(it.k / it.nb);
+    bb = (uint32_t)(it.k - (uint64_t)aa * it.nb);
+  }
   cd.su = it.a0 + aa;
   cd.sv = it.b0 + bb;
   cd.apb = u53(o.z, o.w) * it.pb;
@@ -532,10 +584,10 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
 }
 
 // evaluate up to 64 queued candidates (accept iff Acc * pbar < p_uv)
-template <int D, int MODEL, bool WRITE>
+template <int D, int MODEL>
 __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Verts& v,
-                                           const Cand* __restrict__ cq, Ring2& r,
-                                           uint2* __restrict__ edges, uint64_t& running) {
+                                           const Cand* __restrict__ cq, Ring2& r, const Stage& sg,
+                                           Out& out) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.ct - r.ch;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -544,21 +596,20 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
   if (lane < take) {
     const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
     e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
-    if (WRITE && e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
+    if (e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
   }
-  append2(WRITE, e0, false, p0, p0, edges, running);
+  emit(e0, false, p0, p0, sg, out);
   r.ch += take;
 }
 
 // draw steps: lanes own items (dequeued from the ring), one draw per step;
-// runs while at least `need` items are queued or held, or to the end if
-// need == 0
-template <int D, int MODEL, bool WRITE>
+// runs while at least `need` items are queued or held (to the end if 0)
+template <int D, int MODEL>
 __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts& v,
                                        const QItem2* __restrict__ q, Cand* __restrict__ cq,
                                        Ring2& r, bool& act, QItem2& it, uint32_t need,
-                                       uint2* __restrict__ edges, uint64_t& running,
-                                       uint64_t& ndraws, uint64_t& ncand) {
+                                       const Stage& sg, Out& out, uint64_t& ndraws,
+                                       uint64_t& ncand) {
   const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
   for (;;) {
     const uint64_t mi = __ballot(!act);
@@ -587,19 +638,29 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
     r.ct += (uint32_t)__popcll(mc);
     ncand += hc ? 1 : 0;
-    if (r.ct - r.ch >= 64) eval_cands<D, MODEL, WRITE>(g, v, cq, r, edges, running);
+    if (r.ct - r.ch >= 64) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
   }
 }
 
-template <int D, int MODEL, bool WRITE>
+__device__ __forceinline__ void enqueue2(bool enq, const QItem2& it, QItem2* __restrict__ q,
+                                         Ring2& r) {
+  const uint64_t me = __ballot(enq);
+  if (enq) q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
+  r.qt += (uint32_t)__popcll(me);
+}
+
+// type-II pass: distant cell pairs with neighbouring parents at levels
+// l <= CL(i,j); items of one segment are sampled here, others deferred
+template <int D, int MODEL>
 __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
                                                const Src* __restrict__ src, Sched sc,
-                                               const Pbar* __restrict__ pbt, int nlev, PassOut po,
+                                               const Pbar* __restrict__ pbt, int nlev, Stage sg,
                                                DeferOut dfo) {
   __shared__ VUnit vbs[4][kVCap];
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
+  __shared__ uint2 ebs[4][kEdgeBuf];
   const uint32_t wv = threadIdx.x / kWave;
   VUnit* vb = vbs[wv];
   QItem2* q = qs[wv];
@@ -617,7 +678,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
     Ring2 r{0, 0, 0, 0};
     bool act = false;
     QItem2 cur{};
-    uint64_t running = WRITE ? po.add + po.base[c] : 0;
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (;;) {
       fill_units<D, true>(g, src, u, ue, vb, vn);
       if (vn == 0) break;
@@ -637,7 +698,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
       const uint32_t gp = mu.gap;
       while (__any(jm != 0)) {
         if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-          draws2<D, MODEL, WRITE>(g, v, q, cq, r, act, cur, 64, po.edges, running, ndraws, ncand);
+          draws2<D, MODEL>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand);
         bool enq = false, hv = false;
         QItem2 it{};
         ItemRec rec{};
@@ -652,108 +713,48 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
               const uint64_t N = (uint64_t)na * nb;
               uint64_t G, nseg;
               segment_size(N, pe.e, &G, &nseg);
-              if (nseg > 1 || N >= 0xFFFFFFFFull) {
+              if (nseg > 1) {
                 rec = ItemRec{a0, na, b0, nb, A, mu.B,
                               lvl | (li << 8) | (lj << 16) | (gp << 24), (uint32_t)pe.e};
                 hv = true;
               } else {
                 it = QItem2{A, mu.B, ctr_word3(lvl, li, lj, kKindType2, 0), a0, b0, nb, 0u, 0u,
-                            (uint32_t)N, 0u, pe.pbar, pe.lg};
+                            0ull, N, pe.pbar, pe.lg};
                 enq = true;
               }
             }
           }
         }
-        if (__any(hv)) defer_item(WRITE, hv, rec, c, dseq, dfo);
-        const uint64_t me = __ballot(enq);
-        if (enq) q[(r.qt + lanes_below(me)) & (kQCap - 1)] = it;
-        r.qt += (uint32_t)__popcll(me);
+        if (__any(hv)) defer_item(hv, rec, c, dseq, dfo);
+        enqueue2(enq, it, q, r);
       }
     }
-    draws2<D, MODEL, WRITE>(g, v, q, cq, r, act, cur, 0, po.edges, running, ndraws, ncand);
-    while (r.ct != r.ch) eval_cands<D, MODEL, WRITE>(g, v, cq, r, po.edges, running);
-    if (!WRITE && lane == 0) po.count[c] = running;
+    draws2<D, MODEL>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand);
+    while (r.ct != r.ch) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
+    flush(sg, out);
   }
-  if (!WRITE) {
-    ndraws = wave_sum(ndraws);
-    ncand = wave_sum(ncand);
-    if (lane == 0) {
-      atomicAdd(&po.stats[1], (unsigned long long)ndraws);
-      atomicAdd(&po.stats[2], (unsigned long long)ncand);
-    }
+  ndraws = wave_sum(ndraws);
+  ncand = wave_sum(ncand);
+  if (lane == 0) {
+    const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
+    atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
+    atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
   }
 }
 
-// split type-I items: units of kTestChunk consecutive tests
-template <int D, int MODEL, bool T0, bool WRITE>
-__global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts v,
-                                              const ItemRec* __restrict__ rec,
-                                              const uint64_t* __restrict__ uoff, uint32_t nrec,
-                                              Sched sc, PassOut po) {
-  const uint32_t lane = lane_id();
-  uint64_t ntests = 0;
-  for (;;) {
-    const uint32_t c = next_chunk(sc.next);
-    if (c >= sc.nchunks) break;
-    const uint64_t ub = (uint64_t)c * sc.chunk;
-    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
-    uint64_t u = ub + lane;
-    bool act = false, tri = false;
-    uint32_t A = 0, B = 0, a0 = 0, b0 = 0, nb = 0, a = 0, b = 0, w3 = 0;
-    uint64_t k = 0, kend = 0;
-    uint64_t running = WRITE ? po.add + po.base[c] : 0;
-    for (;;) {
-      if (!act && u < ue) {
-        uint32_t lo = 0, hi = nrec;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) / 2;
-          if (uoff[mid] <= u) lo = mid; else hi = mid;
-        }
-        const ItemRec r = rec[lo];
-        tri = (r.meta >> 31) != 0;
-        const uint64_t tot = tri ? (uint64_t)r.na * (r.na - 1) / 2 : (uint64_t)r.na * r.nb;
-        k = (u - uoff[lo]) * kTestChunk;
-        kend = k + kTestChunk < tot ? k + kTestChunk : tot;
-        A = r.A; B = r.B; a0 = r.a0; b0 = r.b0; nb = r.nb;
-        w3 = ctr_word3(r.meta & 255u, (r.meta >> 8) & 255u, (r.meta >> 16) & 255u, kKindType1, 0);
-        if (tri) {
-          // b = largest with b (b - 1) / 2 <= k
-          uint64_t bb = (uint64_t)floor(0.5 * (1.0 + sqrt(1.0 + 8.0 * (double)k)));
-          while (bb * (bb - 1) / 2 > k) --bb;
-          while ((bb + 1) * bb / 2 <= k) ++bb;
-          b = (uint32_t)bb;
-          a = (uint32_t)(k - bb * (bb - 1) / 2);
-        } else {
-          a = (uint32_t)(k / nb);
-          b = (uint32_t)(k - (uint64_t)a * nb);
-        }
-        u += kWave;
-        act = true;
-      }
-      if (!__any(act)) break;
-      bool e0 = false, e1 = false;
-      uint2 p0 = make_uint2(0, 0), p1 = make_uint2(0, 0);
-      if (act) {
-        type1_step<D, MODEL, T0, WRITE>(g, v, A, B, w3, a0, b0, nb, tri, a, b, k, kend, e0, e1, p0, p1, ntests);
-        if (k >= kend) act = false;
-      }
-      append2(WRITE, e0, e1, p0, p1, po.edges, running);
-    }
-    if (!WRITE && lane == 0) po.count[c] = running;
-  }
-  if (!WRITE) {
-    ntests = wave_sum(ntests);
-    if (lane == 0) atomicAdd(&po.stats[0], (unsigned long long)ntests);
-  }
-}
-
-// deferred type-II items: one segment per unit
-template <int D, int MODEL, bool WRITE>
+// segmented type-II items: one segment per unit
+template <int D, int MODEL>
 __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Verts v,
                                                 const ItemRec* __restrict__ rec,
                                                 const uint64_t* __restrict__ uoff, uint32_t nrec,
                                                 Sched sc, const Pbar* __restrict__ pbt, int nlev,
-                                                PassOut po) {
+                                                Stage sg) {
+  __shared__ QItem2 qs[4][kQCap];
+  __shared__ Cand cqs[4][kCCap];
+  __shared__ uint2 ebs[4][kEdgeBuf];
+  const uint32_t wv = threadIdx.x / kWave;
+  QItem2* q = qs[wv];
+  Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
   const int L = g->L;
   uint64_t ndraws = 0, ncand = 0;
@@ -762,60 +763,47 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     if (c >= sc.nchunks) break;
     const uint64_t ub = (uint64_t)c * sc.chunk;
     const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
-    uint64_t u = ub + lane;
+    Ring2 r{0, 0, 0, 0};
     bool act = false;
-    uint32_t A = 0, B = 0, a0 = 0, b0 = 0, nb = 0, t = 0, w3 = 0;
-    uint64_t k = 0, kend = 0;
-    double pb = 0.0, lg = 0.0;
-    uint64_t running = WRITE ? po.add + po.base[c] : 0;
-    for (;;) {
-      if (!act && u < ue) {
+    QItem2 cur{};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
+      if (r.qt - r.qh > (uint32_t)(kQCap - 64))
+        draws2<D, MODEL>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand);
+      const uint64_t u = u0 + lane;
+      bool enq = false;
+      QItem2 it{};
+      if (u < ue) {
         uint32_t lo = 0, hi = nrec;
         while (hi - lo > 1) {
           const uint32_t mid = (lo + hi) / 2;
           if (uoff[mid] <= u) lo = mid; else hi = mid;
         }
-        const ItemRec r = rec[lo];
+        const ItemRec rr = rec[lo];
         const uint64_t s = u - uoff[lo];
-        const uint32_t lvl = r.meta & 255u, li = (r.meta >> 8) & 255u, lj = (r.meta >> 16) & 255u,
-                       gp = (r.meta >> 24) & 127u;
+        const uint32_t lvl = rr.meta & 255u, li = (rr.meta >> 8) & 255u, lj = (rr.meta >> 16) & 255u,
+                       gp = (rr.meta >> 24) & 127u;
         const Pbar pe = pbt[(((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1)];
-        const uint64_t N = (uint64_t)r.na * r.nb;
+        const uint64_t N = (uint64_t)rr.na * rr.nb;
         uint64_t G, ns;
-        segment_size(N, (int)r.e, &G, &ns);
-        A = r.A; B = r.B; a0 = r.a0; b0 = r.b0; nb = r.nb;
-        pb = pe.pbar;
-        lg = pe.lg;
-        w3 = ctr_word3(lvl, li, lj, kKindType2, (uint32_t)s);
-        k = s * G;
-        kend = (s + 1) * G < N ? (s + 1) * G : N;
-        t = 0;
-        u += kWave;
-        act = true;
+        segment_size(N, (int)rr.e, &G, &ns);
+        const uint64_t k0 = s * G, kend = (s + 1) * G < N ? (s + 1) * G : N;
+        it = QItem2{rr.A, rr.B, ctr_word3(lvl, li, lj, kKindType2, (uint32_t)s), rr.a0, rr.b0, rr.nb,
+                    0u, 0u, k0, kend, pe.pbar, pe.lg};
+        enq = true;
       }
-      if (!__any(act)) break;
-      bool e0 = false;
-      uint2 p0 = make_uint2(0, 0);
-      if (act) {
-        uint32_t su, sv;
-        bool done;
-        e0 = type2_draw<D, MODEL>(g, v, A, B, w3, t, pb, lg, a0, b0, nb, k, kend, done, su, sv, ncand);
-        ++t;
-        ++ndraws;
-        if (WRITE && e0) p0 = make_uint2(v.id[su], v.id[sv]);
-        if (done) act = false;
-      }
-      append2(WRITE, e0, false, p0, p0, po.edges, running);
+      enqueue2(enq, it, q, r);
     }
-    if (!WRITE && lane == 0) po.count[c] = running;
+    draws2<D, MODEL>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand);
+    while (r.ct != r.ch) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
+    flush(sg, out);
   }
-  if (!WRITE) {
-    ndraws = wave_sum(ndraws);
-    ncand = wave_sum(ncand);
-    if (lane == 0) {
-      atomicAdd(&po.stats[1], (unsigned long long)ndraws);
-      atomicAdd(&po.stats[2], (unsigned long long)ncand);
-    }
+  ndraws = wave_sum(ndraws);
+  ncand = wave_sum(ncand);
+  if (lane == 0) {
+    const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
+    atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
+    atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
   }
 }
 
@@ -842,72 +830,85 @@ __global__ __launch_bounds__(256) void k_rec_gather(const ItemRec* __restrict__ 
   if (h < nrec) out[h] = in[perm[h]];
 }
 
+// staged blocks -> final order: count of sorted record w, then copy (one wave
+// per record)
+__global__ __launch_bounds__(256) void k_stage_counts(const uint32_t* __restrict__ rcnt,
+                                                      const uint32_t* __restrict__ perm,
+                                                      uint32_t nrec, uint64_t* __restrict__ cnt) {
+  const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < nrec) cnt[h] = rcnt[perm[h]];
+}
+
+__global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ stage,
+                                                    const uint64_t* __restrict__ rpos,
+                                                    const uint32_t* __restrict__ rcnt,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const uint64_t* __restrict__ off, uint32_t nrec,
+                                                    uint2* __restrict__ out) {
+  const uint32_t lane = lane_id();
+  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < nrec; w += nw) {
+    const uint32_t r = perm[w];
+    const uint64_t src = rpos[r], dst = off[w];
+    const uint32_t cnt = rcnt[r];
+    for (uint32_t i = lane; i < cnt; i += kWave) out[dst + i] = stage[src + i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define HG_DISPATCH_D(MODELV, ...)                                              \
-  do {                                                                          \
+#define HG_DISPATCH_D(...)                                                         \
+  do {                                                                             \
     if (g.model == 1) { constexpr int DD = 1; constexpr int MM = 1; __VA_ARGS__; } \
-    else switch (g.d) {                                                         \
-      case 1: { constexpr int DD = 1; constexpr int MM = 0; __VA_ARGS__; } break; \
-      case 2: { constexpr int DD = 2; constexpr int MM = 0; __VA_ARGS__; } break; \
-      case 3: { constexpr int DD = 3; constexpr int MM = 0; __VA_ARGS__; } break; \
+    else switch (g.d) {                                                            \
+      case 1: { constexpr int DD = 1; constexpr int MM = 0; __VA_ARGS__; } break;  \
+      case 2: { constexpr int DD = 2; constexpr int MM = 0; __VA_ARGS__; } break;  \
+      case 3: { constexpr int DD = 3; constexpr int MM = 0; __VA_ARGS__; } break;  \
       default: { constexpr int DD = 4; constexpr int MM = 0; __VA_ARGS__; } break; \
-    }                                                                           \
+    }                                                                              \
   } while (0)
 
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, bool write, const PassOut& po,
-                        const DeferOut& dfo, hipStream_t st) {
-  const bool t0 = !(g.T > 0.0);
+                        const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
+                        hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  HG_DISPATCH_D(0, {
-    if (t0) {
-      if (write) hipLaunchKernelGGL((k_type1<DD, MM, true, true>), grid, block, 0, st, gd, v, P, src, sc, po, dfo);
-      else hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, P, src, sc, po, dfo);
-    } else {
-      if (write) hipLaunchKernelGGL((k_type1<DD, MM, false, true>), grid, block, 0, st, gd, v, P, src, sc, po, dfo);
-      else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, P, src, sc, po, dfo);
-    }
+  const bool t0 = !(g.T > 0.0);
+  HG_DISPATCH_D({
+    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+    else hipLaunchKernelGGL((k_type1<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
-                       const uint64_t* uoff, uint32_t nrec, const Sched& sc, bool write,
-                       const PassOut& po, hipStream_t st) {
-  const bool t0 = !(g.T > 0.0);
+                       const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Stage& sg,
+                       hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  HG_DISPATCH_D(0, {
-    if (t0) {
-      if (write) hipLaunchKernelGGL((k_big1<DD, MM, true, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, po);
-      else hipLaunchKernelGGL((k_big1<DD, MM, true, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, po);
-    } else {
-      if (write) hipLaunchKernelGGL((k_big1<DD, MM, false, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, po);
-      else hipLaunchKernelGGL((k_big1<DD, MM, false, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, po);
-    }
+  const bool t0 = !(g.T > 0.0);
+  HG_DISPATCH_D({
+    if (t0) hipLaunchKernelGGL((k_big1<DD, MM, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
+    else hipLaunchKernelGGL((k_big1<DD, MM, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev, bool write,
-                        const PassOut& po, const DeferOut& dfo, hipStream_t st) {
+                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
+                        const Stage& sg, const DeferOut& dfo, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  HG_DISPATCH_D(0, {
-    if (write) hipLaunchKernelGGL((k_type2<DD, MM, true>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, po, dfo);
-    else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, po, dfo);
+  HG_DISPATCH_D({
+    hipLaunchKernelGGL((k_type2<DD, MM>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
-                         int nlev, bool write, const PassOut& po, hipStream_t st) {
+                         int nlev, const Stage& sg, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  HG_DISPATCH_D(0, {
-    if (write) hipLaunchKernelGGL((k_heavy2<DD, MM, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, po);
-    else hipLaunchKernelGGL((k_heavy2<DD, MM, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, po);
+  HG_DISPATCH_D({
+    hipLaunchKernelGGL((k_heavy2<DD, MM>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
   });
   return hipGetLastError();
 }
@@ -921,6 +922,21 @@ hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_
 hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_rec_gather, dim3((nrec + 255) / 256), dim3(256), 0, st, in, perm, nrec, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_counts(const uint32_t* rcnt, const uint32_t* perm, uint32_t nrec,
+                               uint64_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_stage_counts, dim3((nrec + 255) / 256), dim3(256), 0, st, rcnt, perm, nrec, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rpos, const uint32_t* rcnt,
+                             const uint32_t* perm, const uint64_t* off, uint32_t nrec, uint2* out,
+                             hipStream_t st) {
+  const uint32_t blocks = std::min<uint32_t>((nrec + 3) / 4, 8192u);
+  hipLaunchKernelGGL(k_stage_copy, dim3(blocks ? blocks : 1), dim3(256), 0, st, stage, rpos, rcnt,
+                     perm, off, nrec, out);
   return hipGetLastError();
 }
 

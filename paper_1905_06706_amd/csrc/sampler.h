@@ -30,18 +30,26 @@ struct Sched {
   uint64_t nunits;
   uint32_t chunk;
   uint32_t nchunks;
+  uint32_t pass;       // 0 type-I, 1 split type-I, 2 type-II, 3 segmented type-II
 };
 
-// per-chunk edge counts (count pass) / exclusive offsets (write pass)
-struct PassOut {
-  uint64_t* count;             // count pass: edges of chunk c
-  const uint64_t* base;        // write pass: offset of chunk c within the pass
-  uint64_t add;                // write pass: offset of the pass
-  uint2* edges;
-  unsigned long long* stats;   // 0 tests, 1 draws, 2 candidates, 3 rechecks
+// staged output: waves flush blocks of edges to buf at atomically reserved
+// positions and record (pass, chunk, flush) -> (position, count)
+struct Stage {
+  uint2* buf;
+  uint64_t cap;                  // edges that fit in buf
+  unsigned long long* cursor;    // edges produced so far
+  uint64_t* rkey;                // pass << 58 | chunk << 26 | flush
+  uint64_t* rpos;
+  uint32_t* rcnt;
+  unsigned int* nrec;
+  uint32_t rcap;
+  // 0-1 tests of passes 0-1, 2-3 draws of passes 2-3, 4-5 candidates of
+  // passes 2-3, 6 rechecks, 8-11 edges of passes 0-3
+  unsigned long long* stats;
 };
 
-// deferred items (count pass only): key = chunk << 24 | sequence in chunk
+// deferred items: key = chunk << 24 | sequence in chunk
 struct DeferOut {
   ItemRec* rec;
   uint64_t* key;
@@ -64,21 +72,27 @@ hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort
 
 // sampling passes
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, bool write, const PassOut& po,
-                        const DeferOut& dfo, hipStream_t st);
+                        const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
+                        hipStream_t st);
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev, bool write,
-                        const PassOut& po, const DeferOut& dfo, hipStream_t st);
-// deferred items: units per record (kind 1: test chunks, kind 2: segments)
+                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
+                        const Stage& sg, const DeferOut& dfo, hipStream_t st);
+// deferred items: units per record (kind 1: test pieces, kind 2: segments)
 hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
                             hipStream_t st);
 hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
                              hipStream_t st);
 hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
-                       const uint64_t* uoff, uint32_t nrec, const Sched& sc, bool write,
-                       const PassOut& po, hipStream_t st);
+                       const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Stage& sg,
+                       hipStream_t st);
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
-                         int nlev, bool write, const PassOut& po, hipStream_t st);
+                         int nlev, const Stage& sg, hipStream_t st);
+// staged blocks in record order
+hipError_t launch_stage_counts(const uint32_t* rcnt, const uint32_t* perm, uint32_t nrec,
+                               uint64_t* cnt, hipStream_t st);
+hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rpos, const uint32_t* rcnt,
+                             const uint32_t* perm, const uint64_t* off, uint32_t nrec, uint2* out,
+                             hipStream_t st);
 
 }  // namespace hg
