@@ -84,9 +84,11 @@ def cpu_baseline(wl: dict) -> dict:
         kw = dict(T=wl["T"], c=c, seed=wl["seed"])
     sample = "one full graph (points, constant, sampling)"
     if n > 2**21:
-        # sampled: cell pairs whose level-3 A-side ancestor is 0 mod 16
-        kw.update(filter_level=3, filter_mod=16, filter_rem=0)
-        sample = "points + constant for the full graph; sampling restricted to 1/16 of the level-3 subtrees"
+        # sampled: every item above level 3, and 1/512 of the level-3 subtrees
+        # (A-side ancestor 0 mod 512)
+        kw.update(filter_level=3, filter_mod=512, filter_rem=0)
+        sample = ("points + constant for the full graph; sampling of every cell pair above level 3 "
+                  "and of 1/512 of the level-3 subtrees")
     run = oracle.run(w, x, **kw)
     dt = time.perf_counter() - t0
     m = len(run.edges)

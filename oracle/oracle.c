@@ -765,7 +765,9 @@ static void recur(orc_run* R, int l, uint64_t A, uint64_t B, int nb, int selecte
     }
   }
   if (!nb || l >= R->D) return;
-  /* children of neighbouring pairs (lines 8-9 of the algorithm), A <= B */
+  /* a sampled run: below the filter level the selection is fixed */
+  if (!selected && p->filter_mod && l >= p->filter_level) return;
+  /* children of neighbouring pairs, A <= B */
   if (!any_nonempty(R, l, A) || !any_nonempty(R, l, B)) return;
   int d = p->d;
   uint64_t nch = (uint64_t)1 << d;

@@ -531,8 +531,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint32_t* smort = ar.get<uint32_t>(n);
   uint8_t* slayer = ar.get<uint8_t>(n);
   double* aux = p.model == 1 ? ar.get<double>(3 * n) : nullptr;
+  const bool mixed = p.precision == 1 && p.model == 0 && p.T > 0.0;
+  float* lw = mixed ? ar.get<float>(n) : nullptr;
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
-  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, sx, smort, slayer, aux, st));
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, sx, smort, slayer, aux, lw, st));
   cx.mark("gather", st);
 
   // constant c (App. B.2)
@@ -577,6 +579,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     }
     g.c = c;
     g.kappa = p.T > 0.0 ? std::pow(c, p.T) : std::pow(c, (double)d);
+    if (p.T > 0.0) {
+      g.C32 = (float)(std::log2(c) - g.inv_T * std::log2(g.W));
+      g.invT32 = (float)g.inv_T;
+    }
   }
   cx.mark("c_solve", st);
 
@@ -627,7 +633,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, true, st));
   cx.mark("sources_fill", st);
 
-  Verts v{sw, sx, ids, smort, slayer, aux, nullptr};
+  Verts v{sw, sx, ids, smort, slayer, aux, lw};
   const bool binomial = p.T > 0.0;
   uint64_t n1 = 1, n2 = 1;
   for (int k = 0; k < d; ++k) { n1 *= 3; n2 *= 6; }

@@ -176,7 +176,7 @@ struct Pbar {
   double pbar;  // upper bound of the edge probability for (i, j, level, gap)
   double lg;    // log1p(-pbar)
   int32_t e;    // segment exponent 5 - ilogb(pbar)
-  int32_t pad;
+  float qscale; // 1 / log2(1 - pbar): a skip is log2(S) * qscale (FP32 filter)
 };
 
 struct Graph {
@@ -185,6 +185,8 @@ struct Graph {
   int32_t d, model, L, D, Dmax, bits;  // bits = d * Dmax (Morton width)
   int32_t cl_bias, max_depth, precision;
   double T, c, W, w0, R, coshR, kappa, inv_T, alpha;
+  // mixed precision: log2 p = C32 + invT32 (log2 w_u + log2 w_v - d log2 r)
+  float C32, invT32;
   uint32_t seed_lo, seed_hi;
   // tables (filled by the table kernel)
   int32_t count[kMaxLayers];

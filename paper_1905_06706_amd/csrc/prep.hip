@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
                                                 const double* __restrict__ x, double* __restrict__ sw,
                                                 double* __restrict__ sx, uint32_t* __restrict__ smort,
                                                 uint8_t* __restrict__ slayer,
-                                                double* __restrict__ aux) {
+                                                double* __restrict__ aux, float* __restrict__ lw) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = g->n;
   if (s >= n) return;
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
   for (int k = 0; k < g->d; ++k) sx[(uint64_t)k * n + s] = x[(uint64_t)k * n + u];
   smort[s] = g->bits == 32 ? (uint32_t)key : (uint32_t)(key & ((1ull << g->bits) - 1));
   slayer[s] = (uint8_t)(key >> g->bits);
+  if (lw) lw[s] = (float)log2(wu);
   if (g->model == 1) {
     aux[s] = exp(wu);
     aux[(uint64_t)n + s] = exp(-wu);
@@ -158,9 +159,9 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
 
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* w, const double* x, double* sw, double* sx, uint32_t* smort,
-                         uint8_t* slayer, double* aux, hipStream_t st) {
+                         uint8_t* slayer, double* aux, float* lw, hipStream_t st) {
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, gd, keys, ids, w,
-                     x, sw, sx, smort, slayer, aux);
+                     x, sw, sx, smort, slayer, aux, lw);
   return hipGetLastError();
 }
 
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
       e.pbar = pbar;
       e.lg = log1p(-pbar);
       e.e = pbar > 0.0 ? kSegExp - ilogb(pbar) : 1 << 20;
+      e.qscale = pbar > 0.0 && pbar < 1.0 ? (float)(0.6931471805599453 / e.lg) : 0.0f;
     }
     pb[p] = e;
   }

@@ -112,6 +112,59 @@ __device__ __forceinline__ bool pair_thresh(const Graph* __restrict__ g, const V
 }
 
 // ---------------------------------------------------------------------------
+// mixed precision (GIRG, T > 0).  log2 min(p_uv, 1) is evaluated in FP32 as
+// C + (1/T)(log2 w_u + log2 w_v - d log2 r) with C = log2 c - (1/T) log2 W
+// (per-vertex log2 w rounded from FP64, r exact in FP64 then rounded).  Every
+// term carries a relative error of a few 2^-24 and __log2f one of about 2^-22,
+// so |L32 - log2 p| < 2^-20 (1 + |C| + (1/T)(|lw_u| + |lw_v| + d |log2 r|));
+// the filter decides only outside 2^-13 times that sum (a factor 128 of
+// slack) and re-decides every other pair with the FP64 formula, so the result
+// is the FP64 path's decision.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, const Verts& v, uint32_t su,
+                                           uint32_t sv, double r, float& Lc, float& err) {
+  if (!(r >= 0x1p-100)) return false;  // r = 0 (p = 1) or below FP32 range: FP64
+  const float lr = __log2f((float)r);
+  const float a = v.lw[su], b = v.lw[sv];
+  const float L = g->C32 + g->invT32 * (a + b - (float)D * lr);
+  err = 0x1p-13f * (1.0f + fabsf(g->C32) + g->invT32 * (fabsf(a) + fabsf(b) + (float)D * fabsf(lr)));
+  Lc = fminf(L, 0.0f);
+  return true;
+}
+
+// type-I test: edge iff U < p_uv
+template <int D>
+__device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Verts& v, uint32_t su,
+                                           uint32_t sv, double U, uint64_t& nre) {
+  const double r = torus_r<D>(v.x, g->n, su, sv);
+  float Lc, err;
+  if (U > 0.0 && mixed_logp<D>(g, v, su, sv, r, Lc, err)) {
+    const float lu = __log2f((float)U);
+    if (lu < Lc - err) return true;
+    if (lu > Lc + err) return false;
+  }
+  ++nre;
+  return U < girg_prob<D>(g, v.w[su], v.w[sv], r);
+}
+
+// type-II candidate: accepted iff Acc * pbar < p_uv
+template <int D>
+__device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Verts& v, uint32_t su,
+                                           uint32_t sv, double acc, double pb, uint64_t& nre) {
+  const double r = torus_r<D>(v.x, g->n, su, sv);
+  float Lc, err;
+  if (acc > 0.0 && pb >= 0x1p-120 && mixed_logp<D>(g, v, su, sv, r, Lc, err)) {
+    const float la = __log2f((float)acc) + __log2f((float)pb);
+    const float e2 = err + 0x1p-13f * (1.0f + fabsf(la));
+    if (la < Lc - e2) return true;
+    if (la > Lc + e2) return false;
+  }
+  ++nre;
+  return acc * pb < girg_prob<D>(g, v.w[su], v.w[sv], r);
+}
+
+// ---------------------------------------------------------------------------
 // unit decoding: source (l, s) x neighbour / distant offset -> cell pair
 // ---------------------------------------------------------------------------
 template <int D>
@@ -247,15 +300,16 @@ struct QItem1 {
 
 // type-II item (or one segment of a segmented one): candidates [k, N)
 struct QItem2 {
-  uint32_t A, B, w3, a0, b0, nb, t, pad;
+  uint32_t A, B, w3, a0, b0, nb, t;
+  float qs;  // 1 / log2(1 - pbar)
   uint64_t k, N;
   double pb, lg;
 };
 
-// type-II candidate: sorted indices and Acc * pbar
+// type-II candidate: sorted indices, Acc and pbar
 struct Cand {
   uint32_t su, sv;
-  double apb;
+  double acc, pb;
 };
 
 // phase A: decode units until 64 valid pairs are buffered or the chunk ends
@@ -311,10 +365,11 @@ struct Ring1 {
   uint32_t bc, bt;  // next Philox block to process / end of the queued blocks
 };
 
-template <int D, int MODEL, bool T0>
+template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Verts& v,
                                            const QItem1& it, uint64_t k, uint64_t kend, bool& e0,
-                                           bool& e1, uint2& p0, uint2& p1, uint64_t& ntests) {
+                                           bool& e1, uint2& p0, uint2& p1, uint64_t& ntests,
+                                           uint64_t& nre) {
   const bool tri = it.tri != 0;
   uint32_t a, b;
   if (tri) {
@@ -343,7 +398,8 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
         e = pair_thresh<D, MODEL>(g, v, su, sv);
       } else {
         const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
-        e = U < pair_prob<D, MODEL>(g, v, su, sv);
+        if constexpr (MX) e = mixed_test<D>(g, v, su, sv, U, nre);
+        else e = U < pair_prob<D, MODEL>(g, v, su, sv);
       }
       if (e) {
         if (h == 0) p0 = make_uint2(v.id[su], v.id[sv]);
@@ -362,10 +418,10 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
 }
 
 // one converged step over up to 64 queued Philox blocks
-template <int D, int MODEL, bool T0>
+template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& v,
                                       const QItem1* __restrict__ q, Ring1& r, const Stage& sg,
-                                      Out& out, uint64_t& ntests) {
+                                      Out& out, uint64_t& ntests, uint64_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.bt - r.bc;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -383,7 +439,7 @@ __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& 
     const uint64_t tot = it.tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
     const uint64_t kb = (uint64_t)it.kb + (gb - it.cs);
     const uint64_t kend = 2ull * ((uint64_t)it.kb + it.nbk) < tot ? 2ull * ((uint64_t)it.kb + it.nbk) : tot;
-    test_block<D, MODEL, T0>(g, v, it, 2ull * kb, kend, e0, e1, p0, p1, ntests);
+    test_block<D, MODEL, T0, MX>(g, v, it, 2ull * kb, kend, e0, e1, p0, p1, ntests, nre);
   }
   emit(e0, e1, p0, p1, sg, out);
   r.bc += take;
@@ -416,7 +472,7 @@ __device__ __forceinline__ void enqueue1(bool enq, QItem1& it, QItem1* __restric
 }
 
 // type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3)
-template <int D, int MODEL, bool T0>
+template <int D, int MODEL, bool T0, bool MX>
 __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
                                                const Src* __restrict__ src, Sched sc, Stage sg,
@@ -428,7 +484,7 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
   VUnit* vb = vbs[wv];
   QItem1* q = qs[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0;
+  uint64_t ntests = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -458,7 +514,7 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
       while (__any(jm != 0)) {
         // room for 64 more items; consume blocks when there are several steps of them
         while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-          step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+          step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
         bool enq = false, big = false;
         QItem1 it{};
         ItemRec rec{};
@@ -484,15 +540,19 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
         enqueue1(enq, it, q, r);
       }
     }
-    while (r.bc < r.bt) step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
     flush(sg, out);
   }
   ntests = wave_sum(ntests);
-  if (lane == 0) atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
+  nre = wave_sum(nre);
+  if (lane == 0) {
+    atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
+    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+  }
 }
 
 // split type-I items: pieces of kTestChunk tests (kTestChunk / 2 blocks)
-template <int D, int MODEL, bool T0>
+template <int D, int MODEL, bool T0, bool MX>
 __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts v,
                                               const ItemRec* __restrict__ rec,
                                               const uint64_t* __restrict__ uoff, uint32_t nrec,
@@ -502,7 +562,7 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
   const uint32_t wv = threadIdx.x / kWave;
   QItem1* q = qs[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0;
+  uint64_t ntests = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -512,7 +572,7 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-        step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+        step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
       const uint64_t u = u0 + lane;
       bool enq = false;
       QItem1 it{};
@@ -535,11 +595,15 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
       }
       enqueue1(enq, it, q, r);
     }
-    while (r.bc < r.bt) step1<D, MODEL, T0>(g, v, q, r, sg, out, ntests);
+    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
     flush(sg, out);
   }
   ntests = wave_sum(ntests);
-  if (lane == 0) atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
+  nre = wave_sum(nre);
+  if (lane == 0) {
+    atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
+    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -555,18 +619,55 @@ struct Ring2 {
 
 // one geometric draw without the candidate test: X ~ Geom_0(pbar) candidates
 // are skipped (X = floor(ln S / ln(1 - pbar))); returns true with the
-// candidate's sorted indices and Acc * pbar when it lies in the range
+// candidate's sorted indices when it lies in the range.  Mixed precision:
+// log2 S in FP32 (a series in the exact 1 - S near S = 1, else __log2f; both
+// within a few 2^-22 relative), times 1 / log2(1 - pbar); X and the end test
+// are taken from it only when both ends of a 2^-13 relative interval agree,
+// otherwise from the FP64 quotient.
+template <bool MX>
 __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, bool& done,
-                                         Cand& cd) {
+                                         Cand& cd, uint64_t& nre) {
   const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
   ++it.t;
-  const double S = u53_open(o.x, o.y);
-  const double q = it.pb >= 1.0 ? 0.0 : log(S) / it.lg;
-  if (q >= (double)(it.N - it.k)) {
+  const uint64_t vv = (((uint64_t)o.y << 32) | o.x) >> 11;
+  const double S = (double)(vv + 1) * 0x1p-53;
+  const uint64_t rem = it.N - it.k;
+  uint64_t skip = 0;
+  bool end = false, decided = false;
+  if (it.pb >= 1.0) {
+    decided = true;  // every candidate is drawn
+  } else if (MX) {
+    const uint64_t om = (1ull << 53) - 1 - vv;  // (1 - S) 2^53, exact
+    float l2s = 0.0f;
+    if (om) {
+      const float t = (float)om * 0x1p-53f;
+      if (t < 0.0625f)
+        l2s = -t * (1.0f + t * (0.5f + t * (0.33333334f + t * (0.25f + t * 0.2f)))) * 1.44269504f;
+      else
+        l2s = __log2f((float)S);
+    }
+    const double q32 = (double)(l2s * it.qs);
+    const double qe = 0x1p-13 * (q32 + 1.0);
+    const double qlo = q32 - qe > 0.0 ? q32 - qe : 0.0, qhi = q32 + qe;
+    if (qlo >= (double)rem) {
+      end = true;
+      decided = true;
+    } else if (qhi < (double)rem && floor(qlo) == floor(qhi)) {
+      skip = (uint64_t)qhi;
+      decided = true;
+    }
+  }
+  if (!decided) {
+    if (MX) ++nre;
+    const double q = log(S) / it.lg;
+    if (q >= (double)rem) end = true;
+    else skip = (uint64_t)q;
+  }
+  if (end) {
     done = true;
     return false;
   }
-  it.k += (uint64_t)q;
+  it.k += skip;
   uint32_t aa, bb;
   if (it.k < 0xFFFFFFFFull) {
     aa = (uint32_t)it.k / it.nb;
@@ -577,17 +678,18 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   }
   cd.su = it.a0 + aa;
   cd.sv = it.b0 + bb;
-  cd.apb = u53(o.z, o.w) * it.pb;
+  cd.acc = u53(o.z, o.w);
+  cd.pb = it.pb;
   ++it.k;
   done = it.k >= it.N;
   return true;
 }
 
 // evaluate up to 64 queued candidates (accept iff Acc * pbar < p_uv)
-template <int D, int MODEL>
+template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Verts& v,
                                            const Cand* __restrict__ cq, Ring2& r, const Stage& sg,
-                                           Out& out) {
+                                           Out& out, uint64_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.ct - r.ch;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -595,7 +697,8 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
   uint2 p0 = make_uint2(0, 0);
   if (lane < take) {
     const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
-    e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
+    if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.acc, cd.pb, nre);
+    else e0 = cd.acc * cd.pb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
     if (e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
   }
   emit(e0, false, p0, p0, sg, out);
@@ -604,12 +707,12 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
 
 // draw steps: lanes own items (dequeued from the ring), one draw per step;
 // runs while at least `need` items are queued or held (to the end if 0)
-template <int D, int MODEL>
+template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts& v,
                                        const QItem2* __restrict__ q, Cand* __restrict__ cq,
                                        Ring2& r, bool& act, QItem2& it, uint32_t need,
                                        const Stage& sg, Out& out, uint64_t& ndraws,
-                                       uint64_t& ncand) {
+                                       uint64_t& ncand, uint64_t& nre) {
   const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
   for (;;) {
     const uint64_t mi = __ballot(!act);
@@ -627,10 +730,10 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     r.qh += got < avail ? got : avail;
     if (!__any(act)) break;
     bool hc = false;
-    Cand cd{0, 0, 0.0};
+    Cand cd{0, 0, 0.0, 0.0};
     if (act) {
       bool done = false;
-      hc = geo_draw(k0s, k1s, it, done, cd);
+      hc = geo_draw<MX>(k0s, k1s, it, done, cd, nre);
       ++ndraws;
       if (done) act = false;
     }
@@ -638,7 +741,7 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
     r.ct += (uint32_t)__popcll(mc);
     ncand += hc ? 1 : 0;
-    if (r.ct - r.ch >= 64) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
+    if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
   }
 }
 
@@ -651,7 +754,7 @@ __device__ __forceinline__ void enqueue2(bool enq, const QItem2& it, QItem2* __r
 
 // type-II pass: distant cell pairs with neighbouring parents at levels
 // l <= CL(i,j); items of one segment are sampled here, others deferred
-template <int D, int MODEL>
+template <int D, int MODEL, bool MX>
 __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
                                                const Src* __restrict__ src, Sched sc,
@@ -667,7 +770,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
   Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
   const int L = g->L;
-  uint64_t ndraws = 0, ncand = 0;
+  uint64_t ndraws = 0, ncand = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -698,7 +801,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
       const uint32_t gp = mu.gap;
       while (__any(jm != 0)) {
         if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-          draws2<D, MODEL>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand);
+          draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
         bool enq = false, hv = false;
         QItem2 it{};
         ItemRec rec{};
@@ -718,7 +821,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
                               lvl | (li << 8) | (lj << 16) | (gp << 24), (uint32_t)pe.e};
                 hv = true;
               } else {
-                it = QItem2{A, mu.B, ctr_word3(lvl, li, lj, kKindType2, 0), a0, b0, nb, 0u, 0u,
+                it = QItem2{A, mu.B, ctr_word3(lvl, li, lj, kKindType2, 0), a0, b0, nb, 0u, pe.qscale,
                             0ull, N, pe.pbar, pe.lg};
                 enq = true;
               }
@@ -729,21 +832,23 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
         enqueue2(enq, it, q, r);
       }
     }
-    draws2<D, MODEL>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand);
-    while (r.ct != r.ch) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
+    draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand, nre);
+    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
     flush(sg, out);
   }
   ndraws = wave_sum(ndraws);
   ncand = wave_sum(ncand);
+  nre = wave_sum(nre);
   if (lane == 0) {
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
     atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
     atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
+    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
   }
 }
 
 // segmented type-II items: one segment per unit
-template <int D, int MODEL>
+template <int D, int MODEL, bool MX>
 __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Verts v,
                                                 const ItemRec* __restrict__ rec,
                                                 const uint64_t* __restrict__ uoff, uint32_t nrec,
@@ -757,7 +862,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
   Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
   const int L = g->L;
-  uint64_t ndraws = 0, ncand = 0;
+  uint64_t ndraws = 0, ncand = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -769,7 +874,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-        draws2<D, MODEL>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand);
+        draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
       const uint64_t u = u0 + lane;
       bool enq = false;
       QItem2 it{};
@@ -789,21 +894,23 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
         segment_size(N, (int)rr.e, &G, &ns);
         const uint64_t k0 = s * G, kend = (s + 1) * G < N ? (s + 1) * G : N;
         it = QItem2{rr.A, rr.B, ctr_word3(lvl, li, lj, kKindType2, (uint32_t)s), rr.a0, rr.b0, rr.nb,
-                    0u, 0u, k0, kend, pe.pbar, pe.lg};
+                    0u, pe.qscale, k0, kend, pe.pbar, pe.lg};
         enq = true;
       }
       enqueue2(enq, it, q, r);
     }
-    draws2<D, MODEL>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand);
-    while (r.ct != r.ch) eval_cands<D, MODEL>(g, v, cq, r, sg, out);
+    draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand, nre);
+    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
     flush(sg, out);
   }
   ndraws = wave_sum(ndraws);
   ncand = wave_sum(ncand);
+  nre = wave_sum(nre);
   if (lane == 0) {
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
     atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
     atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
+    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
   }
 }
 
@@ -869,14 +976,20 @@ __global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ st
     }                                                                              \
   } while (0)
 
+// mixed precision applies to the binomial GIRG only
+static bool use_mixed(const Graph& g) { return g.precision == 1 && g.model == 0 && g.T > 0.0; }
+
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
                         const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
                         hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  const bool t0 = !(g.T > 0.0);
+  const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
-    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
-    else hipLaunchKernelGGL((k_type1<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+    else if constexpr (MM == 0) {
+      if (mx) hipLaunchKernelGGL((k_type1<DD, 0, false, true>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+      else hipLaunchKernelGGL((k_type1<DD, 0, false, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+    } else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
   });
   return hipGetLastError();
 }
@@ -885,10 +998,13 @@ hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const It
                        const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Stage& sg,
                        hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
-  const bool t0 = !(g.T > 0.0);
+  const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
-    if (t0) hipLaunchKernelGGL((k_big1<DD, MM, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
-    else hipLaunchKernelGGL((k_big1<DD, MM, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
+    if (t0) hipLaunchKernelGGL((k_big1<DD, MM, true, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
+    else if constexpr (MM == 0) {
+      if (mx) hipLaunchKernelGGL((k_big1<DD, 0, false, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
+      else hipLaunchKernelGGL((k_big1<DD, 0, false, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
+    } else hipLaunchKernelGGL((k_big1<DD, MM, false, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
   });
   return hipGetLastError();
 }
@@ -897,8 +1013,12 @@ hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const u
                         const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
                         const Stage& sg, const DeferOut& dfo, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
+  const bool mx = use_mixed(g);
   HG_DISPATCH_D({
-    hipLaunchKernelGGL((k_type2<DD, MM>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
+    if constexpr (MM == 0) {
+      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
+      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
+    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
   });
   return hipGetLastError();
 }
@@ -907,8 +1027,12 @@ hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const 
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
                          int nlev, const Stage& sg, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
+  const bool mx = use_mixed(g);
   HG_DISPATCH_D({
-    hipLaunchKernelGGL((k_heavy2<DD, MM>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
+    if constexpr (MM == 0) {
+      if (mx) hipLaunchKernelGGL((k_heavy2<DD, 0, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
+      else hipLaunchKernelGGL((k_heavy2<DD, 0, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
+    } else hipLaunchKernelGGL((k_heavy2<DD, MM, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
   });
   return hipGetLastError();
 }

@@ -62,7 +62,7 @@ hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const do
                             uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st);
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* w, const double* x, double* sw, double* sx, uint32_t* smort,
-                         uint8_t* slayer, double* aux, hipStream_t st);
+                         uint8_t* slayer, double* aux, float* lw, hipStream_t st);
 hipError_t launch_tables(Graph* gd, int Dcap, Pbar* pb, hipStream_t st);
 hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* smort,
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);

@@ -29,6 +29,7 @@ def run_both(hg, orc, w, x, *, T, c, seed, model=0, R=0.0, alpha=0.0, **kw):
     print(f"[parity] n={len(w)} d={x.shape[1]} T={T} c={c} seed={seed} model={model} {kw}", flush=True)
     res = hg.from_points(dev(w), dev(x.T), T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, **kw)
     ge = res.edges.cpu().numpy().view(np.uint32)
+    kw.pop("precision", None)  # the oracle decides in FP64 only
     run = orc.run(w, x, T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, keep=True, **kw)
     return ge, res.info, run
 
@@ -168,3 +169,43 @@ def test_empty_and_tiny_graphs(hg, orc):
     x = synth.positions(64, 3, 1)
     ge, info, run = run_both(hg, orc, w, x, T=0.0, c=1e-9, seed=1)
     assert len(ge) == 0 and len(run.edges) == 0
+
+
+@pytest.mark.parametrize("d,n,beta,T,seed", [(1, 2**16, 2.5, 0.5, 21), (2, 2**17, 2.7, 0.5, 22),
+                                             (3, 2**17, 2.3, 0.8, 23), (4, 2**15, 2.6, 0.3, 24),
+                                             (2, 2**16, 2.1, 0.9, 25)])
+def test_mixed_precision_equals_fp64(hg, d, n, beta, T, seed):
+    """precision = 1 (FP32 filter, FP64 recheck near the boundary) gives the
+    FP64 edge array bit for bit, and reports its rechecks."""
+    print(f"[mixed] d={d} n={n} beta={beta} T={T} seed={seed}", flush=True)
+    kw = dict(d=d, beta=beta, T=T, avg_deg=16.0, seed=seed)
+    a = hg.generate(n, precision=0, **kw)
+    b = hg.generate(n, precision=1, **kw)
+    assert np.array_equal(a.edges.cpu().numpy(), b.edges.cpu().numpy())
+    assert a.info["rechecks"] == 0 and b.info["rechecks"] > 0
+    for k in ("tests", "draws", "candidates", "type1_edges", "type2_edges"):
+        assert a.info[k] == b.info[k], k
+
+
+@pytest.mark.parametrize("d,T,seed", [(2, 0.5, 31), (3, 0.8, 32), (1, 0.2, 33)])
+def test_mixed_precision_from_points(hg, orc, d, T, seed):
+    """Mixed precision on clustered positions (many small distances) and
+    heavy-tailed weights against the oracle."""
+    n = 12000
+    w = synth.pareto_weights(n, 2.1, seed)
+    x = synth.clustered_positions(n, d, seed)
+    c = orc.solve_c(w, d, T, 14.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=seed, precision=1)
+    compare(ge, run)
+    assert info["rechecks"] > 0
+    assert info["draws"] == run.stats["draws"]
+    assert info["candidates"] == run.stats["candidates"]
+
+
+def test_mixed_precision_ignored_where_undefined(hg):
+    """Threshold graphs and HRGs have no FP32 filter: precision = 1 runs the
+    FP64 decisions and reports no rechecks."""
+    a = hg.generate(20000, d=2, beta=2.5, T=0.0, avg_deg=10.0, seed=3, precision=0)
+    b = hg.generate(20000, d=2, beta=2.5, T=0.0, avg_deg=10.0, seed=3, precision=1)
+    assert np.array_equal(a.edges.cpu().numpy(), b.edges.cpu().numpy())
+    assert b.info["rechecks"] == 0
