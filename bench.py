@@ -42,11 +42,45 @@ DEFAULT = "girg_d2_n2p20"
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-operations per second, in T
 
-# algorithmic VALU lane-operations per unit of work (derivation in the design doc)
+# algorithmic VALU lane-operations per unit of work (estimates from the
+# operation counts of each decision; the counters show the issued totals)
 OPS_TEST_T0 = 15.0      # threshold test: torus distance, product, compare
 OPS_TEST_BINOM = 120.0  # binomial test: distance, pow (log + exp), half a Philox block, compare
 OPS_DRAW = 80.0         # geometric draw: one Philox block, one log, divide, compare
 OPS_CAND = 70.0         # candidate: distance, pow, compare
+
+
+# sources of the sampling kernels: HBM byte counters in profiles/ hold for
+# the kernels built from sources with this hash only
+KERNEL_SOURCES = ["paper_1905_06706_amd/csrc/sample.hip", "paper_1905_06706_amd/csrc/device_common.h",
+                  "paper_1905_06706_amd/csrc/sampler.h"]
+STAGE_KERNEL = {"type1": "k_type1<", "split1": "k_big1<", "type2": "k_type2<", "segments2": "k_heavy2<"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, stage: str):
+    """HBM bytes per launch of the stage's kernel (FETCH_SIZE + WRITE_SIZE,
+    each scaled by a plain copy's reading) from the committed rocprofv3
+    summary, or None when there is none or the kernels changed since."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"hbm_bytes_{workload}.txt")
+    if not os.path.exists(path) or stage not in STAGE_KERNEL:
+        return None
+    want = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"traffic (.+) bytes_per_launch=(\d+) source_sha=(\w+)", line)
+            if m and m.group(1).startswith(STAGE_KERNEL[stage]) and m.group(3) == want:
+                return int(m.group(2))
+    return None
 
 
 def make_call(hg, wl: dict):
@@ -96,6 +130,27 @@ def cpu_baseline(wl: dict) -> dict:
             "sample": f"{sample}; {m} edges in {dt:.2f} s"}
 
 
+def hbm_copy(mib: int, steps: int, warmup: int) -> int:
+    """A plain device-to-device copy of a known size: the reference that
+    scales the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of the sampling
+    kernels, and the achievable copy bandwidth."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "steps": steps,
+                      "ms_per_copy": dt * 1e3, "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,11 +158,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hbm-copy", type=int, default=0, metavar="MIB",
+                    help="only time a plain device copy of MIB MiB (HBM calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this sampler has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler has no "
+              "multi-GPU path", file=sys.stderr)
         return 2
+    if args.hbm_copy:
+        return hbm_copy(args.hbm_copy, args.steps, args.warmup)
 
     import torch
     import paper_1905_06706_amd as hg
@@ -164,9 +223,10 @@ def main() -> int:
         units = {"draws": info_d["pass_work"][q], "candidates": info_d["pass_cands"][q]}
         ops = units["draws"] * OPS_DRAW + units["candidates"] * OPS_CAND
     achieved = ops / (dom_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS,
-            "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-            "launch_ms": dom_ms, "units_per_launch": units}
+    roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom] + "...>", "achieved": achieved,
+            "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": profiled_traffic(args.workload, dom), "launch_ms": dom_ms,
+            "units_per_launch": units, "ops_per_launch": ops}
     value = edges / dt
     out = {
         "metric": METRIC,

@@ -1,6 +1,6 @@
 """Python access to the plain C oracle (``oracle.c``).
 
-TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+TEST INFRASTRUCTURE.  Only ``tests/``, the smoke check and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
 code with the HIP library (``paper_1905_06706_amd``) and never imports it.
 

@@ -13,7 +13,7 @@
  *   sampled by geometric jumps under an upper bound pbar and accepted with
  *   p_uv / pbar (Sec. 3.2).
  * Nothing is blocked, fused or reordered.  The readings taken where the paper
- * is silent are listed in the design doc and restated briefly at each use.
+ * is silent are restated briefly at each use.
  */
 #define _GNU_SOURCE
 #include "oracle.h"

@@ -66,7 +66,8 @@ void orc_points_hrg(uint64_t n, double alpha, double R, uint64_t seed, double* r
 double orc_expected_avg_degree(uint64_t n, int d, double T, double c, const double* w);
 int orc_solve_c(uint64_t n, int d, double T, double avg_deg, const double* w, double* c_out);
 /* HRG: expected average degree for radius R (numerical integration) and its
- * inverse by bisection.  Not in the paper; see the readings in the design doc. */
+ * inverse by root finding.  The paper gives no formula for R from the
+ * average degree: the integral is taken over the model of Sec. 2.2. */
 double orc_hrg_expected_avg_degree(uint64_t n, double alpha, double T, double R);
 int orc_hrg_solve_R(uint64_t n, double alpha, double T, double avg_deg, double* R_out);
 
