@@ -84,6 +84,7 @@ struct Ctx {
   uint32_t* flag = nullptr;
   unsigned long long* stats = nullptr;  // 16
   unsigned int* hcount = nullptr;
+  uint32_t* dtab[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // distant offsets per d
   std::mutex mu;
   // stage timing (HIP events on the call's stream), enabled by girg_set_profiling
   bool profiling = false;
@@ -120,6 +121,8 @@ struct Ctx {
     if (flag) (void)hipFree(flag);
     if (stats) (void)hipFree(stats);
     if (hcount) (void)hipFree(hcount);
+    for (auto t : dtab)
+      if (t) (void)hipFree(t);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -609,7 +612,15 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   }
   g.cells = cells;
   if (cells >= 0xFFFFFFFFull * 4) return fail(GIRG_ENOMEM, "too many cells");
+  // layer masks per level up to the deepest insertion level
+  int maxI = 0;
+  for (int i = 0; i < g.L; ++i)
+    if (g.count[i] > 0 && g.I[i] > maxI) maxI = g.I[i];
+  g.moff[0] = 0;
+  for (int l = 0; l < kMaxLevels; ++l)
+    g.moff[l + 1] = g.moff[l] + (l <= maxI ? (1ull << (d * l)) : 0ull);
   HIPCHK(hipMemcpyAsync(cx.gd->pbase, g.pbase, sizeof(g.pbase), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(cx.gd->moff, g.moff, sizeof(g.moff), hipMemcpyHostToDevice, st));
   uint32_t* P = ar.get<uint32_t>(cells);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (cells)");
   cx.mark("-", st);
@@ -621,22 +632,31 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   // run sources
   uint32_t* scnt = ar.get<uint32_t>(n + 1);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
-  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, scnt, nullptr, nullptr, false, st));
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, scnt, nullptr, nullptr, nullptr, false, st));
   HIPCHK(scan_u32(ar, scnt, scnt, n, scnt + n, st));
   cx.mark("sources_count", st);
   uint32_t nsrc = 0;
   HIPCHK(hipMemcpyAsync(&nsrc, scnt + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   Src* src = ar.get<Src>(std::max<uint64_t>(nsrc, 1));
+  uint64_t* masks = ar.get<uint64_t>(g.moff[kMaxLevels]);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
   cx.mark("-", st);
-  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, true, st));
+  HIPCHK(hipMemsetAsync(masks, 0, g.moff[kMaxLevels] * sizeof(uint64_t), st));
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, masks, true, st));
   cx.mark("sources_fill", st);
+  if (!cx.dtab[d]) {
+    const std::vector<uint32_t> tab = distant_table(d);
+    uint32_t* t = nullptr;
+    HIPCHK(hipMalloc(&t, tab.size() * sizeof(uint32_t)));
+    HIPCHK(hipMemcpy(t, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    cx.dtab[d] = t;
+  }
 
   Verts v{sw, sx, ids, smort, slayer, aux, lw};
   const bool binomial = p.T > 0.0;
-  uint64_t n1 = 1, n2 = 1;
-  for (int k = 0; k < d; ++k) { n1 *= 3; n2 *= 6; }
+  uint64_t n1 = 1;
+  for (int k = 0; k < d; ++k) n1 *= 3;
 
   // staging of the edges: capacity = the caller's; flush records
   unsigned int* tickets = ar.get<unsigned int>(8);
@@ -651,8 +671,15 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
     return sc;
   };
+  // type-II chunks are runs of whole sources
+  auto make_sched_src = [&](uint64_t nunits, int pass) {
+    uint64_t ch = (nunits + 32767) / 32768;
+    ch = std::max<uint64_t>(1, std::min<uint64_t>(64, ch));
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
+    return sc;
+  };
   Sched sch[4] = {make_sched(nsrc ? nsrc * n1 : 0, 0), make_sched(0, 1),
-                  make_sched(binomial && nsrc ? nsrc * n2 : 0, 2), make_sched(0, 3)};
+                  make_sched_src(binomial ? nsrc : 0, 2), make_sched(0, 3)};
   uint2* stage = cap ? ar.get<uint2>(cap) : nullptr;
   // every flush but the last of a chunk holds more than 128 edges
   const uint64_t rcap64 = cap / 128 + 2ull * (sch[0].nchunks + sch[2].nchunks) + (1u << 16);
@@ -686,7 +713,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     cx.mark("-", st);
     if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], sg, df0, st));
     cx.mark("type1", st);
-    if (sch[2].nchunks) HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, sg, df1, st));
+    if (sch[2].nchunks)
+      HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, masks, cx.dtab[d], sg, df1, st));
     cx.mark("type2", st);
     HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -198,6 +198,9 @@ struct Graph {
   uint64_t jI[kMaxLayers][kMaxLevels];   // j with CL(i,j) == level
   uint64_t jII[kMaxLayers][kMaxLevels];  // j with CL(i,j) >= level
   uint64_t cells;                   // total prefix-sum entries
+  // layer masks: masks[moff[l] + A] has bit j set iff V_j^A is nonempty at
+  // level l (levels up to max_i I(i))
+  uint64_t moff[kMaxLevels + 1];
 };
 
 // Sorted vertex arrays (structure of arrays).
@@ -208,7 +211,7 @@ struct Verts {
   const uint32_t* mort; // Morton code at level Dmax
   const uint8_t* layer;
   const double* aux;    // HRG: [3][n] = e^r, e^-r, sinh r ; GIRG mixed: [n] log2 w (as double)
-  const float* lw;      // mixed precision: log2(w / W) per vertex (FP32)
+  const float* lw;      // mixed precision: log2 w per vertex (FP32)
 };
 
 }  // namespace hg

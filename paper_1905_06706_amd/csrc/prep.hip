@@ -315,7 +315,8 @@ __global__ __launch_bounds__(256) void k_src_fill(const Graph* __restrict__ g,
                                                   const uint8_t* __restrict__ slayer,
                                                   const uint32_t* __restrict__ P,
                                                   const uint32_t* __restrict__ off,
-                                                  Src* __restrict__ src) {
+                                                  Src* __restrict__ src,
+                                                  unsigned long long* __restrict__ masks) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g->n) return;
   const int h = head_level(g, smort, slayer, (uint32_t)s);
@@ -329,17 +330,20 @@ __global__ __launch_bounds__(256) void k_src_fill(const Graph* __restrict__ g,
     const int sh = g->d * (I - l);
     const uint32_t end = Pi[((uint64_t)A + 1) << sh];
     src[o++] = Src{(uint32_t)s, A, end - (uint32_t)s, (uint32_t)l | ((uint32_t)i << 8)};
+    atomicOr(&masks[g->moff[l] + A], 1ull << i);
   }
 }
 
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
                           const uint8_t* slayer, const uint32_t* P, uint32_t* cnt,
-                          const uint32_t* off, Src* src, bool fill, hipStream_t st) {
+                          const uint32_t* off, Src* src, uint64_t* masks, bool fill,
+                          hipStream_t st) {
   const unsigned blocks = (unsigned)((g.n + 255) / 256);
   if (!fill)
     hipLaunchKernelGGL(k_src_count, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, cnt);
   else
-    hipLaunchKernelGGL(k_src_fill, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, P, off, src);
+    hipLaunchKernelGGL(k_src_fill, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, P, off, src,
+                       reinterpret_cast<unsigned long long*>(masks));
   return hipGetLastError();
 }
 

@@ -752,86 +752,203 @@ __device__ __forceinline__ void enqueue2(bool enq, const QItem2& it, QItem2* __r
   r.qt += (uint32_t)__popcll(me);
 }
 
-// type-II pass: distant cell pairs with neighbouring parents at levels
-// l <= CL(i,j); items of one segment are sampled here, others deferred
+// type-II pass.  A wave walks whole sources (layer i, level l, cell X) of
+// its chunk.  Lanes take the cells Y distant from X whose parents neighbour
+// X's parent: at levels >= 3 from the table of offsets with a positive first
+// nonzero component (each unordered pair once), at levels <= 2 from all
+// 6^d children, deduplicated, with Y > X.  The layer mask of Y restricted to
+// {j : CL(i,j) >= l} lists the nonempty items; they are expanded into an
+// LDS list and taken 64 at a time.  An item is oriented with the smaller cell
+// as its A side (App. B.1), makes its first draw at once, and is queued for
+// more draws only if its range is not exhausted.
+constexpr int kICap = 128;  // item list (>= 2 x 64)
+
+struct IEnt {
+  uint32_t sidx;  // source of the X side
+  uint32_t Y;     // the other cell
+  uint32_t jg;    // layer j of the Y side | gap << 8
+  uint32_t pad;
+};
+
+template <int D, int MODEL, bool MX>
+__device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const Verts& v,
+                                            const uint32_t* __restrict__ P,
+                                            const Src* __restrict__ src,
+                                            const Pbar* __restrict__ pbt, int nlev, IEnt* ib,
+                                            uint32_t& in, QItem2* __restrict__ q,
+                                            Cand* __restrict__ cq, Ring2& r, bool& act,
+                                            QItem2& cur, uint32_t chunk, uint32_t& dseq,
+                                            const DeferOut& dfo, const Stage& sg, Out& out,
+                                            uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
+  const uint32_t lane = lane_id();
+  const uint32_t take = in < 64 ? in : 64;
+  const bool have = lane < take;
+  IEnt e{0, 0, 0, 0};
+  if (have) e = ib[lane];
+  const uint32_t rest = in - take;
+  IEnt tmp{0, 0, 0, 0};
+  if (lane < rest) tmp = ib[take + lane];
+  if (lane < rest) ib[lane] = tmp;
+  in = rest;
+
+  bool fresh = false, hv = false;
+  QItem2 it{};
+  ItemRec rec{};
+  if (have) {
+    const Src sr = src[e.sidx];
+    const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
+    const uint32_t lj = e.jg & 255u, gp = (e.jg >> 8) & 255u;
+    uint32_t b0, nb;
+    cell_range(g, P, (int)lj, (int)lvl, e.Y, &b0, &nb);
+    // orientation: the smaller cell is the A side
+    const bool fwd = e.Y > sr.A;
+    const uint32_t cA = fwd ? sr.A : e.Y, cB = fwd ? e.Y : sr.A;
+    const uint32_t ci = fwd ? li : lj, cj = fwd ? lj : li;
+    const uint32_t ca0 = fwd ? sr.s : b0, cna = fwd ? sr.na : nb;
+    const uint32_t cb0 = fwd ? b0 : sr.s, cnb = fwd ? nb : sr.na;
+    const Pbar pe = pbt[(((uint64_t)ci * g->L + cj) * nlev + lvl) * 2 + (gp - 1)];
+    if (pe.pbar > 0.0 && nb > 0) {
+      const uint64_t N = (uint64_t)cna * cnb;
+      uint64_t G, nseg;
+      segment_size(N, pe.e, &G, &nseg);
+      if (nseg > 1) {
+        rec = ItemRec{ca0, cna, cb0, cnb, cA, cB, lvl | (ci << 8) | (cj << 16) | (gp << 24),
+                      (uint32_t)pe.e};
+        hv = true;
+      } else {
+        it = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), ca0, cb0, cnb, 0u, pe.qscale,
+                    0ull, N, pe.pbar, pe.lg};
+        fresh = true;
+      }
+    }
+  }
+  if (__any(hv)) defer_item(hv, rec, chunk, dseq, dfo);
+  // first draw of every new item
+  bool hc = false, cont = false;
+  Cand cd{0, 0, 0.0, 0.0};
+  if (fresh) {
+    bool done = false;
+    hc = geo_draw<MX>(g->seed_lo, g->seed_hi, it, done, cd, nre);
+    ++ndraws;
+    cont = !done;
+  }
+  const uint64_t mc = __ballot(hc);
+  if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
+  r.ct += (uint32_t)__popcll(mc);
+  ncand += hc ? 1 : 0;
+  if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
+  if (__any(cont)) {
+    if (r.qt - r.qh > (uint32_t)(kQCap - 64))
+      draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
+    enqueue2(cont, it, q, r);
+  }
+}
+
+// append the items of mask m (lane's cell Y, gap) to the list; take 64 when full
+template <int D, int MODEL, bool MX>
+__device__ __forceinline__ void push_items2(uint64_t m, uint32_t sidx, uint32_t Y, uint32_t gap,
+                                            const Graph* __restrict__ g, const Verts& v,
+                                            const uint32_t* __restrict__ P,
+                                            const Src* __restrict__ src,
+                                            const Pbar* __restrict__ pbt, int nlev, IEnt* ib,
+                                            uint32_t& in, QItem2* __restrict__ q,
+                                            Cand* __restrict__ cq, Ring2& r, bool& act,
+                                            QItem2& cur, uint32_t chunk, uint32_t& dseq,
+                                            const DeferOut& dfo, const Stage& sg, Out& out,
+                                            uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
+  while (__any(m != 0)) {
+    const bool has = m != 0;
+    uint32_t j = 0;
+    if (has) {
+      j = (uint32_t)__ffsll((long long)m) - 1;
+      m &= m - 1;
+    }
+    const uint64_t mb = __ballot(has);
+    if (has) ib[in + lanes_below(mb)] = IEnt{sidx, Y, j | (gap << 8), 0u};
+    in += (uint32_t)__popcll(mb);
+    if (in >= 64)
+      take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, chunk, dseq,
+                                dfo, sg, out, ndraws, ncand, nre);
+  }
+}
+
 template <int D, int MODEL, bool MX>
 __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
                                                const Src* __restrict__ src, Sched sc,
-                                               const Pbar* __restrict__ pbt, int nlev, Stage sg,
+                                               const Pbar* __restrict__ pbt, int nlev,
+                                               const uint64_t* __restrict__ masks,
+                                               const uint32_t* __restrict__ dtab, Stage sg,
                                                DeferOut dfo) {
-  __shared__ VUnit vbs[4][kVCap];
+  __shared__ IEnt ibs[4][kICap];
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
   __shared__ uint2 ebs[4][kEdgeBuf];
+  constexpr uint32_t NOFF = Offs<D>::n2;
   const uint32_t wv = threadIdx.x / kWave;
-  VUnit* vb = vbs[wv];
+  IEnt* ib = ibs[wv];
   QItem2* q = qs[wv];
   Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
-  const int L = g->L;
+  const uint32_t dstride = dtab[0];
   uint64_t ndraws = 0, ncand = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
-    const uint64_t ub = (uint64_t)c * sc.chunk;
-    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
-    uint64_t u = ub + lane;
-    uint32_t vn = 0, dseq = 0;
+    const uint64_t sb = (uint64_t)c * sc.chunk;
+    const uint64_t se = sb + sc.chunk < sc.nunits ? sb + sc.chunk : sc.nunits;
+    uint32_t in = 0, dseq = 0;
     Ring2 r{0, 0, 0, 0};
     bool act = false;
     QItem2 cur{};
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
-    for (;;) {
-      fill_units<D, true>(g, src, u, ue, vb, vn);
-      if (vn == 0) break;
-      VUnit mu{};
-      const bool have = take_unit(vb, vn, mu);
-      uint64_t jm = 0;
-      uint32_t A = 0, a0 = 0, na = 0, lvl = 0, li = 0;
-      if (have) {
-        const Src sr = src[mu.sidx];
-        lvl = sr.meta & 255u;
-        li = sr.meta >> 8;
-        A = sr.A;
-        a0 = sr.s;
-        na = sr.na;
-        jm = g->jII[li][lvl];
-      }
-      const uint32_t gp = mu.gap;
-      while (__any(jm != 0)) {
-        if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-          draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
-        bool enq = false, hv = false;
-        QItem2 it{};
-        ItemRec rec{};
-        if (jm) {
-          const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
-          jm &= jm - 1;
-          uint32_t b0, nb;
-          cell_range(g, P, lj, lvl, mu.B, &b0, &nb);
-          if (nb) {
-            const Pbar pe = pbt[(((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1)];
-            if (pe.pbar > 0.0) {
-              const uint64_t N = (uint64_t)na * nb;
-              uint64_t G, nseg;
-              segment_size(N, pe.e, &G, &nseg);
-              if (nseg > 1) {
-                rec = ItemRec{a0, na, b0, nb, A, mu.B,
-                              lvl | (li << 8) | (lj << 16) | (gp << 24), (uint32_t)pe.e};
-                hv = true;
-              } else {
-                it = QItem2{A, mu.B, ctr_word3(lvl, li, lj, kKindType2, 0), a0, b0, nb, 0u, pe.qscale,
-                            0ull, N, pe.pbar, pe.lg};
-                enq = true;
-              }
-            }
+    for (uint64_t si = sb; si < se; ++si) {
+      const uint32_t sidx = (uint32_t)si;
+      const Src sr = src[sidx];
+      const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
+      const uint64_t jm = g->jII[li][lvl];
+      if (jm == 0) continue;
+      const uint64_t* mk = masks + g->moff[lvl];
+      if (lvl >= 3) {
+        uint32_t qa[D];
+        morton_decode<D>(sr.A, qa);
+        const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
+        uint32_t par = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) par |= (qa[k] & 1u) << k;
+        const uint32_t noff = dtab[1 + par];
+        const uint32_t* tb = dtab + kDistHead + par * dstride;
+        for (uint32_t t0 = 0; t0 < noff; t0 += kWave) {
+          const uint32_t t = t0 + lane;
+          uint64_t m = 0;
+          uint32_t Y = 0, gap = 0;
+          if (t < noff) {
+            const uint32_t en = tb[t];
+            uint32_t b[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) b[k] = (qa[k] + ((en >> (3 * k)) & 7u) - 3u) & cm;
+            Y = morton_encode<D>(b);
+            gap = en >> 28;
+            m = mk[Y] & jm;
           }
+          push_items2<D, MODEL, MX>(m, sidx, Y, gap, g, v, P, src, pbt, nlev, ib, in, q, cq, r,
+                                    act, cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
         }
-        if (__any(hv)) defer_item(hv, rec, c, dseq, dfo);
-        enqueue2(enq, it, q, r);
+      } else {
+        for (uint32_t o0 = 0; o0 < NOFF; o0 += kWave) {
+          const uint32_t o = o0 + lane;
+          uint64_t m = 0;
+          uint32_t Y = 0;
+          int gap = 0;
+          if (o < NOFF && distant_cell<D>(sr.A, (int)lvl, o, &Y, &gap) && Y > sr.A) m = mk[Y] & jm;
+          push_items2<D, MODEL, MX>(m, sidx, Y, (uint32_t)gap, g, v, P, src, pbt, nlev, ib, in, q,
+                                    cq, r, act, cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
+        }
       }
     }
+    while (in)
+      take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, c, dseq, dfo,
+                                sg, out, ndraws, ncand, nre);
     draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand, nre);
     while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
     flush(sg, out);
@@ -1011,16 +1128,50 @@ hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const It
 
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
                         const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
-                        const Stage& sg, const DeferOut& dfo, hipStream_t st) {
+                        const uint64_t* masks, const uint32_t* dtab, const Stage& sg,
+                        const DeferOut& dfo, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
   const bool mx = use_mixed(g);
   HG_DISPATCH_D({
     if constexpr (MM == 0) {
-      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
-      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
-    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, sg, dfo);
+      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
+      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
+    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
   });
   return hipGetLastError();
+}
+
+std::vector<uint32_t> distant_table(int d) {
+  const int npar = 1 << d;
+  std::vector<std::vector<uint32_t>> lists(npar);
+  int noff = 1;
+  for (int k = 0; k < d; ++k) noff *= 6;
+  for (int par = 0; par < npar; ++par) {
+    for (int o = 0; o < noff; ++o) {
+      int rem = o, dm = 0, first = 0;
+      uint32_t en = 0;
+      for (int k = 0; k < d; ++k) {
+        const int jk = rem % 6;
+        rem /= 6;
+        const int delta = jk - 2 - ((par >> k) & 1);  // child of a parent-neighbour
+        const int ad = delta < 0 ? -delta : delta;
+        dm = ad > dm ? ad : dm;
+        if (first == 0) first = delta;
+        en |= (uint32_t)(delta + 3) << (3 * k);
+      }
+      if (dm < 2 || first < 0) continue;  // a neighbour, or listed at the other cell
+      lists[par].push_back(en | ((uint32_t)(dm - 1) << 28));
+    }
+  }
+  size_t stride = 1;
+  for (auto& l : lists) stride = l.size() > stride ? l.size() : stride;
+  std::vector<uint32_t> tab(kDistHead + npar * stride, 0u);
+  tab[0] = (uint32_t)stride;
+  for (int par = 0; par < npar; ++par) {
+    tab[1 + par] = (uint32_t)lists[par].size();
+    for (size_t t = 0; t < lists[par].size(); ++t) tab[kDistHead + par * stride + t] = lists[par][t];
+  }
+  return tab;
 }
 
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,

@@ -68,15 +68,25 @@ hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* sm
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
                           const uint8_t* slayer, const uint32_t* P, uint32_t* cnt,
-                          const uint32_t* off, Src* src, bool fill, hipStream_t st);
+                          const uint32_t* off, Src* src, uint64_t* masks, bool fill,
+                          hipStream_t st);
 
 // sampling passes
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
                         const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
                         hipStream_t st);
+// distant offsets of a cell at levels >= 3 by the parity pattern p of its
+// coordinates: dtab[0] = stride, dtab[1 + p] = count, entries at
+// dtab[kDistHead + p * stride + t] = sum_k (delta_k + 3) << 3k | gap << 28;
+// only offsets whose first nonzero delta is positive (the other orientation
+// of each pair is listed at the other cell)
+constexpr int kDistHead = 32;
+std::vector<uint32_t> distant_table(int d);
+
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
                         const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
-                        const Stage& sg, const DeferOut& dfo, hipStream_t st);
+                        const uint64_t* masks, const uint32_t* dtab, const Stage& sg,
+                        const DeferOut& dfo, hipStream_t st);
 // deferred items: units per record (kind 1: test pieces, kind 2: segments)
 hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
                             hipStream_t st);
