@@ -172,7 +172,6 @@ struct CSolve {
   std::vector<double> h;   // heaviest weights, descending
   std::vector<double> pw, pp;  // prefix sums of h and h^(1/T)
   double wcut;             // every weight not in h is <= wcut
-  bool incomplete = false;
 
   std::vector<double> hp;  // h^(1/T)
 
@@ -188,11 +187,16 @@ struct CSolve {
     }
   }
 
+  // a pair (u, v) is in E_R iff w_u w_v > th(c)
+  double th(double c) const {
+    return T > 0.0 ? std::ldexp(W / std::pow(c, T), -d) : W / std::ldexp(std::pow(c, (double)d), d);
+  }
+  // E_R within h, i.e. no pair with a weight outside h, at this c (and at
+  // every smaller c: th decreases in c)
+  bool complete_at(double c) const { return h.empty() || !(h[0] * wcut > th(c)); }
+
   double f(double c) {
-    const double th = T > 0.0 ? std::ldexp(W / std::pow(c, T), -d)
-                              : W / std::ldexp(std::pow(c, (double)d), d);
-    // a pair (u, v) is in E_R iff w_u w_v > th
-    if (!h.empty() && h[0] * wcut > th) incomplete = true;
+    const double th = this->th(c);
     double A, B = 0.0;
     if (T > 0.0) {
       A = std::pow(c, T) * std::ldexp(1.0, d) / (1.0 - T);
@@ -221,7 +225,12 @@ struct CSolve {
   }
 
   // bracket by doubling / halving, then regula falsi (Illinois) on log c
-  // until the bracket is a few ulps wide; returns its upper end
+  // until the bracket is a few ulps wide; returns its upper end.  f is
+  // evaluated exactly wherever h is complete, i.e. at every c up to some
+  // bound.  A lower end is only taken where f < target and an upper end where
+  // f >= target, so when h is complete at the final upper end (checked by the
+  // caller) both ends were evaluated exactly and the root lies between them,
+  // whatever inexact values steered the search on the way.
   int solve(double target, double* out) {
     double lo = 1.0, hi = 1.0;
     double flo = f(1.0) - target, fhi = flo;
@@ -572,9 +581,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
         cs.prepare();
-        cs.incomplete = false;
         if (cs.solve(p.avg_deg, &c) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
-        if (!cs.incomplete || i0 == 0) break;
+        if (cs.complete_at(c) || i0 == 0) break;
         // take layers until the tail at least doubles
         const uint64_t want = 2 * cs.h.size();
         while (i0 > 0 && n - g.lstart[i0] < want) --i0;

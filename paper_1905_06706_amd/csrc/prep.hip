@@ -175,6 +175,7 @@ hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, 
 __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
                                                 Pbar* __restrict__ pb) {
   __shared__ int dmax;
+  __shared__ int8_t scl[kMaxLayers][kMaxLayers];
   const int L = g->L, d = g->d;
   if (threadIdx.x == 0) dmax = 0;
   __syncthreads();
@@ -208,31 +209,33 @@ __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
       atomicMax(&dmax, l);
     }
     g->CL[i][j] = (int8_t)l;
+    scl[i][j] = (int8_t)l;
   }
   __syncthreads();
   if (threadIdx.x == 0) g->D = dmax;
   for (int i = threadIdx.x; i < kMaxLayers; i += blockDim.x) {
     int I = -1;
-    for (int j = 0; j < kMaxLayers; ++j) I = g->CL[i][j] > I ? g->CL[i][j] : I;
+    for (int j = 0; j < kMaxLayers; ++j) I = scl[i][j] > I ? scl[i][j] : I;
     g->I[i] = (int8_t)I;
-    for (int l = 0; l < kMaxLevels; ++l) {
-      uint64_t m1 = 0, m2 = 0;
-      for (int j = 0; j < kMaxLayers; ++j) {
-        const int cl = g->CL[i][j];
-        if (cl < 0) continue;
-        if (cl == l) m1 |= 1ull << j;
-        if (cl >= l && l >= 2) m2 |= 1ull << j;  // distant pairs exist from level 2
-      }
-      g->jI[i][l] = m1;
-      g->jII[i][l] = g->T > 0.0 ? m2 : 0ull;  // threshold: distant cells hold no edges
+  }
+  for (int p = threadIdx.x; p < kMaxLayers * kMaxLevels; p += blockDim.x) {
+    const int i = p / kMaxLevels, l = p % kMaxLevels;
+    uint64_t m1 = 0, m2 = 0;
+    for (int j = 0; j < kMaxLayers; ++j) {
+      const int cl = scl[i][j];
+      if (cl < 0) continue;
+      if (cl == l) m1 |= 1ull << j;
+      if (cl >= l && l >= 2) m2 |= 1ull << j;  // distant pairs exist from level 2
     }
+    g->jI[i][l] = m1;
+    g->jII[i][l] = g->T > 0.0 ? m2 : 0ull;  // threshold: distant cells hold no edges
   }
   if (!(g->T > 0.0) || pb == nullptr) return;
   // pbar for (i, j, level, gap): largest weights, smallest distance gap 2^-level
   const int nl = Dcap + 1;
   for (int p = threadIdx.x; p < L * L * nl * 2; p += blockDim.x) {
     const int gi = p & 1, l = (p >> 1) % nl, ij = (p >> 1) / nl, i = ij / L, j = ij % L;
-    const int cl = (i < L && j < L) ? g->CL[i][j] : -1;
+    const int cl = (i < L && j < L) ? scl[i][j] : -1;
     Pbar e{0.0, 0.0, 0, 0};
     if (cl >= l && l >= 2) {
       const double dist = ldexp((double)(gi + 1), -l);

@@ -198,20 +198,45 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* _
 }
 
 // one thread folds the block partials in order: out = [sum_0..sum_3, min, max]
-__global__ void k_reduce_final(const double* __restrict__ part, int nblocks,
-                               double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one wave: lane t merges partials t, t + 64, ... in order, then a fixed
+// pairwise tree over the lanes (deterministic)
+__global__ __launch_bounds__(64) void k_reduce_final(const double* __restrict__ part, int nblocks,
+                                                     double* __restrict__ out) {
+  __shared__ double shi[4][64], slo[4][64], smin[64], smax[64];
+  const int t = threadIdx.x;
   double hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
   double mn = __builtin_inf(), mx = -__builtin_inf();
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = t; b < nblocks; b += 64) {
     const double* o = part + (uint64_t)b * 10;
-    for (int t = 0; t < 4; ++t) dd_merge(hi[t], lo[t], o[2 * t], o[2 * t + 1]);
+    for (int k = 0; k < 4; ++k) dd_merge(hi[k], lo[k], o[2 * k], o[2 * k + 1]);
     mn = fmin(mn, o[8]);
     mx = fmax(mx, o[9]);
   }
-  for (int t = 0; t < 4; ++t) out[t] = hi[t] + lo[t];
-  out[4] = mn;
-  out[5] = mx;
+  for (int k = 0; k < 4; ++k) {
+    shi[k][t] = hi[k];
+    slo[k][t] = lo[k];
+  }
+  smin[t] = mn;
+  smax[t] = mx;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int k = 0; k < 4; ++k) {
+        double h = shi[k][t], l = slo[k][t];
+        dd_merge(h, l, shi[k][t + s], slo[k][t + s]);
+        shi[k][t] = h;
+        slo[k][t] = l;
+      }
+      smin[t] = fmin(smin[t], smin[t + s]);
+      smax[t] = fmax(smax[t], smax[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int k = 0; k < 4; ++k) out[k] = shi[k][0] + slo[k][0];
+    out[4] = smin[0];
+    out[5] = smax[0];
+  }
 }
 
 hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,

@@ -767,7 +767,6 @@ struct IEnt {
   uint32_t sidx;  // source of the X side
   uint32_t Y;     // the other cell
   uint32_t jg;    // layer j of the Y side | gap << 8
-  uint32_t pad;
 };
 
 template <int D, int MODEL, bool MX>
@@ -783,10 +782,10 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   const uint32_t lane = lane_id();
   const uint32_t take = in < 64 ? in : 64;
   const bool have = lane < take;
-  IEnt e{0, 0, 0, 0};
+  IEnt e{0, 0, 0};
   if (have) e = ib[lane];
   const uint32_t rest = in - take;
-  IEnt tmp{0, 0, 0, 0};
+  IEnt tmp{0, 0, 0};
   if (lane < rest) tmp = ib[take + lane];
   if (lane < rest) ib[lane] = tmp;
   in = rest;
@@ -864,12 +863,32 @@ __device__ __forceinline__ void push_items2(uint64_t m, uint32_t sidx, uint32_t 
       m &= m - 1;
     }
     const uint64_t mb = __ballot(has);
-    if (has) ib[in + lanes_below(mb)] = IEnt{sidx, Y, j | (gap << 8), 0u};
+    if (has) ib[in + lanes_below(mb)] = IEnt{sidx, Y, j | (gap << 8)};
     in += (uint32_t)__popcll(mb);
     if (in >= 64)
       take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, chunk, dseq,
                                 dfo, sg, out, ndraws, ncand, nre);
   }
+}
+
+// per-wave source batch: 64 sources, their candidate-cell counts and the
+// inclusive prefix of the counts (load-balanced expansion over the lanes)
+struct SrcSlot {
+  uint64_t jm;    // layers j with CL(i,j) >= level
+  uint32_t sidx;  // source index
+  uint32_t A;     // its cell
+  uint32_t info;  // level | parity << 8 (parity 255: all 6^d children)
+  uint32_t incl;  // inclusive prefix of the counts
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
 }
 
 template <int D, int MODEL, bool MX>
@@ -884,11 +903,13 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
   __shared__ uint2 ebs[4][kEdgeBuf];
+  __shared__ SrcSlot sss[4][kWave];
   constexpr uint32_t NOFF = Offs<D>::n2;
   const uint32_t wv = threadIdx.x / kWave;
   IEnt* ib = ibs[wv];
   QItem2* q = qs[wv];
   Cand* cq = cqs[wv];
+  SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
   const uint32_t dstride = dtab[0];
   uint64_t ndraws = 0, ncand = 0, nre = 0;
@@ -902,48 +923,71 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
     bool act = false;
     QItem2 cur{};
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
-    for (uint64_t si = sb; si < se; ++si) {
-      const uint32_t sidx = (uint32_t)si;
-      const Src sr = src[sidx];
-      const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
-      const uint64_t jm = g->jII[li][lvl];
-      if (jm == 0) continue;
-      const uint64_t* mk = masks + g->moff[lvl];
-      if (lvl >= 3) {
-        uint32_t qa[D];
-        morton_decode<D>(sr.A, qa);
-        const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
-        uint32_t par = 0;
+    for (uint64_t base = sb; base < se; base += kWave) {
+      // one source per lane: its candidate cells
+      const uint64_t si = base + lane;
+      uint32_t cnt = 0;
+      SrcSlot mine{0ull, (uint32_t)si, 0u, 0u, 0u};
+      if (si < se) {
+        const Src sr = src[si];
+        const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
+        mine.jm = g->jII[li][lvl];
+        mine.A = sr.A;
+        if (mine.jm) {
+          if (lvl >= 3) {
+            uint32_t qa[D];
+            morton_decode<D>(sr.A, qa);
+            uint32_t par = 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) par |= (qa[k] & 1u) << k;
-        const uint32_t noff = dtab[1 + par];
-        const uint32_t* tb = dtab + kDistHead + par * dstride;
-        for (uint32_t t0 = 0; t0 < noff; t0 += kWave) {
-          const uint32_t t = t0 + lane;
-          uint64_t m = 0;
-          uint32_t Y = 0, gap = 0;
-          if (t < noff) {
-            const uint32_t en = tb[t];
-            uint32_t b[D];
+            for (int k = 0; k < D; ++k) par |= (qa[k] & 1u) << k;
+            cnt = dtab[1 + par];
+            mine.info = lvl | (par << 8);
+          } else {
+            cnt = NOFF;
+            mine.info = lvl | (255u << 8);
+          }
+        }
+      }
+      mine.incl = wave_incl_scan(cnt);
+      ss[lane] = mine;
+      const uint32_t total = __shfl(mine.incl, 63, 64);
+      // (source, offset) pairs spread over the lanes
+      for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
+        const uint32_t k = k0 + lane;
+        uint64_t m = 0;
+        uint32_t Y = 0, gap = 0, sidx = 0;
+        if (k < total) {
+          // slot = number of inclusive prefixes <= k
+          uint32_t lo = 0, hi = 64;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ss[mid].incl <= k) lo = mid + 1;
+            else hi = mid;
+          }
+          const SrcSlot sl = ss[lo];
+          const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
+          const uint32_t lvl = sl.info & 255u, par = sl.info >> 8;
+          sidx = sl.sidx;
+          bool ok;
+          if (par != 255u) {
+            uint32_t qa[D], b[D];
+            morton_decode<D>(sl.A, qa);
+            const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
+            const uint32_t en = dtab[kDistHead + par * dstride + t];
 #pragma unroll
-            for (int k = 0; k < D; ++k) b[k] = (qa[k] + ((en >> (3 * k)) & 7u) - 3u) & cm;
+            for (int kk = 0; kk < D; ++kk) b[kk] = (qa[kk] + ((en >> (3 * kk)) & 7u) - 3u) & cm;
             Y = morton_encode<D>(b);
             gap = en >> 28;
-            m = mk[Y] & jm;
+            ok = true;
+          } else {
+            int gp = 0;
+            ok = distant_cell<D>(sl.A, (int)lvl, t, &Y, &gp) && Y > sl.A;
+            gap = (uint32_t)gp;
           }
-          push_items2<D, MODEL, MX>(m, sidx, Y, gap, g, v, P, src, pbt, nlev, ib, in, q, cq, r,
-                                    act, cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
+          if (ok) m = masks[g->moff[lvl] + Y] & sl.jm;
         }
-      } else {
-        for (uint32_t o0 = 0; o0 < NOFF; o0 += kWave) {
-          const uint32_t o = o0 + lane;
-          uint64_t m = 0;
-          uint32_t Y = 0;
-          int gap = 0;
-          if (o < NOFF && distant_cell<D>(sr.A, (int)lvl, o, &Y, &gap) && Y > sr.A) m = mk[Y] & jm;
-          push_items2<D, MODEL, MX>(m, sidx, Y, (uint32_t)gap, g, v, P, src, pbt, nlev, ib, in, q,
-                                    cq, r, act, cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
-        }
+        push_items2<D, MODEL, MX>(m, sidx, Y, gap, g, v, P, src, pbt, nlev, ib, in, q, cq, r, act,
+                                  cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
       }
     }
     while (in)
