@@ -663,8 +663,6 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
 
   Verts v{sw, sx, ids, smort, slayer, aux, lw};
   const bool binomial = p.T > 0.0;
-  uint64_t n1 = 1;
-  for (int k = 0; k < d; ++k) n1 *= 3;
 
   // staging of the edges: capacity = the caller's; flush records
   unsigned int* tickets = ar.get<unsigned int>(8);
@@ -686,7 +684,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
     return sc;
   };
-  Sched sch[4] = {make_sched(nsrc ? nsrc * n1 : 0, 0), make_sched(0, 1),
+  Sched sch[4] = {make_sched_src(nsrc, 0), make_sched(0, 1),
                   make_sched_src(binomial ? nsrc : 0, 2), make_sched(0, 3)};
   uint2* stage = cap ? ar.get<uint2>(cap) : nullptr;
   // every flush but the last of a chunk holds more than 128 edges
@@ -719,7 +717,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
     DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
     cx.mark("-", st);
-    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], sg, df0, st));
+    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], masks, sg, df0, st));
     cx.mark("type1", st);
     if (sch[2].nchunks)
       HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, masks, cx.dtab[d], sg, df1, st));

@@ -287,6 +287,7 @@ __device__ __forceinline__ void defer_item(bool pending, const ItemRec& rec, uin
 constexpr int kVCap = 128;  // valid-unit buffer (>= 2 x 64)
 constexpr int kQCap = 128;  // item ring (power of two, >= 2 x 64)
 constexpr int kCCap = 128;  // candidate ring (power of two, >= 2 x 64)
+constexpr int kICap = 128;  // item lists (>= 2 x 64)
 
 struct VUnit {
   uint32_t sidx, B, gap, pad;
@@ -471,75 +472,196 @@ __device__ __forceinline__ void enqueue1(bool enq, QItem1& it, QItem1* __restric
   r.bt += total;
 }
 
-// type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3)
+// per-wave source batch: 64 sources, their candidate-cell counts and the
+// inclusive prefix of the counts (load-balanced expansion over the lanes)
+struct SrcSlot {
+  uint64_t jm;    // layers j with CL(i,j) >= level
+  uint32_t sidx;  // source index
+  uint32_t A;     // its cell
+  uint32_t info;  // level | parity << 8 (parity 255: all 6^d children)
+  uint32_t incl;  // inclusive prefix of the counts
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+// type-I pass: neighbouring cell pairs at level CL(i,j) (loop swap, Sec. 3.3).
+// Waves take batches of 64 sources (layer i, level l, cell X); the
+// (source, neighbour) pairs are spread over the lanes.  At levels >= 2 the
+// neighbours are X itself (layers j >= i) and the offsets in {-1,0,1}^d whose
+// first nonzero component is positive (index o > (3^d - 1) / 2 in balanced
+// ternary, dimension 0 most significant); the other orientation of each pair
+// is listed at the other cell.  At levels <= 1 all 3^d offsets are decoded,
+// deduplicated, with Y >= X.  The layer mask of Y restricted to
+// {j : CL(i,j) == l} lists the nonempty items; they are oriented with the
+// smaller cell as their A side and queued for the flat test steps.
+struct IEnt1 {
+  uint32_t sidx;  // source of the X side
+  uint32_t Y;     // the other cell
+  uint32_t j;     // layer of the Y side
+};
+
+template <int D, int MODEL, bool T0, bool MX>
+__device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const Verts& v,
+                                            const uint32_t* __restrict__ P,
+                                            const Src* __restrict__ src, IEnt1* ib, uint32_t& in,
+                                            QItem1* __restrict__ q, Ring1& r, uint32_t chunk,
+                                            uint32_t& dseq, const DeferOut& dfo, const Stage& sg,
+                                            Out& out, uint64_t& ntests, uint64_t& nre) {
+  const uint32_t lane = lane_id();
+  const uint32_t take = in < 64 ? in : 64;
+  const bool have = lane < take;
+  IEnt1 e{0, 0, 0};
+  if (have) e = ib[lane];
+  const uint32_t rest = in - take;
+  IEnt1 tmp{0, 0, 0};
+  if (lane < rest) tmp = ib[take + lane];
+  if (lane < rest) ib[lane] = tmp;
+  in = rest;
+  // room for 64 more items; consume blocks when there are several steps of them
+  while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
+    step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
+  bool enq = false, big = false;
+  QItem1 it{};
+  ItemRec rec{};
+  if (have) {
+    const Src sr = src[e.sidx];
+    const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8, lj = e.j;
+    uint32_t b0, nb;
+    cell_range(g, P, (int)lj, (int)lvl, e.Y, &b0, &nb);
+    // orientation: the smaller cell is the A side
+    const bool fwd = e.Y >= sr.A;
+    const uint32_t cA = fwd ? sr.A : e.Y, cB = fwd ? e.Y : sr.A;
+    const uint32_t ci = fwd ? li : lj, cj = fwd ? lj : li;
+    const uint32_t ca0 = fwd ? sr.s : b0, cna = fwd ? sr.na : nb;
+    const uint32_t cb0 = fwd ? b0 : sr.s, cnb = fwd ? nb : sr.na;
+    const bool tri = cA == cB && ci == cj;
+    const uint64_t tot = tri ? (uint64_t)cna * (cna - 1) / 2 : (uint64_t)cna * cnb;
+    if (nb && tot) {
+      if (tot > kBigTests) {
+        rec = ItemRec{ca0, cna, cb0, cnb, cA, cB,
+                      lvl | (ci << 8) | (cj << 16) | (tri ? 1u << 31 : 0u), 0u};
+        big = true;
+      } else {
+        it = QItem1{cA, cB, ctr_word3(lvl, ci, cj, kKindType1, 0), ca0, cb0, cnb, cna,
+                    tri ? 1u : 0u, 0u, 0u, (uint32_t)((tot + 1) / 2), 0u};
+        enq = true;
+      }
+    }
+  }
+  if (__any(big)) defer_item(big, rec, chunk, dseq, dfo);
+  enqueue1(enq, it, q, r);
+}
+
 template <int D, int MODEL, bool T0, bool MX>
 __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Verts v,
                                                const uint32_t* __restrict__ P,
-                                               const Src* __restrict__ src, Sched sc, Stage sg,
+                                               const Src* __restrict__ src, Sched sc,
+                                               const uint64_t* __restrict__ masks, Stage sg,
                                                DeferOut dfo) {
-  __shared__ VUnit vbs[4][kVCap];
+  __shared__ IEnt1 ibs[4][kICap];
   __shared__ QItem1 qs[4][kQCap];
   __shared__ uint2 ebs[4][kEdgeBuf];
+  __shared__ SrcSlot sss[4][kWave];
+  constexpr uint32_t NOFF = Offs<D>::n1;
+  constexpr uint32_t HALF = (Offs<D>::n1 - 1) / 2;
   const uint32_t wv = threadIdx.x / kWave;
-  VUnit* vb = vbs[wv];
+  IEnt1* ib = ibs[wv];
   QItem1* q = qs[wv];
+  SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
   uint64_t ntests = 0, nre = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
-    const uint64_t ub = (uint64_t)c * sc.chunk;
-    const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
-    uint64_t u = ub + lane;
-    uint32_t vn = 0, dseq = 0;
+    const uint64_t sb = (uint64_t)c * sc.chunk;
+    const uint64_t se = sb + sc.chunk < sc.nunits ? sb + sc.chunk : sc.nunits;
+    uint32_t in = 0, dseq = 0;
     Ring1 r{0, 0, 0, 0};
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
-    for (;;) {
-      fill_units<D, false>(g, src, u, ue, vb, vn);
-      if (vn == 0) break;
-      VUnit mu{};
-      const bool have = take_unit(vb, vn, mu);
-      uint64_t jm = 0;
-      uint32_t A = 0, a0 = 0, na = 0, lvl = 0, li = 0;
-      if (have) {
-        const Src sr = src[mu.sidx];
-        lvl = sr.meta & 255u;
-        li = sr.meta >> 8;
-        A = sr.A;
-        a0 = sr.s;
-        na = sr.na;
-        jm = g->jI[li][lvl];
-        if (mu.B == A) jm &= ~((1ull << li) - 1ull);  // j >= i when A = B
+    for (uint64_t base = sb; base < se; base += kWave) {
+      // one source per lane: its neighbour cells
+      const uint64_t si = base + lane;
+      uint32_t cnt = 0;
+      SrcSlot mine{0ull, (uint32_t)si, 0u, 0u, 0u};
+      if (si < se) {
+        const Src sr = src[si];
+        const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
+        mine.jm = g->jI[li][lvl];
+        mine.A = sr.A;
+        // info: level | table flag << 8 | layer << 16
+        if (mine.jm) {
+          const bool tab = lvl >= 2;
+          cnt = tab ? HALF + 1 : NOFF;
+          mine.info = lvl | (tab ? 0u : 255u << 8) | (li << 16);
+        }
       }
-      while (__any(jm != 0)) {
-        // room for 64 more items; consume blocks when there are several steps of them
-        while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-          step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
-        bool enq = false, big = false;
-        QItem1 it{};
-        ItemRec rec{};
-        if (jm) {
-          const uint32_t lj = (uint32_t)__ffsll((long long)jm) - 1;
-          jm &= jm - 1;
-          uint32_t b0, nb;
-          cell_range(g, P, lj, lvl, mu.B, &b0, &nb);
-          const bool tri = mu.B == A && lj == li;
-          const uint64_t tot = tri ? (uint64_t)na * (na - 1) / 2 : (uint64_t)na * nb;
-          if (nb && tot) {
-            const uint32_t w3 = ctr_word3(lvl, li, lj, kKindType1, 0);
-            if (tot > kBigTests) {
-              rec = ItemRec{a0, na, b0, nb, A, mu.B, lvl | (li << 8) | (lj << 16) | (tri ? 1u << 31 : 0u), 0u};
-              big = true;
-            } else {
-              it = QItem1{A, mu.B, w3, a0, b0, nb, na, tri ? 1u : 0u, 0u, 0u, (uint32_t)((tot + 1) / 2), 0u};
-              enq = true;
+      mine.incl = wave_incl_scan(cnt);
+      ss[lane] = mine;
+      const uint32_t total = __shfl(mine.incl, 63, 64);
+      for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
+        const uint32_t k = k0 + lane;
+        uint64_t m = 0;
+        uint32_t Y = 0, sidx = 0;
+        if (k < total) {
+          uint32_t lo = 0, hi = 64;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ss[mid].incl <= k) lo = mid + 1;
+            else hi = mid;
+          }
+          const SrcSlot sl = ss[lo];
+          const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
+          const uint32_t lvl = sl.info & 255u, li = sl.info >> 16;
+          sidx = sl.sidx;
+          bool ok;
+          if (((sl.info >> 8) & 255u) == 0u) {
+            // balanced-ternary offset o = HALF + t: t = 0 is X itself
+            uint32_t qa[D], b[D];
+            morton_decode<D>(sl.A, qa);
+            const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
+            uint32_t o = HALF + t;
+#pragma unroll
+            for (int kk = D - 1; kk >= 0; --kk) {
+              b[kk] = (qa[kk] + (o % 3u) - 1u) & cm;
+              o /= 3u;
             }
+            Y = morton_encode<D>(b);
+            ok = true;
+          } else {
+            ok = neighbour_cell<D>(sl.A, (int)lvl, t, &Y) && Y >= sl.A;
+          }
+          if (ok) {
+            m = masks[g->moff[lvl] + Y] & sl.jm;
+            if (Y == sl.A) m &= ~((1ull << li) - 1ull);  // j >= i when X = Y
           }
         }
-        if (__any(big)) defer_item(big, rec, c, dseq, dfo);
-        enqueue1(enq, it, q, r);
+        // expand the items of the lane's cell into the list; take 64 when full
+        while (__any(m != 0)) {
+          const bool has = m != 0;
+          uint32_t j = 0;
+          if (has) {
+            j = (uint32_t)__ffsll((long long)m) - 1;
+            m &= m - 1;
+          }
+          const uint64_t mb = __ballot(has);
+          if (has) ib[in + lanes_below(mb)] = IEnt1{sidx, Y, j};
+          in += (uint32_t)__popcll(mb);
+          if (in >= 64)
+            take_items1<D, MODEL, T0, MX>(g, v, P, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests,
+                                          nre);
+        }
       }
     }
+    while (in)
+      take_items1<D, MODEL, T0, MX>(g, v, P, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests, nre);
     while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
     flush(sg, out);
   }
@@ -761,8 +883,6 @@ __device__ __forceinline__ void enqueue2(bool enq, const QItem2& it, QItem2* __r
 // LDS list and taken 64 at a time.  An item is oriented with the smaller cell
 // as its A side (App. B.1), makes its first draw at once, and is queued for
 // more draws only if its range is not exhausted.
-constexpr int kICap = 128;  // item list (>= 2 x 64)
-
 struct IEnt {
   uint32_t sidx;  // source of the X side
   uint32_t Y;     // the other cell
@@ -869,26 +989,6 @@ __device__ __forceinline__ void push_items2(uint64_t m, uint32_t sidx, uint32_t 
       take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, chunk, dseq,
                                 dfo, sg, out, ndraws, ncand, nre);
   }
-}
-
-// per-wave source batch: 64 sources, their candidate-cell counts and the
-// inclusive prefix of the counts (load-balanced expansion over the lanes)
-struct SrcSlot {
-  uint64_t jm;    // layers j with CL(i,j) >= level
-  uint32_t sidx;  // source index
-  uint32_t A;     // its cell
-  uint32_t info;  // level | parity << 8 (parity 255: all 6^d children)
-  uint32_t incl;  // inclusive prefix of the counts
-};
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= (uint32_t)o) x += y;
-  }
-  return x;
 }
 
 template <int D, int MODEL, bool MX>
@@ -1141,16 +1241,16 @@ __global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ st
 static bool use_mixed(const Graph& g) { return g.precision == 1 && g.model == 0 && g.T > 0.0; }
 
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
-                        hipStream_t st) {
+                        const Src* src, const Sched& sc, const uint64_t* masks, const Stage& sg,
+                        const DeferOut& dfo, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
   const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
-    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
     else if constexpr (MM == 0) {
-      if (mx) hipLaunchKernelGGL((k_type1<DD, 0, false, true>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
-      else hipLaunchKernelGGL((k_type1<DD, 0, false, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
-    } else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, P, src, sc, sg, dfo);
+      if (mx) hipLaunchKernelGGL((k_type1<DD, 0, false, true>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
+      else hipLaunchKernelGGL((k_type1<DD, 0, false, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
+    } else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
   });
   return hipGetLastError();
 }

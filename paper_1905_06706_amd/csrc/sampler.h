@@ -73,8 +73,8 @@ hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort
 
 // sampling passes
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Stage& sg, const DeferOut& dfo,
-                        hipStream_t st);
+                        const Src* src, const Sched& sc, const uint64_t* masks, const Stage& sg,
+                        const DeferOut& dfo, hipStream_t st);
 // distant offsets of a cell at levels >= 3 by the parity pattern p of its
 // coordinates: dtab[0] = stride, dtab[1 + p] = count, entries at
 // dtab[kDistHead + p * stride + t] = sum_k (delta_k + 3) << 3k | gap << 28;
