@@ -35,6 +35,11 @@ WORKLOADS = {
                      dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=0)),
     "girg_d3_n1e7_mixed": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4 FP32 filter + FP64 recheck",
                            dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=1)),
+    "girg_batch256": ("256 GIRGs, n=round(10^(3+3U)), d in {1,2}, beta~U[2.1,3], T in {0,0.3,0.9}, "
+                      "avg_deg~U[8,32], seed 1000+b (numpy default_rng(5)) FP64",
+                      dict(model=0, batch=256, master_seed=5, precision=0)),
+    "girg_batch256_mixed": ("the same 256 GIRGs, FP32 filter + FP64 recheck",
+                            dict(model=0, batch=256, master_seed=5, precision=1)),
 }
 DEFAULT = "girg_d2_n2p20"
 
@@ -83,8 +88,50 @@ def profiled_traffic(workload: str, stage: str):
     return None
 
 
+def batch_params(hg, wl: dict) -> list:
+    """The batch recipe: per instance n = round(10^(3+3U)), d uniform in {1, 2},
+    beta ~ U[2.1, 3.0], T uniform in {0, 0.3, 0.9}, average degree ~ U[8, 32],
+    seed 1000 + b; parameters drawn from numpy's default_rng(master_seed)."""
+    import numpy as np
+    rng = np.random.default_rng(wl["master_seed"])
+    out = []
+    for b in range(wl["batch"]):
+        n = int(round(10 ** (3 + 3 * rng.random())))
+        d = int(rng.integers(1, 3))
+        beta = float(rng.uniform(2.1, 3.0))
+        T = float(rng.choice([0.0, 0.3, 0.9]))
+        deg = float(rng.uniform(8.0, 32.0))
+        out.append(hg.make_params(n, d, beta, T, deg, 0.0, 1000 + b, wl["precision"]))
+    return out
+
+
 def make_call(hg, wl: dict):
     L = hg.load()
+    if "batch" in wl:
+        params = batch_params(hg, wl)
+        cnt = len(params)
+        arr = (hg.Params * cnt)(*params)
+        offs = (ctypes.c_uint64 * (cnt + 1))()
+        infos = (hg.Info * cnt)()
+
+        def call(buf, cap, m, info, stream):
+            st = L.girg_generate_batch(arr, cnt, buf, cap, offs, infos, stream)
+            m._obj.value = offs[cnt]
+            # totals of the batch in `info`
+            tot = {k: 0 for k in ("tests", "draws", "candidates", "rechecks", "type1_edges", "type2_edges")}
+            for i in infos:
+                for k in tot:
+                    tot[k] += getattr(i, k)
+            for k, v in tot.items():
+                setattr(info._obj, k, v)
+            info._obj.m = offs[cnt]
+            call.ops = sum(i.tests * (OPS_TEST_T0 if p.T == 0.0 else OPS_TEST_BINOM)
+                           + i.draws * OPS_DRAW + i.candidates * OPS_CAND for i, p in zip(infos, params))
+            return st
+        call.n_total = sum(p.n for p in params)
+        call.params = params
+        call.ops = 0.0
+        return call
     if wl["model"] == 1:
         def call(buf, cap, m, info, stream):
             return L.girg_hrg(wl["n"], wl["alpha"], wl["T"], 0.0, wl["avg_deg"], wl["seed"], buf, cap,
@@ -128,6 +175,26 @@ def cpu_baseline(wl: dict) -> dict:
     m = len(run.edges)
     return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}; {m} edges in {dt:.2f} s"}
+
+
+def cpu_baseline_batch(params: list, budget_s: float = 15.0) -> dict:
+    """The oracle, single-threaded, on the batch's instances in order (points,
+    constant, sampling of each) until about `budget_s` seconds are spent."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    m = 0
+    k = 0
+    for p in params:
+        w, x = oracle.points_girg(p.n, p.d, p.beta, p.seed)
+        c = oracle.solve_c(w, p.d, p.T, p.avg_deg)
+        m += len(oracle.run(w, x, T=p.T, c=c, seed=p.seed).edges)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {k} of {len(params)} instances, whole graphs; {m} edges in {dt:.2f} s"}
 
 
 def hbm_copy(mib: int, steps: int, warmup: int) -> int:
@@ -210,23 +277,33 @@ def main() -> int:
         print(f"[bench]   {k:>14s} {v:9.4f} ms", file=sys.stderr)
     print(f"[bench] info {info_d}", file=sys.stderr)
 
-    # dominant sampling kernel and its roofline (VALU-bound: lane-operations)
-    kernel_pass = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
-    kstages = {k: v for k, v in stages.items() if k in kernel_pass}
-    dom = max(kstages, key=kstages.get)
-    dom_ms = stages[dom]
-    q = kernel_pass[dom]
-    if q < 2:
-        units = {"tests": info_d["pass_work"][q]}
-        ops = units["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
+    if "batch" in wl:
+        # instances run concurrently on several streams: the whole step is the
+        # unit (all kernels of all instances)
+        ops = call.ops
+        achieved = ops / (dt / args.steps) / 1e12
+        roof = {"bound": "alu", "kernel": "whole batch step (all kernels, concurrent streams)",
+                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "launch_ms": dt / args.steps * 1e3, "ops_per_launch": ops}
     else:
-        units = {"draws": info_d["pass_work"][q], "candidates": info_d["pass_cands"][q]}
-        ops = units["draws"] * OPS_DRAW + units["candidates"] * OPS_CAND
-    achieved = ops / (dom_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom] + "...>", "achieved": achieved,
-            "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": profiled_traffic(args.workload, dom), "launch_ms": dom_ms,
-            "units_per_launch": units, "ops_per_launch": ops}
+        # dominant sampling kernel and its roofline (VALU-bound: lane-operations)
+        kernel_pass = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
+        kstages = {k: v for k, v in stages.items() if k in kernel_pass}
+        dom = max(kstages, key=kstages.get)
+        dom_ms = stages[dom]
+        q = kernel_pass[dom]
+        if q < 2:
+            units = {"tests": info_d["pass_work"][q]}
+            ops = units["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
+        else:
+            units = {"draws": info_d["pass_work"][q], "candidates": info_d["pass_cands"][q]}
+            ops = units["draws"] * OPS_DRAW + units["candidates"] * OPS_CAND
+        achieved = ops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom] + "...>", "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": profiled_traffic(args.workload, dom), "launch_ms": dom_ms,
+                "units_per_launch": units, "ops_per_launch": ops}
     value = edges / dt
     out = {
         "metric": METRIC,
@@ -248,7 +325,7 @@ def main() -> int:
         "stages_ms": stages,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline_batch(call.params) if "batch" in wl else cpu_baseline(wl)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -157,75 +157,95 @@ static int cmp_desc(const void* a, const void* b) {
   return (x < y) - (x > y);
 }
 
-/* f(c) = E[average degree] for the given weights.  T > 0: the formula for
- * f(c) of App. B.2 (Eqs. short, long, shortlong, deg) with the error term
- * over E_R = ordered pairs u != v with c^T w_u w_v / W > 2^-d (k > 1/2).
- * T = 0 ("analogous"): E[X_uv] = (2k)^d with k = c (w_u w_v / W)^{1/d} when
- * k <= 1/2, else 1. */
+/* f(c) = E[average degree] = (1/n) sum over ordered pairs u != v of
+ * E[X_uv] (App. B.2, Eq. deg).  E[X_uv] is 1 on E_R, the pairs whose ball of
+ * probability 1 reaches beyond the torus (k > 1/2: T > 0, c^T w_u w_v / W >
+ * 2^-d; T = 0, 2^d c^d w_u w_v / W > 1), and elsewhere the closed form of
+ * App. B.2: T > 0 A x - B x^{1/T} with x = w_u w_v / W, A = 2^d c^T / (1 - T),
+ * B = 2^{d/T} c / (1/T - 1) (Eqs. short, long, shortlong); T = 0
+ * ("analogous") (2k)^d = 2^d c^d x.  The paper evaluates the closed form over
+ * all pairs and subtracts its excess over E_R; here the pairs outside E_R are
+ * summed directly (the same value), so that no large excess is formed and
+ * subtracted: with weights in descending order, E_R partners of u are a
+ * prefix [0, m_u) and the other partners a suffix, summed from suffix sums. */
 typedef struct {
   uint64_t n;
   int d;
-  double T, W, s1, s2;
-  double* sorted; /* weights in descending order */
+  double T, W;
+  double* sorted;              /* weights in descending order */
+  double *sw, *sw2, *sp, *sp2; /* suffix sums from index k: w, w^2, w^{1/T}, w^{2/T} */
 } cctx;
 
 static double f_of_c(const cctx* q, double c) {
   uint64_t n = q->n;
   int d = q->d;
   double T = q->T, W = q->W;
-  double err = 0.0;
-  if (T == 0.0) {
-    double a = ldexp(pow(c, (double)d), d); /* 2^d c^d */
-    for (uint64_t u = 0; u < n; u++) {
-      double wu = q->sorted[u];
-      if (a * wu * q->sorted[0] / W <= 1.0) break;
-      for (uint64_t v = 0; v < n; v++) {
-        double X = wu * q->sorted[v] / W;
-        if (a * X <= 1.0) break;
-        if (v != u) err += a * X - 1.0;
-      }
-    }
-    return (a * q->s1 - err) / (double)n;
-  }
-  double cT = pow(c, T);
-  double A = cT * ldexp(1.0, d) / (1.0 - T);
-  double B = c * pow(2.0, (double)d / T) / (1.0 / T - 1.0);
-  double thr = ldexp(1.0, -d);
+  double cT = T > 0.0 ? pow(c, T) : 0.0;
+  double a0 = ldexp(pow(c, (double)d), d); /* T = 0: 2^d c^d */
+  double A = T > 0.0 ? cT * ldexp(1.0, d) / (1.0 - T) : a0;
+  double B = T > 0.0 ? c * pow(2.0, (double)d / T) / (1.0 / T - 1.0) : 0.0;
+  double WT = T > 0.0 ? pow(W, 1.0 / T) : 1.0;
+  double Wsum = q->sw[0], P = T > 0.0 ? q->sp[0] : 0.0;
+  long double cnt = 0.0L, S1 = 0.0L, S2 = 0.0L; /* S1 = sum w_u w_v, S2 = sum (w_u w_v)^{1/T} off E_R */
+  uint64_t m = n;
   for (uint64_t u = 0; u < n; u++) {
     double wu = q->sorted[u];
-    if (cT * (wu * q->sorted[0] / W) <= thr) break;
-    for (uint64_t v = 0; v < n; v++) {
-      double X = wu * q->sorted[v] / W;
-      if (cT * X <= thr) break;
-      if (v != u) err += A * X - B * pow(X, 1.0 / T) - 1.0;
+    /* m = number of v with (u, v) in E_R, v ranging over all vertices */
+    while (m > 0) {
+      double X = wu * q->sorted[m - 1] / W;
+      int in_er = T > 0.0 ? cT * X > ldexp(1.0, -d) : a0 * X > 1.0;
+      if (in_er) break;
+      m--;
     }
+    if (m == 0) {
+      /* no vertex from u on has a partner in E_R: all other vertices count */
+      S1 += (long double)Wsum * q->sw[u] - q->sw2[u];
+      if (T > 0.0) S2 += (long double)P * q->sp[u] - q->sp2[u];
+      break;
+    }
+    int self_out = u >= m; /* u itself lies in the suffix */
+    double hu = T > 0.0 ? pow(wu, 1.0 / T) : 0.0;
+    cnt += (long double)(m - (self_out ? 0 : 1));
+    S1 += (long double)wu * (q->sw[m] - (self_out ? wu : 0.0));
+    if (T > 0.0) S2 += (long double)hu * (q->sp[m] - (self_out ? hu : 0.0));
   }
-  return (A * q->s1 - B * q->s2 - err) / (double)n;
+  long double nf = (long double)A * (S1 / W) - (long double)B * (S2 / WT) + cnt;
+  return (double)(nf / (long double)n);
+}
+
+static void cctx_free(cctx* q) {
+  free(q->sorted);
+  free(q->sw);
+  free(q->sw2);
+  free(q->sp);
+  free(q->sp2);
 }
 
 static int cctx_init(cctx* q, uint64_t n, int d, double T, const double* w) {
   q->n = n; q->d = d; q->T = T;
   q->W = sum_ld(w, n);
-  long double s1 = 0.0L, p = 0.0L, r = 0.0L;
-  for (uint64_t u = 0; u < n; u++) {
-    s1 += (long double)(w[u] * w[u] / q->W);
-    if (T > 0.0) {
-      p += (long double)pow(w[u], 1.0 / T);
-      r += (long double)pow(w[u] * w[u] / q->W, 1.0 / T);
-    }
-  }
-  q->s1 = q->W - (double)s1; /* sum_u sum_{v != u} w_u w_v / W */
-  if (T > 0.0) {
-    /* sum_u (w_u^{1/T} / W^{1/T}) sum_v w_v^{1/T} - sum_v (w_v^2/W)^{1/T} */
-    double P = (double)p;
-    q->s2 = P / pow(q->W, 1.0 / T) * P - (double)r;
-  } else {
-    q->s2 = 0.0;
-  }
   q->sorted = (double*)malloc(sizeof(double) * n);
-  if (!q->sorted) return -1;
+  q->sw = (double*)malloc(sizeof(double) * (n + 1));
+  q->sw2 = (double*)malloc(sizeof(double) * (n + 1));
+  q->sp = (double*)malloc(sizeof(double) * (n + 1));
+  q->sp2 = (double*)malloc(sizeof(double) * (n + 1));
+  if (!q->sorted || !q->sw || !q->sw2 || !q->sp || !q->sp2) { cctx_free(q); return -1; }
   memcpy(q->sorted, w, sizeof(double) * n);
   qsort(q->sorted, n, sizeof(double), cmp_desc);
+  /* suffix sums, accumulated from the light end */
+  long double a = 0.0L, b = 0.0L, e = 0.0L, f = 0.0L;
+  q->sw[n] = q->sw2[n] = q->sp[n] = q->sp2[n] = 0.0;
+  for (uint64_t k = n; k-- > 0;) {
+    double x = q->sorted[k];
+    a += x;
+    b += (long double)x * x;
+    if (T > 0.0) {
+      double h = pow(x, 1.0 / T);
+      e += h;
+      f += (long double)h * h;
+    }
+    q->sw[k] = (double)a; q->sw2[k] = (double)b; q->sp[k] = (double)e; q->sp2[k] = (double)f;
+  }
   return 0;
 }
 
@@ -233,7 +253,7 @@ double orc_expected_avg_degree(uint64_t n, int d, double T, double c, const doub
   cctx q;
   if (cctx_init(&q, n, d, T, w)) return NAN;
   double f = f_of_c(&q, c);
-  free(q.sorted);
+  cctx_free(&q);
   return f;
 }
 
@@ -249,12 +269,12 @@ int orc_solve_c(uint64_t n, int d, double T, double avg_deg, const double* w, do
   if (f_of_c(&q, 1.0) < avg_deg) {
     while (f_of_c(&q, hi) < avg_deg) {
       lo = hi; hi *= 2.0;
-      if (++it > 2000) { free(q.sorted); set_err("solve_c: no bracket"); return -5; }
+      if (++it > 2000) { cctx_free(&q); set_err("solve_c: no bracket"); return -5; }
     }
   } else {
     while (f_of_c(&q, lo) >= avg_deg) {
       hi = lo; lo *= 0.5;
-      if (++it > 2000) { free(q.sorted); set_err("solve_c: no bracket"); return -5; }
+      if (++it > 2000) { cctx_free(&q); set_err("solve_c: no bracket"); return -5; }
     }
   }
   for (it = 0; it < 200; it++) {
@@ -262,7 +282,7 @@ int orc_solve_c(uint64_t n, int d, double T, double avg_deg, const double* w, do
     if (!(mid > lo && mid < hi)) break;
     if (f_of_c(&q, mid) < avg_deg) lo = mid; else hi = mid;
   }
-  free(q.sorted);
+  cctx_free(&q);
   *c_out = hi;
   return 0;
 }

@@ -16,7 +16,10 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <atomic>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -85,6 +88,7 @@ struct Ctx {
   unsigned long long* stats = nullptr;  // 16
   unsigned int* hcount = nullptr;
   uint32_t* dtab[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // distant offsets per d
+  hipStream_t own = nullptr;  // batch workers: the slot's own stream
   std::mutex mu;
   // stage timing (HIP events on the call's stream), enabled by girg_set_profiling
   bool profiling = false;
@@ -123,18 +127,22 @@ struct Ctx {
     if (hcount) (void)hipFree(hcount);
     for (auto t : dtab)
       if (t) (void)hipFree(t);
+    if (own) (void)hipStreamDestroy(own);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
+// contexts per (device, slot): slot 0 serves the single-graph calls, slots
+// 1.. the workers of girg_generate_batch (each with its own stream)
+constexpr int kBatchWorkers = 8;  // concurrent instances of a batch
 static std::mutex g_ctx_mu;
-static std::map<int, std::unique_ptr<Ctx>> g_ctx;
+static std::map<std::pair<int, int>, std::unique_ptr<Ctx>> g_ctx;
 
-static girg_status get_ctx(Ctx** out) {
+static girg_status get_ctx(Ctx** out, int slot = 0) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ctx_mu);
-  auto it = g_ctx.find(dev);
+  auto it = g_ctx.find({dev, slot});
   if (it != g_ctx.end()) {
     *out = it->second.get();
     return GIRG_OK;
@@ -146,8 +154,9 @@ static girg_status get_ctx(Ctx** out) {
   HIPCHK(hipMalloc(&c->flag, sizeof(uint32_t)));
   HIPCHK(hipMalloc(&c->stats, 16 * sizeof(unsigned long long)));
   HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
+  if (slot > 0) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
   *out = c.get();
-  g_ctx[dev] = std::move(c);
+  g_ctx[{dev, slot}] = std::move(c);
   return GIRG_OK;
 }
 
@@ -168,22 +177,34 @@ static int bitlen(uint64_t v) {
 struct CSolve {
   uint64_t n;
   int d;
-  double T, W, s1, s2;     // s1 = sum_{u != v} w_u w_v / W ; s2 = same with (.)^(1/T)
-  std::vector<double> h;   // heaviest weights, descending
-  std::vector<double> pw, pp;  // prefix sums of h and h^(1/T)
-  double wcut;             // every weight not in h is <= wcut
-
-  std::vector<double> hp;  // h^(1/T)
+  double T, W;
+  std::vector<double> h;        // heaviest weights (the tail), descending
+  std::vector<double> hp;       // h^(1/T)
+  std::vector<double> sw, sw2;  // suffix sums over h: w, w^2
+  std::vector<double> sp, sp2;  // suffix sums over h: w^(1/T), w^(2/T)
+  // sums over the weights outside h: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
+  double out_w = 0.0, out_q1 = 0.0, out_p = 0.0, out_q2 = 0.0;
+  double wcut;  // every weight not in h is <= wcut
 
   // h must already be in descending order
   void prepare() {
-    pw.assign(h.size() + 1, 0.0);
-    pp.assign(h.size() + 1, 0.0);
-    hp.assign(h.size(), 0.0);
-    for (size_t i = 0; i < h.size(); ++i) {
-      hp[i] = T > 0.0 ? std::pow(h[i], 1.0 / T) : 0.0;
-      pw[i + 1] = pw[i] + h[i];
-      pp[i + 1] = pp[i] + hp[i];
+    const size_t K = h.size();
+    hp.assign(K, 0.0);
+    sw.assign(K + 1, 0.0);
+    sw2.assign(K + 1, 0.0);
+    sp.assign(K + 1, 0.0);
+    sp2.assign(K + 1, 0.0);
+    long double a = 0.0L, b = 0.0L, e = 0.0L, f = 0.0L;
+    for (size_t k = K; k-- > 0;) {
+      hp[k] = T > 0.0 ? std::pow(h[k], 1.0 / T) : 0.0;
+      a += h[k];
+      b += (long double)h[k] * h[k];
+      e += hp[k];
+      f += (long double)hp[k] * hp[k];
+      sw[k] = (double)a;
+      sw2[k] = (double)b;
+      sp[k] = (double)e;
+      sp2[k] = (double)f;
     }
   }
 
@@ -195,6 +216,11 @@ struct CSolve {
   // every smaller c: th decreases in c)
   bool complete_at(double c) const { return h.empty() || !(h[0] * wcut > th(c)); }
 
+  // expected average degree (App. B.2): E[X_uv] = 1 on E_R and the closed
+  // form A x - B x^(1/T) (T = 0: A x), x = w_u w_v / W, elsewhere.  The pairs
+  // outside E_R are summed directly from suffix sums over h and the sums over
+  // the weights outside h (all of whose pairs are outside E_R when h is
+  // complete), so no large excess over E_R is formed and subtracted.
   double f(double c) {
     const double th = this->th(c);
     double A, B = 0.0;
@@ -205,23 +231,28 @@ struct CSolve {
       A = std::ldexp(std::pow(c, (double)d), d);
     }
     const double WT = T > 0.0 ? std::pow(W, 1.0 / T) : 1.0;
-    double err = 0.0;
-    size_t m = h.size();
-    for (size_t u = 0; u < h.size(); ++u) {
+    const size_t K = h.size();
+    const double P = (K ? sp[0] : 0.0) + out_p;
+    long double cnt = 0.0L, s1 = 0.0L, s2 = 0.0L;  // s1 = sum x, s2 = sum x^(1/T) off E_R
+    size_t m = K;
+    for (size_t u = 0; u < K; ++u) {
       const double wu = h[u];
       while (m > 0 && !(wu * h[m - 1] > th)) --m;
-      if (m == 0) break;
-      const bool self = u < m;
-      const double sw = pw[m] - (self ? wu : 0.0);
-      const double cntv = (double)m - (self ? 1.0 : 0.0);
-      double term = A * (wu / W) * sw - cntv;
-      if (T > 0.0) {
-        const double sp = pp[m] - (self ? hp[u] : 0.0);
-        term -= B * (hp[u] / WT) * sp;
+      if (m == 0) {
+        // no vertex of h from u on has an E_R partner
+        s1 += ((long double)W * sw[u] - sw2[u]) / W;
+        if (T > 0.0) s2 += ((long double)P * sp[u] - sp2[u]) / WT;
+        break;
       }
-      err += term;
+      const bool self_out = u >= m;
+      cnt += (long double)(m - (self_out ? 0 : 1));
+      s1 += (long double)(wu / W) * (sw[m] - (self_out ? wu : 0.0) + out_w);
+      if (T > 0.0) s2 += (long double)(hp[u] / WT) * (sp[m] - (self_out ? hp[u] : 0.0) + out_p);
     }
-    return (A * s1 - B * s2 - err) / (double)n;
+    // vertices outside h: every other vertex is a partner off E_R
+    s1 += (long double)out_w - out_q1;
+    if (T > 0.0) s2 += (long double)out_p * P / WT - out_q2;
+    return (double)(((long double)A * s1 - (long double)B * s2 + cnt) / (long double)n);
   }
 
   // bracket by doubling / halving, then regula falsi (Illinois) on log c
@@ -268,18 +299,24 @@ struct CSolve {
   }
 };
 
-// sums over all weights (device) -> s1, s2
-static girg_status csolve_sums(Ctx& cx, const double* w, uint64_t n, double T, double W,
-                               CSolve* cs, hipStream_t st) {
+// sums over the first `cnt` layer-sorted weights (those outside the tail), on
+// the device: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
+static girg_status csolve_out_sums(Ctx& cx, const double* sw, uint64_t cnt, double T, double W,
+                                   CSolve* cs, hipStream_t st) {
+  cs->out_w = cs->out_q1 = cs->out_p = cs->out_q2 = 0.0;
+  if (cnt == 0) return GIRG_OK;
   const double invT = T > 0.0 ? 1.0 / T : 0.0;
-  const int nterms = T > 0.0 ? 3 : 1;
-  HIPCHK(reduce_terms(cx.ar, w, n, nterms, 1, W, invT, cx.red, st));
+  const int nterms = T > 0.0 ? 4 : 2;
+  HIPCHK(reduce_terms(cx.ar, sw, cnt, nterms, 0, W, invT, cx.red, st));
   double r[6];
   HIPCHK(hipMemcpyAsync(r, cx.red, sizeof(r), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  cs->s1 = W - r[0];
-  if (T > 0.0) cs->s2 = r[1] / std::pow(W, invT) * r[1] - r[2];
-  else cs->s2 = 0.0;
+  cs->out_w = r[0];
+  cs->out_q1 = r[1];
+  if (T > 0.0) {
+    cs->out_p = r[2];
+    cs->out_q2 = r[3];
+  }
   return GIRG_OK;
 }
 
@@ -463,9 +500,13 @@ static girg_status validate(const girg_params& p, bool need_beta) {
 // ---------------------------------------------------------------------------
 // the sampler over resident points
 // ---------------------------------------------------------------------------
+// Output placement for batches: called with the edge count once it is known;
+// returns where to write them (nullptr: nowhere, the count is still returned).
+using Place = std::function<uint32_t*(uint64_t m)>;
+
 static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, const double* x,
                              uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
-                             hipStream_t st) {
+                             hipStream_t st, const Place* place = nullptr) {
   Arena& ar = cx.ar;
   Graph g;
   std::memset(&g, 0, sizeof(g));
@@ -556,8 +597,6 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (!(c > 0.0)) {
       CSolve cs;
       cs.n = n; cs.d = d; cs.T = p.T; cs.W = g.W;
-      girg_status s = csolve_sums(cx, w, n, p.T, g.W, &cs, st);
-      if (s != GIRG_OK) return s;
       // heaviest layers first; grow the tail until E_R is complete
       int i0 = g.L;
       uint64_t tail = 0;
@@ -577,6 +616,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         HIPCHK(hipStreamSynchronize(st));
         ar.reset(mk);
         cs.h.assign(asc.rbegin(), asc.rend());
+        girg_status s = csolve_out_sums(cx, sw, g.lstart[i0], p.T, g.W, &cs, st);
+        if (s != GIRG_OK) return s;
         cs.wcut = 0.0;
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
@@ -657,7 +698,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     const std::vector<uint32_t> tab = distant_table(d);
     uint32_t* t = nullptr;
     HIPCHK(hipMalloc(&t, tab.size() * sizeof(uint32_t)));
-    HIPCHK(hipMemcpy(t, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(t, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     cx.dtab[d] = t;
   }
 
@@ -773,9 +815,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   if (info) info->m = mtot;
   if (mtot > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
   if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
+  if (place) edges = (*place)(mtot);
 
   // staged blocks in (pass, chunk, flush) order
-  if (nrec) {
+  if (nrec && edges) {
     uint32_t* perm = ar.get<uint32_t>(nrec);
     uint64_t* kt = ar.get<uint64_t>(nrec);
     uint64_t* off = ar.get<uint64_t>(nrec + 1);
@@ -821,8 +864,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   return GIRG_OK;
 }
 
-static girg_status with_ctx(Ctx** cx) {
-  girg_status s = get_ctx(cx);
+static girg_status with_ctx(Ctx** cx, int slot = 0) {
+  girg_status s = get_ctx(cx, slot);
   if (s != GIRG_OK) return s;
   (*cx)->ar.reset_all();
   (*cx)->ar.clear_failure();
@@ -842,7 +885,10 @@ girg_status girg_release(void) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ctx_mu);
-  g_ctx.erase(dev);
+  for (auto it = g_ctx.begin(); it != g_ctx.end();) {
+    if (it->first.first == dev) it = g_ctx.erase(it);
+    else ++it;
+  }
   return GIRG_OK;
 }
 
@@ -887,7 +933,8 @@ girg_status girg_from_points(const girg_params* p, const double* w, const double
 }
 
 static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t cap,
-                                 uint64_t* m_out, girg_info* info, void* stream) {
+                                 uint64_t* m_out, girg_info* info, void* stream, int slot = 0,
+                                 const Place* place = nullptr) {
   girg_params q = *p;
   girg_status s = validate(q, q.model == 0);
   if (s != GIRG_OK) return s;
@@ -896,10 +943,10 @@ static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t
     if (s != GIRG_OK) return s;
   }
   Ctx* cx = nullptr;
-  if ((s = with_ctx(&cx)) != GIRG_OK) return s;
+  if ((s = with_ctx(&cx, slot)) != GIRG_OK) return s;
   std::lock_guard<std::mutex> lk(cx->mu);
   if (info) std::memset(info, 0, sizeof(*info));
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStream_t st = slot > 0 ? cx->own : static_cast<hipStream_t>(stream);
   const int d = q.model == 1 ? 1 : q.d;
   double* w = cx->ar.get<double>(q.n);
   double* x = cx->ar.get<double>(q.n * d);
@@ -917,7 +964,7 @@ static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t
   cx->mark("-", st);
   HIPCHK(launch_points(g, q.beta, w, x, st));
   cx->mark("points", st);
-  return run_graph(*cx, q, w, x, edges, cap, m_out, info, st);
+  return run_graph(*cx, q, w, x, edges, cap, m_out, info, st, place);
 }
 
 girg_status girg_generate(const girg_params* p, uint32_t* edges, uint64_t cap, uint64_t* m_out,
@@ -947,27 +994,86 @@ girg_status girg_hrg(uint64_t n, double alpha, double T, double R, double avg_de
 girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
                                 uint64_t* offsets, girg_info* infos, void* stream) {
   if (!p || count < 0 || !offsets || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
-  uint64_t used = 0;
   offsets[0] = 0;
+  if (count == 0) return GIRG_OK;
   for (int32_t b = 0; b < count; ++b) {
-    uint64_t m = 0;
-    girg_status s = generate_impl(&p[b], edges ? edges + 2 * used : nullptr, cap - used, &m,
-                                  infos ? &infos[b] : nullptr, stream);
-    if (s == GIRG_EOVERFLOW) {
-      // count the rest so that the caller learns the total
-      uint64_t need = used + m;
-      for (int32_t r = b + 1; r < count; ++r) {
-        uint64_t mr = 0;
-        girg_status sr = generate_impl(&p[r], nullptr, 0, &mr, nullptr, stream);
-        if (sr != GIRG_OK && sr != GIRG_EOVERFLOW) return sr;
-        need += mr;
+    girg_params q = p[b];
+    girg_status s = validate(q, q.model == 0);
+    if (s != GIRG_OK) return fail(s, "instance " + std::to_string(b) + ": " + g_err);
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  // instances run concurrently, one per worker, each on its own context and
+  // stream; an instance's edges go to the caller's buffer at a position
+  // reserved once its count is known (completion order), and are put into
+  // instance order at the end
+  const int nw = std::min<int>(count, kBatchWorkers);
+  std::atomic<int32_t> next{0};
+  std::atomic<bool> stop{false};
+  std::mutex cur_mu;
+  uint64_t cursor = 0;
+  std::vector<uint64_t> m(count, 0), pos(count, 0);
+  std::vector<girg_status> st(count, GIRG_OK);
+  std::vector<std::string> msg(count);
+  auto worker = [&](int slot) {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      if (stop.load()) return;
+      const int32_t b = next.fetch_add(1);
+      if (b >= count) return;
+      const girg_params& q = p[b];
+      const double deg = q.avg_deg > 0.0 ? q.avg_deg : 16.0;
+      uint64_t scap = (uint64_t)(1.25 * 0.5 * deg * (double)q.n) + 4096;
+      Place place = [&, b](uint64_t mb) -> uint32_t* {
+        std::lock_guard<std::mutex> lk(cur_mu);
+        pos[b] = cursor;
+        cursor += mb;
+        return edges && pos[b] + mb <= cap ? edges + 2 * pos[b] : nullptr;
+      };
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        uint64_t mb = 0;
+        // the staging capacity only: edges go where `place` says
+        girg_status s = generate_impl(&q, nullptr, scap, &mb, infos ? &infos[b] : nullptr, nullptr,
+                                      slot, &place);
+        if (s == GIRG_EOVERFLOW && attempt == 0) {
+          scap = mb;
+          continue;
+        }
+        st[b] = s;
+        m[b] = mb;
+        if (s != GIRG_OK) {
+          msg[b] = g_err;
+          stop.store(true);
+        }
+        break;
       }
-      offsets[count] = need;
-      return fail(GIRG_EOVERFLOW, "edge capacity too small");
     }
-    if (s != GIRG_OK) return s;
-    used += m;
-    offsets[b + 1] = used;
+  };
+  std::vector<std::thread> pool;
+  for (int k = 0; k < nw; ++k) pool.emplace_back(worker, k + 1);
+  for (auto& t : pool) t.join();
+  for (int32_t b = 0; b < count; ++b)
+    if (st[b] != GIRG_OK) return fail(st[b], "instance " + std::to_string(b) + ": " + msg[b]);
+  for (int32_t b = 0; b < count; ++b) offsets[b + 1] = offsets[b] + m[b];
+  const uint64_t total = offsets[count];
+  if (total > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
+  // completion order -> instance order
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  bool same = true;
+  for (int32_t b = 0; b < count; ++b) same = same && pos[b] == offsets[b];
+  if (!same && total) {
+    uint32_t* tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, total * 2 * sizeof(uint32_t)));
+    girg_status s = GIRG_OK;
+    hipError_t e = hipMemcpyAsync(tmp, edges, total * 2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, hs);
+    for (int32_t b = 0; b < count && e == hipSuccess; ++b)
+      if (m[b])
+        e = hipMemcpyAsync(edges + 2 * offsets[b], tmp + 2 * pos[b], m[b] * 2 * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) s = fail(GIRG_EDEVICE, std::string("batch reorder: ") + hipGetErrorString(e));
+    (void)hipFree(tmp);
+    return s;
   }
   return GIRG_OK;
 }
@@ -1002,18 +1108,9 @@ girg_status girg_solve_c(const double* w_host, uint64_t n, int32_t d, double T, 
     return fail(GIRG_EINVAL, "invalid d, T or avg_deg");
   CSolve cs;
   cs.n = n; cs.d = d; cs.T = T;
-  long double W = 0.0L, q1 = 0.0L, q2 = 0.0L, q3 = 0.0L;
+  long double W = 0.0L;
   for (uint64_t i = 0; i < n; ++i) W += w_host[i];
   cs.W = (double)W;
-  for (uint64_t i = 0; i < n; ++i) {
-    q1 += w_host[i] * w_host[i] / cs.W;
-    if (T > 0.0) {
-      q2 += std::pow(w_host[i], 1.0 / T);
-      q3 += std::pow(w_host[i] * w_host[i] / cs.W, 1.0 / T);
-    }
-  }
-  cs.s1 = cs.W - (double)q1;
-  cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
   cs.h.assign(w_host, w_host + n);
   std::sort(cs.h.begin(), cs.h.end(), [](double a, double b) { return a > b; });
   cs.wcut = 0.0;
@@ -1027,18 +1124,9 @@ girg_status girg_expected_degree(const double* w_host, uint64_t n, int32_t d, do
   if (!w_host || !deg_out || n < 2 || !(c > 0.0)) return fail(GIRG_EINVAL, "invalid argument");
   CSolve cs;
   cs.n = n; cs.d = d; cs.T = T;
-  long double W = 0.0L, q1 = 0.0L, q2 = 0.0L, q3 = 0.0L;
+  long double W = 0.0L;
   for (uint64_t i = 0; i < n; ++i) W += w_host[i];
   cs.W = (double)W;
-  for (uint64_t i = 0; i < n; ++i) {
-    q1 += w_host[i] * w_host[i] / cs.W;
-    if (T > 0.0) {
-      q2 += std::pow(w_host[i], 1.0 / T);
-      q3 += std::pow(w_host[i] * w_host[i] / cs.W, 1.0 / T);
-    }
-  }
-  cs.s1 = cs.W - (double)q1;
-  cs.s2 = T > 0.0 ? (double)q2 / std::pow(cs.W, 1.0 / T) * (double)q2 - (double)q3 : 0.0;
   cs.h.assign(w_host, w_host + n);
   std::sort(cs.h.begin(), cs.h.end(), [](double a, double b) { return a > b; });
   cs.wcut = 0.0;

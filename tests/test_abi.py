@@ -57,6 +57,15 @@ def test_host_solvers_agree_with_oracle(orc):
         c_orc = orc.solve_c(w, d, T, deg)
         assert abs(c_lib / c_orc - 1) < 1e-12
         assert abs(hg.expected_degree(w, d, T, c_orc) / orc.expected_avg_degree(w, d, T, c_orc) - 1) < 1e-12
+    # heavy tails and low temperature: the closed form over all pairs and its
+    # excess over E_R are both huge there; the sums must not cancel
+    for n, d, beta, T, deg, seed in ((5689, 1, 2.283, 0.3, 15.8, 1008), (100000, 2, 2.1, 0.3, 30.0, 7),
+                                     (20000, 1, 2.05, 0.2, 12.0, 3)):
+        w = synth.pareto_weights(n, beta, seed)
+        c_lib = hg.solve_c(w, d, T, deg)
+        c_orc = orc.solve_c(w, d, T, deg)
+        assert abs(c_lib / c_orc - 1) < 1e-12, (n, d, beta, T)
+        assert abs(orc.expected_avg_degree(w, d, T, c_orc) / deg - 1) < 1e-13
     for T in (0.0, 0.5):
         a = hg.hrg_expected_degree(5000, 0.75, T, 16.0)
         b = orc.hrg_expected_avg_degree(5000, 0.75, T, 16.0)

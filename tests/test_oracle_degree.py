@@ -44,6 +44,25 @@ def test_expected_degree_matches_pairwise_integral(orc, d, T):
         assert got == pytest.approx(want, rel=1e-8, abs=1e-12)
 
 
+@pytest.mark.parametrize("d,T", [(1, 0.3), (2, 0.2), (1, 0.0)])
+def test_expected_degree_heavy_tail(orc, d, T):
+    """beta close to 2 and low temperature, where the closed form summed over
+    all pairs exceeds the degree by orders of magnitude before the E_R
+    correction: the pairwise sum must still be matched closely."""
+    n = 60
+    w = synth.pareto_weights(n, 2.05, 23) * 5.0
+    W = w.sum()
+    for c in (0.3, 2.0, 9.0):
+        want = 0.0
+        for u in range(n):
+            for v in range(n):
+                if u != v:
+                    want += pair_expectation(w[u], w[v], W, c, d, T)
+        want /= n
+        got = orc.expected_avg_degree(w, d, T, c)
+        assert got == pytest.approx(want, rel=1e-9, abs=1e-12)
+
+
 def test_ball_volume_monte_carlo():
     # P(||x_u - x_v|| <= t) = (2t)^d on the torus (App. B.2)
     rng = np.random.default_rng(0)
