@@ -580,14 +580,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(radix_sort(ar, keys, ids, n, g.bits + lbits, st));
   cx.mark("sort", st);
   double* sw = ar.get<double>(n);
-  double* sx = ar.get<double>(n * d);
+  double* rec = ar.get<double>(n * (uint64_t)rec_stride(d, p.model));
   uint32_t* smort = ar.get<uint32_t>(n);
   uint8_t* slayer = ar.get<uint8_t>(n);
-  double* aux = p.model == 1 ? ar.get<double>(3 * n) : nullptr;
-  const bool mixed = p.precision == 1 && p.model == 0 && p.T > 0.0;
-  float* lw = mixed ? ar.get<float>(n) : nullptr;
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
-  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, sx, smort, slayer, aux, lw, st));
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, rec, smort, slayer, st));
   cx.mark("gather", st);
 
   // constant c (App. B.2)
@@ -661,7 +658,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   }
   g.cells = cells;
   if (cells >= 0xFFFFFFFFull * 4) return fail(GIRG_ENOMEM, "too many cells");
-  // layer masks per level up to the deepest insertion level
+  // per-cell layer sets per level up to the deepest insertion level
   int maxI = 0;
   for (int i = 0; i < g.L; ++i)
     if (g.count[i] > 0 && g.I[i] > maxI) maxI = g.I[i];
@@ -688,11 +685,19 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(hipMemcpyAsync(&nsrc, scnt + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   Src* src = ar.get<Src>(std::max<uint64_t>(nsrc, 1));
-  uint64_t* masks = ar.get<uint64_t>(g.moff[kMaxLevels]);
+  const uint64_t ncl = g.moff[kMaxLevels];
+  CellL* cl = ar.get<CellL>(ncl);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sources)");
   cx.mark("-", st);
-  HIPCHK(hipMemsetAsync(masks, 0, g.moff[kMaxLevels] * sizeof(uint64_t), st));
-  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, masks, true, st));
+  HIPCHK(hipMemsetAsync(cl, 0, ncl * sizeof(CellL), st));
+  HIPCHK(launch_sources(g, cx.gd, smort, slayer, P, nullptr, scnt, src, cl, true, st));
+  // (first, count) records of every cell's layers: popcounts, scan, ranks
+  uint32_t* ccnt = ar.get<uint32_t>(ncl + 1);
+  uint2* crec = ar.get<uint2>(std::max<uint64_t>(nsrc, 1));
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (cell layers)");
+  HIPCHK(launch_cell_layers(cx.gd, cl, ncl, ccnt, src, nsrc, crec, false, st));
+  HIPCHK(scan_u32(ar, ccnt, ccnt, ncl, nullptr, st));
+  HIPCHK(launch_cell_layers(cx.gd, cl, ncl, ccnt, src, nsrc, crec, true, st));
   cx.mark("sources_fill", st);
   if (!cx.dtab[d]) {
     const std::vector<uint32_t> tab = distant_table(d);
@@ -703,7 +708,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     cx.dtab[d] = t;
   }
 
-  Verts v{sw, sx, ids, smort, slayer, aux, lw};
+  Verts v{rec, ids, smort, slayer};
   const bool binomial = p.T > 0.0;
 
   // staging of the edges: capacity = the caller's; flush records
@@ -759,10 +764,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
     DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
     cx.mark("-", st);
-    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, P, src, sch[0], masks, sg, df0, st));
+    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, cl, crec, src, sch[0], sg, df0, st));
     cx.mark("type1", st);
     if (sch[2].nchunks)
-      HIPCHK(launch_type2(g, cx.gd, v, P, src, sch[2], pbt, nlev, masks, cx.dtab[d], sg, df1, st));
+      HIPCHK(launch_type2(g, cx.gd, v, cl, crec, src, sch[2], pbt, nlev, cx.dtab[d], sg, df1, st));
     cx.mark("type2", st);
     HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -198,20 +198,33 @@ struct Graph {
   uint64_t jI[kMaxLayers][kMaxLevels];   // j with CL(i,j) == level
   uint64_t jII[kMaxLayers][kMaxLevels];  // j with CL(i,j) >= level
   uint64_t cells;                   // total prefix-sum entries
-  // layer masks: masks[moff[l] + A] has bit j set iff V_j^A is nonempty at
-  // level l (levels up to max_i I(i))
+  // per-cell layer sets: entry moff[l] + A at level l (levels up to
+  // max_i I(i)), bit j set iff V_j^A is nonempty
   uint64_t moff[kMaxLevels + 1];
 };
 
-// Sorted vertex arrays (structure of arrays).
+// Per sorted vertex, everything a pair decision reads, in one aligned record
+// of rec_stride(d, model) doubles: GIRG (w, x_0 .. x_{d-1}), padded to 2, 4 or
+// 8 doubles; HRG (x, e^r, e^-r, sinh r).
+__host__ __device__ constexpr int rec_stride(int d, int model) {
+  return model == 1 ? 4 : (d == 1 ? 2 : (d <= 3 ? 4 : 8));
+}
+
+// Sorted vertex arrays.
 struct Verts {
-  const double* w;      // weight (GIRG) / radius (HRG)
-  const double* x;      // [d][n]
+  const double* rec;    // [n][rec_stride] records
   const uint32_t* id;   // original id
   const uint32_t* mort; // Morton code at level Dmax
   const uint8_t* layer;
-  const double* aux;    // HRG: [3][n] = e^r, e^-r, sinh r ; GIRG mixed: [n] log2 w (as double)
-  const float* lw;      // mixed precision: log2 w per vertex (FP32)
+};
+
+// Per cell and level (index moff[l] + cell): the layers with vertices there
+// and the index of the first of their (first sorted position, count) records,
+// which follow in layer order.
+struct CellL {
+  uint64_t mask;
+  uint32_t base;
+  uint32_t pad;
 };
 
 }  // namespace hg

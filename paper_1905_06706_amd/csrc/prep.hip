@@ -136,9 +136,8 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
                                                 const uint32_t* __restrict__ ids,
                                                 const double* __restrict__ w,
                                                 const double* __restrict__ x, double* __restrict__ sw,
-                                                double* __restrict__ sx, uint32_t* __restrict__ smort,
-                                                uint8_t* __restrict__ slayer,
-                                                double* __restrict__ aux, float* __restrict__ lw) {
+                                                double* __restrict__ rec, uint32_t* __restrict__ smort,
+                                                uint8_t* __restrict__ slayer) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = g->n;
   if (s >= n) return;
@@ -146,22 +145,27 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
   const uint64_t key = keys[s];
   const double wu = w[u];
   sw[s] = wu;
-  for (int k = 0; k < g->d; ++k) sx[(uint64_t)k * n + s] = x[(uint64_t)k * n + u];
   smort[s] = g->bits == 32 ? (uint32_t)key : (uint32_t)(key & ((1ull << g->bits) - 1));
   slayer[s] = (uint8_t)(key >> g->bits);
-  if (lw) lw[s] = (float)log2(wu);
+  const int S = rec_stride(g->d, g->model);
+  double* r = rec + s * (uint64_t)S;
   if (g->model == 1) {
-    aux[s] = exp(wu);
-    aux[(uint64_t)n + s] = exp(-wu);
-    aux[2 * (uint64_t)n + s] = sinh(wu);
+    r[0] = x[u];
+    r[1] = exp(wu);
+    r[2] = exp(-wu);
+    r[3] = sinh(wu);
+  } else {
+    r[0] = wu;
+    for (int k = 0; k < g->d; ++k) r[1 + k] = x[(uint64_t)k * n + u];
+    for (int k = 1 + g->d; k < S; ++k) r[k] = 0.0;
   }
 }
 
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
-                         const double* w, const double* x, double* sw, double* sx, uint32_t* smort,
-                         uint8_t* slayer, double* aux, float* lw, hipStream_t st) {
+                         const double* w, const double* x, double* sw, double* rec, uint32_t* smort,
+                         uint8_t* slayer, hipStream_t st) {
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, gd, keys, ids, w,
-                     x, sw, sx, smort, slayer, aux, lw);
+                     x, sw, rec, smort, slayer);
   return hipGetLastError();
 }
 
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_src_fill(const Graph* __restrict__ g,
                                                   const uint32_t* __restrict__ P,
                                                   const uint32_t* __restrict__ off,
                                                   Src* __restrict__ src,
-                                                  unsigned long long* __restrict__ masks) {
+                                                  CellL* __restrict__ cl) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g->n) return;
   const int h = head_level(g, smort, slayer, (uint32_t)s);
@@ -333,20 +337,61 @@ __global__ __launch_bounds__(256) void k_src_fill(const Graph* __restrict__ g,
     const int sh = g->d * (I - l);
     const uint32_t end = Pi[((uint64_t)A + 1) << sh];
     src[o++] = Src{(uint32_t)s, A, end - (uint32_t)s, (uint32_t)l | ((uint32_t)i << 8)};
-    atomicOr(&masks[g->moff[l] + A], 1ull << i);
+    atomicOr(reinterpret_cast<unsigned long long*>(&cl[g->moff[l] + A].mask), 1ull << i);
   }
+}
+
+// layer counts of every (level, cell) entry, for the scan that gives `base`
+__global__ __launch_bounds__(256) void k_cell_popc(const CellL* __restrict__ cl, uint64_t ne,
+                                                   uint32_t* __restrict__ cnt) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) cnt[e] = (uint32_t)__popcll(cl[e].mask);
+}
+
+__global__ __launch_bounds__(256) void k_cell_base(CellL* __restrict__ cl, uint64_t ne,
+                                                   const uint32_t* __restrict__ off) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) cl[e].base = off[e];
+}
+
+// every source's (first sorted position, count) at its rank among the layers
+// of its cell
+__global__ __launch_bounds__(256) void k_src_rank(const Graph* __restrict__ g,
+                                                  const Src* __restrict__ src, uint64_t nsrc,
+                                                  const CellL* __restrict__ cl,
+                                                  uint2* __restrict__ crec) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nsrc) return;
+  const Src sr = src[q];
+  const uint32_t l = sr.meta & 255u, i = sr.meta >> 8;
+  const CellL c = cl[g->moff[l] + sr.A];
+  crec[c.base + (uint32_t)__popcll(c.mask & ((1ull << i) - 1ull))] = make_uint2(sr.s, sr.na);
 }
 
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
                           const uint8_t* slayer, const uint32_t* P, uint32_t* cnt,
-                          const uint32_t* off, Src* src, uint64_t* masks, bool fill,
-                          hipStream_t st) {
+                          const uint32_t* off, Src* src, CellL* cl, bool fill, hipStream_t st) {
   const unsigned blocks = (unsigned)((g.n + 255) / 256);
   if (!fill)
     hipLaunchKernelGGL(k_src_count, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, cnt);
   else
-    hipLaunchKernelGGL(k_src_fill, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, P, off, src,
-                       reinterpret_cast<unsigned long long*>(masks));
+    hipLaunchKernelGGL(k_src_fill, dim3(blocks), dim3(256), 0, st, gd, smort, slayer, P, off, src, cl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_layers(const Graph* gd, CellL* cl, uint64_t ne, uint32_t* cnt,
+                              const Src* src, uint64_t nsrc, uint2* crec, bool ranks,
+                              hipStream_t st) {
+  if (!ranks) {
+    if (ne)
+      hipLaunchKernelGGL(k_cell_popc, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, cl, ne, cnt);
+  } else {
+    if (ne)
+      hipLaunchKernelGGL(k_cell_base, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, cl, ne, cnt);
+    if (nsrc)
+      hipLaunchKernelGGL(k_src_rank, dim3((unsigned)((nsrc + 255) / 256)), dim3(256), 0, st, gd, src,
+                         nsrc, cl, crec);
+  }
   return hipGetLastError();
 }
 

@@ -4,15 +4,21 @@
 // geometric jumps under pbar, then rejection) cell pairs, plus the kernels for
 // items split because they are large.
 //
-// Work decomposition.  The unit of work is (run source, cell offset).  Waves
-// take chunks of consecutive units by atomic ticket (persistent grid).  Inside
-// a chunk a wave runs converged phases over small per-wave LDS buffers:
-//   A  lanes decode units and append the valid (run, cell B) pairs;
-//   B  lanes take 64 pairs and walk their layers j; non-empty items go to an
-//      item ring (large ones to a deferred list);
+// Work decomposition.  The unit of work is a run source (layer i, level l,
+// cell X).  Waves take chunks of consecutive sources by atomic ticket
+// (persistent grid) and run converged phases over small per-wave LDS buffers:
+//   A  lanes take 64 sources and count their candidate cells; a wave prefix
+//      sum spreads the (source, cell Y) pairs over the lanes, which read the
+//      layer set of Y at level l (one 16-byte entry) and append one entry per
+//      nonempty item to an LDS list;
+//   B  lanes take 64 items, read the (first, count) record of V_j^Y, orient
+//      the pair (smaller cell = A side) and queue it (large ones go to a
+//      deferred list);
 //   C  type-I: 64 Philox blocks (two tests each) per step, flat across the
-//      queued items; type-II: lanes own one item each and draw once per step,
-//      candidates go to a ring that is evaluated 64 at a time.
+//      queued items; type-II: each item makes its first draw at once, items
+//      with draws left are queued, one draw per lane and step, and candidates
+//      go to a ring that is evaluated 64 at a time.
+// Pair decisions read one packed record (w, x) per vertex.
 // Accepted edges are appended (wave ballots) to an LDS buffer that is flushed
 // in blocks of at least 128 edges to a staging array at an atomically reserved
 // position, with a record (pass, chunk, flush number) -> position.  Sorting
@@ -38,13 +44,36 @@ __device__ __forceinline__ T wave_sum(T x) {
 // ---------------------------------------------------------------------------
 // edge decisions (FP64)
 // ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ double torus_r(const double* __restrict__ x, uint32_t n, uint32_t su,
-                                          uint32_t sv) {
+// the record of sorted vertex s, loaded 16 bytes at a time
+template <int D, int MODEL>
+struct Rec {
+  static constexpr int S = rec_stride(D, MODEL);
+  double v[S];
+};
+
+template <int D, int MODEL>
+__device__ __forceinline__ Rec<D, MODEL> load_rec(const double* __restrict__ rec, uint32_t s) {
+  constexpr int S = rec_stride(D, MODEL);
+  Rec<D, MODEL> r;
+  const double2* p = reinterpret_cast<const double2*>(rec + (uint64_t)s * S);
+#pragma unroll
+  for (int q = 0; q < S / 2; ++q) {
+    const double2 t = p[q];
+    r.v[2 * q] = t.x;
+    r.v[2 * q + 1] = t.y;
+  }
+  return r;
+}
+
+// L-infinity torus distance of two records (GIRG: coordinates from slot 1,
+// HRG: the angle / 2 pi in slot 0)
+template <int D, int MODEL>
+__device__ __forceinline__ double torus_r(const Rec<D, MODEL>& a, const Rec<D, MODEL>& b) {
+  constexpr int X0 = MODEL == 1 ? 0 : 1;
   double r = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const double df = fabs(x[(uint64_t)k * n + su] - x[(uint64_t)k * n + sv]);
+    const double df = fabs(a.v[X0 + k] - b.v[X0 + k]);
     const double m = df < 1.0 - df ? df : 1.0 - df;
     r = m > r ? m : r;
   }
@@ -70,14 +99,11 @@ __device__ __forceinline__ double girg_prob(const Graph* __restrict__ g, double 
 
 // HRG: cosh of the hyperbolic distance, cosh(ru - rv) + 2 sinh ru sinh rv
 // sin^2(pi dx), with cosh(ru - rv) from per-vertex e^r, e^-r.
-__device__ __forceinline__ double hrg_coshd(const Verts& v, uint32_t n, uint32_t su, uint32_t sv,
-                                            double dx) {
-  const double* e = v.aux;
-  const double* ei = v.aux + n;
-  const double* sh = v.aux + 2 * (uint64_t)n;
-  const double ch = 0.5 * (e[su] * ei[sv] + e[sv] * ei[su]);
+template <int D>
+__device__ __forceinline__ double hrg_coshd(const Rec<D, 1>& a, const Rec<D, 1>& b, double dx) {
+  const double ch = 0.5 * (a.v[1] * b.v[2] + b.v[1] * a.v[2]);
   const double s = sinpi(dx);
-  return ch + 2.0 * sh[su] * sh[sv] * s * s;
+  return ch + 2.0 * a.v[3] * b.v[3] * s * s;
 }
 
 __device__ __forceinline__ double hrg_prob(const Graph* __restrict__ g, double coshd) {
@@ -88,12 +114,12 @@ __device__ __forceinline__ double hrg_prob(const Graph* __restrict__ g, double c
 template <int D, int MODEL>
 __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const Verts& v,
                                             uint32_t su, uint32_t sv) {
-  const uint32_t n = g->n;
-  const double r = torus_r<D>(v.x, n, su, sv);
+  const Rec<D, MODEL> a = load_rec<D, MODEL>(v.rec, su), b = load_rec<D, MODEL>(v.rec, sv);
+  const double r = torus_r<D, MODEL>(a, b);
   if constexpr (MODEL == 0) {
-    return girg_prob<D>(g, v.w[su], v.w[sv], r);
+    return girg_prob<D>(g, a.v[0], b.v[0], r);
   } else {
-    return hrg_prob(g, hrg_coshd(v, n, su, sv, r));
+    return hrg_prob(g, hrg_coshd<D>(a, b, r));
   }
 }
 
@@ -101,32 +127,32 @@ __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const V
 template <int D, int MODEL>
 __device__ __forceinline__ bool pair_thresh(const Graph* __restrict__ g, const Verts& v,
                                             uint32_t su, uint32_t sv) {
-  const uint32_t n = g->n;
-  const double r = torus_r<D>(v.x, n, su, sv);
+  const Rec<D, MODEL> a = load_rec<D, MODEL>(v.rec, su), b = load_rec<D, MODEL>(v.rec, sv);
+  const double r = torus_r<D, MODEL>(a, b);
   if constexpr (MODEL == 0) {
     // ||x_u - x_v|| <= c (w_u w_v / W)^{1/d}  <=>  r^d W <= c^d w_u w_v
-    return pow_d<D>(r) * g->W <= g->kappa * v.w[su] * v.w[sv];
+    return pow_d<D>(r) * g->W <= g->kappa * a.v[0] * b.v[0];
   } else {
-    return hrg_coshd(v, n, su, sv, r) < g->coshR;
+    return hrg_coshd<D>(a, b, r) < g->coshR;
   }
 }
 
 // ---------------------------------------------------------------------------
 // mixed precision (GIRG, T > 0).  log2 min(p_uv, 1) is evaluated in FP32 as
 // C + (1/T)(log2 w_u + log2 w_v - d log2 r) with C = log2 c - (1/T) log2 W
-// (per-vertex log2 w rounded from FP64, r exact in FP64 then rounded).  Every
-// term carries a relative error of a few 2^-24 and __log2f one of about 2^-22,
-// so |L32 - log2 p| < 2^-20 (1 + |C| + (1/T)(|lw_u| + |lw_v| + d |log2 r|));
+// (w and r exact in FP64, rounded to FP32, then __log2f).  Every term carries
+// a relative error of a few 2^-24 and __log2f one of about 2^-22, so
+// |L32 - log2 p| < 2^-20 (1 + |C| + (1/T)(|log2 w_u| + |log2 w_v| + d |log2 r|));
 // the filter decides only outside 2^-13 times that sum (a factor 128 of
 // slack) and re-decides every other pair with the FP64 formula, so the result
 // is the FP64 path's decision.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double r, float& Lc, float& err) {
+__device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, double wu, double wv,
+                                           double r, float& Lc, float& err) {
   if (!(r >= 0x1p-100)) return false;  // r = 0 (p = 1) or below FP32 range: FP64
   const float lr = __log2f((float)r);
-  const float a = v.lw[su], b = v.lw[sv];
+  const float a = __log2f((float)wu), b = __log2f((float)wv);
   const float L = g->C32 + g->invT32 * (a + b - (float)D * lr);
   err = 0x1p-13f * (1.0f + fabsf(g->C32) + g->invT32 * (fabsf(a) + fabsf(b) + (float)D * fabsf(lr)));
   Lc = fminf(L, 0.0f);
@@ -137,31 +163,33 @@ __device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, const Ve
 template <int D>
 __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Verts& v, uint32_t su,
                                            uint32_t sv, double U, uint64_t& nre) {
-  const double r = torus_r<D>(v.x, g->n, su, sv);
+  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+  const double r = torus_r<D, 0>(a, b);
   float Lc, err;
-  if (U > 0.0 && mixed_logp<D>(g, v, su, sv, r, Lc, err)) {
+  if (U > 0.0 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
     const float lu = __log2f((float)U);
     if (lu < Lc - err) return true;
     if (lu > Lc + err) return false;
   }
   ++nre;
-  return U < girg_prob<D>(g, v.w[su], v.w[sv], r);
+  return U < girg_prob<D>(g, a.v[0], b.v[0], r);
 }
 
-// type-II candidate: accepted iff Acc * pbar < p_uv
+// type-II candidate: accepted iff Acc * pbar < p_uv (apb = Acc * pbar in FP64)
 template <int D>
 __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double acc, double pb, uint64_t& nre) {
-  const double r = torus_r<D>(v.x, g->n, su, sv);
+                                           uint32_t sv, double apb, uint64_t& nre) {
+  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+  const double r = torus_r<D, 0>(a, b);
   float Lc, err;
-  if (acc > 0.0 && pb >= 0x1p-120 && mixed_logp<D>(g, v, su, sv, r, Lc, err)) {
-    const float la = __log2f((float)acc) + __log2f((float)pb);
+  if (apb >= 0x1p-120 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
+    const float la = __log2f((float)apb);
     const float e2 = err + 0x1p-13f * (1.0f + fabsf(la));
     if (la < Lc - e2) return true;
     if (la > Lc + e2) return false;
   }
   ++nre;
-  return acc * pb < girg_prob<D>(g, v.w[su], v.w[sv], r);
+  return apb < girg_prob<D>(g, a.v[0], b.v[0], r);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,16 +236,6 @@ __device__ __forceinline__ bool distant_cell(uint32_t A, int lvl, uint32_t off, 
   return true;
 }
 
-__device__ __forceinline__ void cell_range(const Graph* __restrict__ g, const uint32_t* __restrict__ P,
-                                           int j, int lvl, uint32_t B, uint32_t* b0,
-                                           uint32_t* nb) {
-  const int sh = g->d * (g->I[j] - lvl);
-  const uint32_t* Pj = P + g->pbase[j];
-  const uint32_t lo = Pj[(uint64_t)B << sh];
-  *b0 = lo;
-  *nb = Pj[((uint64_t)B + 1) << sh] - lo;
-}
-
 __device__ __forceinline__ void segment_size(uint64_t N, int e, uint64_t* G, uint64_t* nseg) {
   const int emin = bitlen64(N - 1) - kSegMaxBits;
   if (e < emin) e = emin;
@@ -228,7 +246,8 @@ __device__ __forceinline__ void segment_size(uint64_t N, int e, uint64_t* G, uin
 // ---------------------------------------------------------------------------
 // per-wave edge buffer and its flushes to the staging array
 // ---------------------------------------------------------------------------
-constexpr uint32_t kEdgeBuf = 256;  // LDS edges per wave; flushed above 128
+constexpr uint32_t kEdgeBuf = 256;   // LDS edges per wave; flushed above 128
+constexpr uint32_t kEdgeBuf2 = 192;  // the same for waves that emit at most one edge per lane
 
 struct Out {
   uint2* lb;      // LDS buffer of this wave
@@ -282,16 +301,11 @@ __device__ __forceinline__ void defer_item(bool pending, const ItemRec& rec, uin
 }
 
 // ---------------------------------------------------------------------------
-// per-wave LDS buffers: valid units, item rings, candidate ring
+// per-wave LDS buffers: item lists, item rings, candidate ring
 // ---------------------------------------------------------------------------
-constexpr int kVCap = 128;  // valid-unit buffer (>= 2 x 64)
 constexpr int kQCap = 128;  // item ring (power of two, >= 2 x 64)
 constexpr int kCCap = 128;  // candidate ring (power of two, >= 2 x 64)
 constexpr int kICap = 128;  // item lists (>= 2 x 64)
-
-struct VUnit {
-  uint32_t sidx, B, gap, pad;
-};
 
 // type-I item (or a piece of a split one): Philox blocks [kb, kb + nbk) of
 // the item; cs = index of its first block in the wave's stream of blocks
@@ -302,59 +316,26 @@ struct QItem1 {
 // type-II item (or one segment of a segmented one): candidates [k, N)
 struct QItem2 {
   uint32_t A, B, w3, a0, b0, nb, t;
-  float qs;  // 1 / log2(1 - pbar)
+  uint32_t pidx;  // entry of the pbar table
   uint64_t k, N;
-  double pb, lg;
 };
 
-// type-II candidate: sorted indices, Acc and pbar
+// the pbar-table values an item's draws use, held in registers by the lane
+// that owns the item
+struct PB {
+  double pbar, lg;
+  float qs;  // 1 / log2(1 - pbar)
+};
+__device__ __forceinline__ PB load_pb(const Pbar* __restrict__ pbt, uint32_t pidx) {
+  const Pbar e = pbt[pidx];
+  return PB{e.pbar, e.lg, e.qscale};
+}
+
+// type-II candidate: sorted indices and Acc * pbar
 struct Cand {
   uint32_t su, sv;
-  double acc, pb;
+  double apb;
 };
-
-// phase A: decode units until 64 valid pairs are buffered or the chunk ends
-template <int D, bool DISTANT>
-__device__ __forceinline__ void fill_units(const Graph* __restrict__ g, const Src* __restrict__ src,
-                                           uint64_t& u, uint64_t ue, VUnit* __restrict__ vb,
-                                           uint32_t& vn) {
-  constexpr int NOFF = DISTANT ? Offs<D>::n2 : Offs<D>::n1;
-  while (vn < 64 && __any(u < ue)) {
-    bool valid = false;
-    uint32_t B = 0;
-    int gap = 0;
-    uint64_t sidx = 0;
-    if (u < ue) {
-      sidx = u / NOFF;
-      const uint32_t off = (uint32_t)(u - sidx * NOFF);
-      u += kWave;
-      const Src sr = src[sidx];
-      const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
-      if constexpr (DISTANT) {
-        if (g->jII[li][lvl]) valid = distant_cell<D>(sr.A, lvl, off, &B, &gap) && B > sr.A;
-      } else {
-        if (g->jI[li][lvl]) valid = neighbour_cell<D>(sr.A, lvl, off, &B) && B >= sr.A;
-      }
-    }
-    const uint64_t mv = __ballot(valid);
-    if (valid) vb[vn + lanes_below(mv)] = VUnit{(uint32_t)sidx, B, (uint32_t)gap, 0u};
-    vn += (uint32_t)__popcll(mv);
-  }
-}
-
-// phase B helper: lane takes buffered pair `lane` (if any) and shifts the rest
-__device__ __forceinline__ bool take_unit(VUnit* __restrict__ vb, uint32_t& vn, VUnit& mine) {
-  const uint32_t lane = lane_id();
-  const uint32_t take = vn < 64 ? vn : 64;
-  const bool have = lane < take;
-  if (have) mine = vb[lane];
-  const uint32_t rest = vn - take;
-  VUnit tmp{};
-  if (lane < rest) tmp = vb[take + lane];
-  if (lane < rest) vb[lane] = tmp;
-  vn = rest;
-  return have;
-}
 
 // ---------------------------------------------------------------------------
 // type-I tests.  Pair index k = a * |V_j^B| + b, or for A = B and i = j (only
@@ -475,10 +456,9 @@ __device__ __forceinline__ void enqueue1(bool enq, QItem1& it, QItem1* __restric
 // per-wave source batch: 64 sources, their candidate-cell counts and the
 // inclusive prefix of the counts (load-balanced expansion over the lanes)
 struct SrcSlot {
-  uint64_t jm;    // layers j with CL(i,j) >= level
   uint32_t sidx;  // source index
   uint32_t A;     // its cell
-  uint32_t info;  // level | parity << 8 (parity 255: all 6^d children)
+  uint32_t info;  // level | kind << 8 | layer << 16 (kind: table row, 255 = all offsets)
   uint32_t incl;  // inclusive prefix of the counts
 };
 
@@ -505,12 +485,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 struct IEnt1 {
   uint32_t sidx;  // source of the X side
   uint32_t Y;     // the other cell
+  uint32_t ridx;  // record (first, count) of V_j^Y
   uint32_t j;     // layer of the Y side
 };
 
 template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const Verts& v,
-                                            const uint32_t* __restrict__ P,
+                                            const uint2* __restrict__ crec,
                                             const Src* __restrict__ src, IEnt1* ib, uint32_t& in,
                                             QItem1* __restrict__ q, Ring1& r, uint32_t chunk,
                                             uint32_t& dseq, const DeferOut& dfo, const Stage& sg,
@@ -518,10 +499,10 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
   const uint32_t lane = lane_id();
   const uint32_t take = in < 64 ? in : 64;
   const bool have = lane < take;
-  IEnt1 e{0, 0, 0};
+  IEnt1 e{0, 0, 0, 0};
   if (have) e = ib[lane];
   const uint32_t rest = in - take;
-  IEnt1 tmp{0, 0, 0};
+  IEnt1 tmp{0, 0, 0, 0};
   if (lane < rest) tmp = ib[take + lane];
   if (lane < rest) ib[lane] = tmp;
   in = rest;
@@ -534,8 +515,8 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
   if (have) {
     const Src sr = src[e.sidx];
     const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8, lj = e.j;
-    uint32_t b0, nb;
-    cell_range(g, P, (int)lj, (int)lvl, e.Y, &b0, &nb);
+    const uint2 cr = crec[e.ridx];
+    const uint32_t b0 = cr.x, nb = cr.y;
     // orientation: the smaller cell is the A side
     const bool fwd = e.Y >= sr.A;
     const uint32_t cA = fwd ? sr.A : e.Y, cB = fwd ? e.Y : sr.A;
@@ -561,10 +542,10 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
 }
 
 template <int D, int MODEL, bool T0, bool MX>
-__global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Verts v,
-                                               const uint32_t* __restrict__ P,
-                                               const Src* __restrict__ src, Sched sc,
-                                               const uint64_t* __restrict__ masks, Stage sg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_type1(const Graph* __restrict__ g, Verts v,
+                                               const CellL* __restrict__ cl,
+                                               const uint2* __restrict__ crec,
+                                               const Src* __restrict__ src, Sched sc, Stage sg,
                                                DeferOut dfo) {
   __shared__ IEnt1 ibs[4][kICap];
   __shared__ QItem1 qs[4][kQCap];
@@ -590,14 +571,13 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
       // one source per lane: its neighbour cells
       const uint64_t si = base + lane;
       uint32_t cnt = 0;
-      SrcSlot mine{0ull, (uint32_t)si, 0u, 0u, 0u};
+      SrcSlot mine{(uint32_t)si, 0u, 0u, 0u};
       if (si < se) {
         const Src sr = src[si];
         const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
-        mine.jm = g->jI[li][lvl];
         mine.A = sr.A;
         // info: level | table flag << 8 | layer << 16
-        if (mine.jm) {
+        if (g->jI[li][lvl]) {
           const bool tab = lvl >= 2;
           cnt = tab ? HALF + 1 : NOFF;
           mine.info = lvl | (tab ? 0u : 255u << 8) | (li << 16);
@@ -608,8 +588,8 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
       const uint32_t total = __shfl(mine.incl, 63, 64);
       for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
         const uint32_t k = k0 + lane;
-        uint64_t m = 0;
-        uint32_t Y = 0, sidx = 0;
+        uint64_t m = 0, fm = 0;
+        uint32_t Y = 0, sidx = 0, base = 0;
         if (k < total) {
           uint32_t lo = 0, hi = 64;
           while (lo < hi) {
@@ -639,7 +619,10 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
             ok = neighbour_cell<D>(sl.A, (int)lvl, t, &Y) && Y >= sl.A;
           }
           if (ok) {
-            m = masks[g->moff[lvl] + Y] & sl.jm;
+            const CellL ce = cl[g->moff[lvl] + Y];
+            fm = ce.mask;
+            base = ce.base;
+            m = fm & g->jI[li][lvl];
             if (Y == sl.A) m &= ~((1ull << li) - 1ull);  // j >= i when X = Y
           }
         }
@@ -652,16 +635,18 @@ __global__ __launch_bounds__(256) void k_type1(const Graph* __restrict__ g, Vert
             m &= m - 1;
           }
           const uint64_t mb = __ballot(has);
-          if (has) ib[in + lanes_below(mb)] = IEnt1{sidx, Y, j};
+          if (has)
+            ib[in + lanes_below(mb)] =
+                IEnt1{sidx, Y, base + (uint32_t)__popcll(fm & ((1ull << j) - 1ull)), j};
           in += (uint32_t)__popcll(mb);
           if (in >= 64)
-            take_items1<D, MODEL, T0, MX>(g, v, P, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests,
+            take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests,
                                           nre);
         }
       }
     }
     while (in)
-      take_items1<D, MODEL, T0, MX>(g, v, P, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests, nre);
+      take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests, nre);
     while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
     flush(sg, out);
   }
@@ -747,8 +732,8 @@ struct Ring2 {
 // are taken from it only when both ends of a 2^-13 relative interval agree,
 // otherwise from the FP64 quotient.
 template <bool MX>
-__device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, bool& done,
-                                         Cand& cd, uint64_t& nre) {
+__device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, const PB& pe,
+                                         bool& done, Cand& cd, uint64_t& nre) {
   const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
   ++it.t;
   const uint64_t vv = (((uint64_t)o.y << 32) | o.x) >> 11;
@@ -756,7 +741,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   const uint64_t rem = it.N - it.k;
   uint64_t skip = 0;
   bool end = false, decided = false;
-  if (it.pb >= 1.0) {
+  if (pe.pbar >= 1.0) {
     decided = true;  // every candidate is drawn
   } else if (MX) {
     const uint64_t om = (1ull << 53) - 1 - vv;  // (1 - S) 2^53, exact
@@ -768,7 +753,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
       else
         l2s = __log2f((float)S);
     }
-    const double q32 = (double)(l2s * it.qs);
+    const double q32 = (double)(l2s * pe.qs);
     const double qe = 0x1p-13 * (q32 + 1.0);
     const double qlo = q32 - qe > 0.0 ? q32 - qe : 0.0, qhi = q32 + qe;
     if (qlo >= (double)rem) {
@@ -781,7 +766,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   }
   if (!decided) {
     if (MX) ++nre;
-    const double q = log(S) / it.lg;
+    const double q = log(S) / pe.lg;
     if (q >= (double)rem) end = true;
     else skip = (uint64_t)q;
   }
@@ -800,8 +785,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   }
   cd.su = it.a0 + aa;
   cd.sv = it.b0 + bb;
-  cd.acc = u53(o.z, o.w);
-  cd.pb = it.pb;
+  cd.apb = u53(o.z, o.w) * pe.pbar;
   ++it.k;
   done = it.k >= it.N;
   return true;
@@ -819,8 +803,8 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
   uint2 p0 = make_uint2(0, 0);
   if (lane < take) {
     const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
-    if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.acc, cd.pb, nre);
-    else e0 = cd.acc * cd.pb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
+    if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.apb, nre);
+    else e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
     if (e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
   }
   emit(e0, false, p0, p0, sg, out);
@@ -831,8 +815,9 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
 // runs while at least `need` items are queued or held (to the end if 0)
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts& v,
+                                       const Pbar* __restrict__ pbt,
                                        const QItem2* __restrict__ q, Cand* __restrict__ cq,
-                                       Ring2& r, bool& act, QItem2& it, uint32_t need,
+                                       Ring2& r, bool& act, QItem2& it, PB& pe, uint32_t need,
                                        const Stage& sg, Out& out, uint64_t& ndraws,
                                        uint64_t& ncand, uint64_t& nre) {
   const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
@@ -845,6 +830,7 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
       const uint32_t rk = lanes_below(mi);
       if (rk < avail) {
         it = q[(r.qh + rk) & (kQCap - 1)];
+        pe = load_pb(pbt, it.pidx);
         act = true;
       }
     }
@@ -852,10 +838,10 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     r.qh += got < avail ? got : avail;
     if (!__any(act)) break;
     bool hc = false;
-    Cand cd{0, 0, 0.0, 0.0};
+    Cand cd{0, 0, 0.0};
     if (act) {
       bool done = false;
-      hc = geo_draw<MX>(k0s, k1s, it, done, cd, nre);
+      hc = geo_draw<MX>(k0s, k1s, it, pe, done, cd, nre);
       ++ndraws;
       if (done) act = false;
     }
@@ -886,57 +872,60 @@ __device__ __forceinline__ void enqueue2(bool enq, const QItem2& it, QItem2* __r
 struct IEnt {
   uint32_t sidx;  // source of the X side
   uint32_t Y;     // the other cell
+  uint32_t ridx;  // record (first, count) of V_j^Y
   uint32_t jg;    // layer j of the Y side | gap << 8
 };
 
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const Verts& v,
-                                            const uint32_t* __restrict__ P,
+                                            const uint2* __restrict__ crec,
                                             const Src* __restrict__ src,
                                             const Pbar* __restrict__ pbt, int nlev, IEnt* ib,
                                             uint32_t& in, QItem2* __restrict__ q,
                                             Cand* __restrict__ cq, Ring2& r, bool& act,
-                                            QItem2& cur, uint32_t chunk, uint32_t& dseq,
+                                            QItem2& cur, PB& cpe, uint32_t chunk, uint32_t& dseq,
                                             const DeferOut& dfo, const Stage& sg, Out& out,
                                             uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t take = in < 64 ? in : 64;
   const bool have = lane < take;
-  IEnt e{0, 0, 0};
+  IEnt e{0, 0, 0, 0};
   if (have) e = ib[lane];
   const uint32_t rest = in - take;
-  IEnt tmp{0, 0, 0};
+  IEnt tmp{0, 0, 0, 0};
   if (lane < rest) tmp = ib[take + lane];
   if (lane < rest) ib[lane] = tmp;
   in = rest;
 
   bool fresh = false, hv = false;
   QItem2 it{};
+  PB pe{0.0, 0.0, 0.0f};
   ItemRec rec{};
   if (have) {
     const Src sr = src[e.sidx];
     const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
     const uint32_t lj = e.jg & 255u, gp = (e.jg >> 8) & 255u;
-    uint32_t b0, nb;
-    cell_range(g, P, (int)lj, (int)lvl, e.Y, &b0, &nb);
+    const uint2 cr = crec[e.ridx];
+    const uint32_t b0 = cr.x, nb = cr.y;
     // orientation: the smaller cell is the A side
     const bool fwd = e.Y > sr.A;
     const uint32_t cA = fwd ? sr.A : e.Y, cB = fwd ? e.Y : sr.A;
     const uint32_t ci = fwd ? li : lj, cj = fwd ? lj : li;
     const uint32_t ca0 = fwd ? sr.s : b0, cna = fwd ? sr.na : nb;
     const uint32_t cb0 = fwd ? b0 : sr.s, cnb = fwd ? nb : sr.na;
-    const Pbar pe = pbt[(((uint64_t)ci * g->L + cj) * nlev + lvl) * 2 + (gp - 1)];
-    if (pe.pbar > 0.0 && nb > 0) {
+    const uint32_t pidx = (uint32_t)((((uint64_t)ci * g->L + cj) * nlev + lvl) * 2 + (gp - 1));
+    const Pbar e = pbt[pidx];
+    if (e.pbar > 0.0 && nb > 0) {
       const uint64_t N = (uint64_t)cna * cnb;
       uint64_t G, nseg;
-      segment_size(N, pe.e, &G, &nseg);
+      segment_size(N, e.e, &G, &nseg);
       if (nseg > 1) {
         rec = ItemRec{ca0, cna, cb0, cnb, cA, cB, lvl | (ci << 8) | (cj << 16) | (gp << 24),
-                      (uint32_t)pe.e};
+                      (uint32_t)e.e};
         hv = true;
       } else {
-        it = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), ca0, cb0, cnb, 0u, pe.qscale,
-                    0ull, N, pe.pbar, pe.lg};
+        it = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), ca0, cb0, cnb, 0u, pidx, 0ull, N};
+        pe = PB{e.pbar, e.lg, e.qscale};
         fresh = true;
       }
     }
@@ -944,10 +933,10 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   if (__any(hv)) defer_item(hv, rec, chunk, dseq, dfo);
   // first draw of every new item
   bool hc = false, cont = false;
-  Cand cd{0, 0, 0.0, 0.0};
+  Cand cd{0, 0, 0.0};
   if (fresh) {
     bool done = false;
-    hc = geo_draw<MX>(g->seed_lo, g->seed_hi, it, done, cd, nre);
+    hc = geo_draw<MX>(g->seed_lo, g->seed_hi, it, pe, done, cd, nre);
     ++ndraws;
     cont = !done;
   }
@@ -958,21 +947,22 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
   if (__any(cont)) {
     if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-      draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
+      draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
     enqueue2(cont, it, q, r);
   }
 }
 
 // append the items of mask m (lane's cell Y, gap) to the list; take 64 when full
 template <int D, int MODEL, bool MX>
-__device__ __forceinline__ void push_items2(uint64_t m, uint32_t sidx, uint32_t Y, uint32_t gap,
+__device__ __forceinline__ void push_items2(uint64_t m, uint64_t fm, uint32_t base, uint32_t sidx,
+                                            uint32_t Y, uint32_t gap,
                                             const Graph* __restrict__ g, const Verts& v,
-                                            const uint32_t* __restrict__ P,
+                                            const uint2* __restrict__ crec,
                                             const Src* __restrict__ src,
                                             const Pbar* __restrict__ pbt, int nlev, IEnt* ib,
                                             uint32_t& in, QItem2* __restrict__ q,
                                             Cand* __restrict__ cq, Ring2& r, bool& act,
-                                            QItem2& cur, uint32_t chunk, uint32_t& dseq,
+                                            QItem2& cur, PB& cpe, uint32_t chunk, uint32_t& dseq,
                                             const DeferOut& dfo, const Stage& sg, Out& out,
                                             uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
   while (__any(m != 0)) {
@@ -983,26 +973,28 @@ __device__ __forceinline__ void push_items2(uint64_t m, uint32_t sidx, uint32_t 
       m &= m - 1;
     }
     const uint64_t mb = __ballot(has);
-    if (has) ib[in + lanes_below(mb)] = IEnt{sidx, Y, j | (gap << 8)};
+    if (has)
+      ib[in + lanes_below(mb)] =
+          IEnt{sidx, Y, base + (uint32_t)__popcll(fm & ((1ull << j) - 1ull)), j | (gap << 8)};
     in += (uint32_t)__popcll(mb);
     if (in >= 64)
-      take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, chunk, dseq,
-                                dfo, sg, out, ndraws, ncand, nre);
+      take_items2<D, MODEL, MX>(g, v, crec, src, pbt, nlev, ib, in, q, cq, r, act, cur, cpe, chunk,
+                                dseq, dfo, sg, out, ndraws, ncand, nre);
   }
 }
 
 template <int D, int MODEL, bool MX>
-__global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Verts v,
-                                               const uint32_t* __restrict__ P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_type2(const Graph* __restrict__ g, Verts v,
+                                               const CellL* __restrict__ cl,
+                                               const uint2* __restrict__ crec,
                                                const Src* __restrict__ src, Sched sc,
                                                const Pbar* __restrict__ pbt, int nlev,
-                                               const uint64_t* __restrict__ masks,
                                                const uint32_t* __restrict__ dtab, Stage sg,
                                                DeferOut dfo) {
   __shared__ IEnt ibs[4][kICap];
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
-  __shared__ uint2 ebs[4][kEdgeBuf];
+  __shared__ uint2 ebs[4][kEdgeBuf2];
   __shared__ SrcSlot sss[4][kWave];
   constexpr uint32_t NOFF = Offs<D>::n2;
   const uint32_t wv = threadIdx.x / kWave;
@@ -1022,18 +1014,18 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
     Ring2 r{0, 0, 0, 0};
     bool act = false;
     QItem2 cur{};
+    PB cpe{0.0, 0.0, 0.0f};
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (uint64_t base = sb; base < se; base += kWave) {
       // one source per lane: its candidate cells
       const uint64_t si = base + lane;
       uint32_t cnt = 0;
-      SrcSlot mine{0ull, (uint32_t)si, 0u, 0u, 0u};
+      SrcSlot mine{(uint32_t)si, 0u, 0u, 0u};
       if (si < se) {
         const Src sr = src[si];
         const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
-        mine.jm = g->jII[li][lvl];
         mine.A = sr.A;
-        if (mine.jm) {
+        if (g->jII[li][lvl]) {
           if (lvl >= 3) {
             uint32_t qa[D];
             morton_decode<D>(sr.A, qa);
@@ -1041,10 +1033,10 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
 #pragma unroll
             for (int k = 0; k < D; ++k) par |= (qa[k] & 1u) << k;
             cnt = dtab[1 + par];
-            mine.info = lvl | (par << 8);
+            mine.info = lvl | (par << 8) | (li << 16);
           } else {
             cnt = NOFF;
-            mine.info = lvl | (255u << 8);
+            mine.info = lvl | (255u << 8) | (li << 16);
           }
         }
       }
@@ -1054,8 +1046,8 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
       // (source, offset) pairs spread over the lanes
       for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
         const uint32_t k = k0 + lane;
-        uint64_t m = 0;
-        uint32_t Y = 0, gap = 0, sidx = 0;
+        uint64_t m = 0, fm = 0;
+        uint32_t Y = 0, gap = 0, sidx = 0, base = 0;
         if (k < total) {
           // slot = number of inclusive prefixes <= k
           uint32_t lo = 0, hi = 64;
@@ -1066,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
           }
           const SrcSlot sl = ss[lo];
           const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
-          const uint32_t lvl = sl.info & 255u, par = sl.info >> 8;
+          const uint32_t lvl = sl.info & 255u, par = (sl.info >> 8) & 255u, li = sl.info >> 16;
           sidx = sl.sidx;
           bool ok;
           if (par != 255u) {
@@ -1084,16 +1076,21 @@ __global__ __launch_bounds__(256) void k_type2(const Graph* __restrict__ g, Vert
             ok = distant_cell<D>(sl.A, (int)lvl, t, &Y, &gp) && Y > sl.A;
             gap = (uint32_t)gp;
           }
-          if (ok) m = masks[g->moff[lvl] + Y] & sl.jm;
+          if (ok) {
+            const CellL ce = cl[g->moff[lvl] + Y];
+            fm = ce.mask;
+            base = ce.base;
+            m = fm & g->jII[li][lvl];
+          }
         }
-        push_items2<D, MODEL, MX>(m, sidx, Y, gap, g, v, P, src, pbt, nlev, ib, in, q, cq, r, act,
-                                  cur, c, dseq, dfo, sg, out, ndraws, ncand, nre);
+        push_items2<D, MODEL, MX>(m, fm, base, sidx, Y, gap, g, v, crec, src, pbt, nlev, ib, in, q, cq,
+                                  r, act, cur, cpe, c, dseq, dfo, sg, out, ndraws, ncand, nre);
       }
     }
     while (in)
-      take_items2<D, MODEL, MX>(g, v, P, src, pbt, nlev, ib, in, q, cq, r, act, cur, c, dseq, dfo,
-                                sg, out, ndraws, ncand, nre);
-    draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand, nre);
+      take_items2<D, MODEL, MX>(g, v, crec, src, pbt, nlev, ib, in, q, cq, r, act, cur, cpe, c, dseq,
+                                dfo, sg, out, ndraws, ncand, nre);
+    draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
     while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
     flush(sg, out);
   }
@@ -1117,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
                                                 Stage sg) {
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
-  __shared__ uint2 ebs[4][kEdgeBuf];
+  __shared__ uint2 ebs[4][kEdgeBuf2];
   const uint32_t wv = threadIdx.x / kWave;
   QItem2* q = qs[wv];
   Cand* cq = cqs[wv];
@@ -1132,10 +1129,11 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     Ring2 r{0, 0, 0, 0};
     bool act = false;
     QItem2 cur{};
+    PB cpe{0.0, 0.0, 0.0f};
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-        draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 64, sg, out, ndraws, ncand, nre);
+        draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
       const uint64_t u = u0 + lane;
       bool enq = false;
       QItem2 it{};
@@ -1149,18 +1147,18 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
         const uint64_t s = u - uoff[lo];
         const uint32_t lvl = rr.meta & 255u, li = (rr.meta >> 8) & 255u, lj = (rr.meta >> 16) & 255u,
                        gp = (rr.meta >> 24) & 127u;
-        const Pbar pe = pbt[(((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1)];
+        const uint32_t pidx = (uint32_t)((((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1));
         const uint64_t N = (uint64_t)rr.na * rr.nb;
         uint64_t G, ns;
         segment_size(N, (int)rr.e, &G, &ns);
         const uint64_t k0 = s * G, kend = (s + 1) * G < N ? (s + 1) * G : N;
         it = QItem2{rr.A, rr.B, ctr_word3(lvl, li, lj, kKindType2, (uint32_t)s), rr.a0, rr.b0, rr.nb,
-                    0u, pe.qscale, k0, kend, pe.pbar, pe.lg};
+                    0u, pidx, k0, kend};
         enq = true;
       }
       enqueue2(enq, it, q, r);
     }
-    draws2<D, MODEL, MX>(g, v, q, cq, r, act, cur, 0, sg, out, ndraws, ncand, nre);
+    draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
     while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
     flush(sg, out);
   }
@@ -1240,17 +1238,17 @@ __global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ st
 // mixed precision applies to the binomial GIRG only
 static bool use_mixed(const Graph& g) { return g.precision == 1 && g.model == 0 && g.T > 0.0; }
 
-hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const uint64_t* masks, const Stage& sg,
+hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                        const uint2* crec, const Src* src, const Sched& sc, const Stage& sg,
                         const DeferOut& dfo, hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
   const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
-    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
+    if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, sg, dfo);
     else if constexpr (MM == 0) {
-      if (mx) hipLaunchKernelGGL((k_type1<DD, 0, false, true>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
-      else hipLaunchKernelGGL((k_type1<DD, 0, false, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
-    } else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, P, src, sc, masks, sg, dfo);
+      if (mx) hipLaunchKernelGGL((k_type1<DD, 0, false, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, sg, dfo);
+      else hipLaunchKernelGGL((k_type1<DD, 0, false, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, sg, dfo);
+    } else hipLaunchKernelGGL((k_type1<DD, MM, false, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, sg, dfo);
   });
   return hipGetLastError();
 }
@@ -1270,17 +1268,17 @@ hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const It
   return hipGetLastError();
 }
 
-hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
-                        const uint64_t* masks, const uint32_t* dtab, const Stage& sg,
-                        const DeferOut& dfo, hipStream_t st) {
+hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                        const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
+                        int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
+                        hipStream_t st) {
   const dim3 grid(kPersistBlocks), block(256);
   const bool mx = use_mixed(g);
   HG_DISPATCH_D({
     if constexpr (MM == 0) {
-      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
-      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
-    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, P, src, sc, pbt, nlev, masks, dtab, sg, dfo);
+      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
+      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
+    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
   });
   return hipGetLastError();
 }

@@ -61,19 +61,23 @@ hipError_t launch_points(const Graph& g, double beta, double* w, double* x, hipS
 hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const double* x,
                             uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st);
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
-                         const double* w, const double* x, double* sw, double* sx, uint32_t* smort,
-                         uint8_t* slayer, double* aux, float* lw, hipStream_t st);
+                         const double* w, const double* x, double* sw, double* rec, uint32_t* smort,
+                         uint8_t* slayer, hipStream_t st);
 hipError_t launch_tables(Graph* gd, int Dcap, Pbar* pb, hipStream_t st);
 hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* smort,
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
                           const uint8_t* slayer, const uint32_t* P, uint32_t* cnt,
-                          const uint32_t* off, Src* src, uint64_t* masks, bool fill,
-                          hipStream_t st);
+                          const uint32_t* off, Src* src, CellL* cl, bool fill, hipStream_t st);
+// per-cell layer sets: counts (ranks = false), then bases from their scan
+// `cnt` and the (first, count) records of every source (ranks = true)
+hipError_t launch_cell_layers(const Graph* gd, CellL* cl, uint64_t ne, uint32_t* cnt,
+                              const Src* src, uint64_t nsrc, uint2* crec, bool ranks,
+                              hipStream_t st);
 
 // sampling passes
-hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const uint64_t* masks, const Stage& sg,
+hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                        const uint2* crec, const Src* src, const Sched& sc, const Stage& sg,
                         const DeferOut& dfo, hipStream_t st);
 // distant offsets of a cell at levels >= 3 by the parity pattern p of its
 // coordinates: dtab[0] = stride, dtab[1 + p] = count, entries at
@@ -83,10 +87,10 @@ hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const u
 constexpr int kDistHead = 32;
 std::vector<uint32_t> distant_table(int d);
 
-hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const uint32_t* P,
-                        const Src* src, const Sched& sc, const Pbar* pbt, int nlev,
-                        const uint64_t* masks, const uint32_t* dtab, const Stage& sg,
-                        const DeferOut& dfo, hipStream_t st);
+hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                        const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
+                        int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
+                        hipStream_t st);
 // deferred items: units per record (kind 1: test pieces, kind 2: segments)
 hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
                             hipStream_t st);
