@@ -523,6 +523,19 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   g.alpha = p.alpha;
   g.R = p.R;
   g.coshR = p.model == 1 ? std::cosh(p.R) : 0.0;
+  if (p.model == 1 && p.T > 0.0) {
+    // p_T(d) = x at d = R + 2T ln(1/x - 1)
+    for (int m = 0; m < kHrgTab; ++m) {
+      const double x = (double)m / (kHrgTab - 1);
+      double c = 0.0;
+      if (m == 0) c = INFINITY;
+      else if (m < kHrgTab - 1) {
+        const double dx = p.R + 2.0 * p.T * std::log(1.0 / x - 1.0);
+        c = dx > 0.0 ? std::cosh(dx) : 0.0;
+      }
+      g.hct[m] = c;
+    }
+  }
   g.seed_lo = (uint32_t)p.seed;
   g.seed_hi = (uint32_t)(p.seed >> 32);
   const uint64_t n = p.n;

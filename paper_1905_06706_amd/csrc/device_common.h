@@ -10,6 +10,7 @@ namespace hg {
 
 constexpr int kMaxLayers = 64;
 constexpr int kMaxLevels = 33;  // levels 0..32
+constexpr int kHrgTab = 100;    // HRG distance filter: grid points of p_T
 constexpr int kWave = 64;
 constexpr int kSegExp = 5;       // type-II segment: about 2^5..2^6 expected candidates
 constexpr int kSegMaxBits = 12;  // at most 2^12 segments per item
@@ -201,6 +202,10 @@ struct Graph {
   // per-cell layer sets: entry moff[l] + A at level l (levels up to
   // max_i I(i)), bit j set iff V_j^A is nonempty
   uint64_t moff[kMaxLevels + 1];
+  // HRG binomial distance filter (App. B.4): hct[m] = cosh of the distance at
+  // which p_T equals m / (kHrgTab - 1) (+inf at m = 0, 0 where that distance
+  // is not positive)
+  double hct[kHrgTab];
 };
 
 // Per sorted vertex, everything a pair decision reads, in one aligned record

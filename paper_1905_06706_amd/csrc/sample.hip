@@ -110,6 +110,26 @@ __device__ __forceinline__ double hrg_prob(const Graph* __restrict__ g, double c
   return 1.0 / (exp((acosh(coshd) - g->R) * (0.5 * g->inv_T)) + 1.0);
 }
 
+// binomial HRG decision U < p_T(d) with the distance filter of App. B.4: for
+// U in [x_m, x_{m+1}) on the grid x = m / (kHrgTab - 1), d below the distance
+// where p_T = x_{m+1} means an edge and d above the one where p_T = x_m means
+// none (p_T decreases in d), compared as cosh d against the table.  Only
+// pairs outside a 1e-12 relative margin of both entries, and U outside 1e-9
+// of a grid point, are decided by the table; the rest evaluate p_T, so the
+// result is that of the direct FP64 comparison.
+template <int D>
+__device__ __forceinline__ bool hrg_below(const Graph* __restrict__ g, const Rec<D, 1>& a,
+                                          const Rec<D, 1>& b, double U) {
+  const double ch = hrg_coshd<D>(a, b, torus_r<D, 1>(a, b));
+  const double t = U * (double)(kHrgTab - 1);
+  const int m = (int)t;
+  if (m < kHrgTab - 1 && t - (double)m > 1e-9 && (double)(m + 1) - t > 1e-9) {
+    if (ch < g->hct[m + 1] * (1.0 - 1e-12)) return true;
+    if (ch > g->hct[m] * (1.0 + 1e-12)) return false;
+  }
+  return U < hrg_prob(g, ch);
+}
+
 // probability (binomial variants) of the pair of sorted vertices (su, sv)
 template <int D, int MODEL>
 __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const Verts& v,
@@ -381,6 +401,8 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
       } else {
         const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
         if constexpr (MX) e = mixed_test<D>(g, v, su, sv, U, nre);
+        else if constexpr (MODEL == 1)
+          e = hrg_below<D>(g, load_rec<D, 1>(v.rec, su), load_rec<D, 1>(v.rec, sv), U);
         else e = U < pair_prob<D, MODEL>(g, v, su, sv);
       }
       if (e) {
@@ -804,6 +826,8 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
   if (lane < take) {
     const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
     if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.apb, nre);
+    else if constexpr (MODEL == 1)
+      e0 = hrg_below<D>(g, load_rec<D, 1>(v.rec, cd.su), load_rec<D, 1>(v.rec, cd.sv), cd.apb);
     else e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
     if (e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
   }
