@@ -270,10 +270,11 @@ constexpr uint32_t kEdgeBuf = 256;   // LDS edges per wave; flushed above 128
 constexpr uint32_t kEdgeBuf2 = 192;  // the same for waves that emit at most one edge per lane
 
 struct Out {
-  uint2* lb;      // LDS buffer of this wave
-  uint32_t bn;    // edges in it
-  uint32_t seq;   // flushes of the current chunk
-  uint64_t key;   // pass << 58 | chunk << 26
+  uint2* lb;           // LDS buffer of this wave: sorted positions of the edges
+  uint32_t bn;         // edges in it
+  uint32_t seq;        // flushes of the current chunk
+  uint64_t key;        // pass << 58 | chunk << 26
+  const uint32_t* id;  // original ids of the sorted positions (applied at the flush)
 };
 
 __device__ __forceinline__ void flush(const Stage& sg, Out& o) {
@@ -283,7 +284,10 @@ __device__ __forceinline__ void flush(const Stage& sg, Out& o) {
   if (lane == 0) pos = atomicAdd(sg.cursor, (unsigned long long)o.bn);
   pos = __shfl(pos, 0, 64);
   for (uint32_t i = lane; i < o.bn; i += kWave)
-    if (pos + i < sg.cap) sg.buf[pos + i] = o.lb[i];
+    if (pos + i < sg.cap) {
+      const uint2 e = o.lb[i];
+      sg.buf[pos + i] = make_uint2(o.id[e.x], o.id[e.y]);
+    }
   if (lane == 0) {
     atomicAdd(&sg.stats[8 + (o.key >> 58)], (unsigned long long)o.bn);  // edges per pass
     const unsigned int slot = atomicAdd(sg.nrec, 1u);
@@ -406,8 +410,8 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
         else e = U < pair_prob<D, MODEL>(g, v, su, sv);
       }
       if (e) {
-        if (h == 0) p0 = make_uint2(v.id[su], v.id[sv]);
-        else p1 = make_uint2(v.id[su], v.id[sv]);
+        if (h == 0) p0 = make_uint2(su, sv);
+        else p1 = make_uint2(su, sv);
       }
       if (h == 0) e0 = e; else e1 = e;
       ++ntests;
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint64_t se = sb + sc.chunk < sc.nunits ? sb + sc.chunk : sc.nunits;
     uint32_t in = 0, dseq = 0;
     Ring1 r{0, 0, 0, 0};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
     for (uint64_t base = sb; base < se; base += kWave) {
       // one source per lane: its neighbour cells
       const uint64_t si = base + lane;
@@ -698,7 +702,7 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
     const uint64_t ub = (uint64_t)c * sc.chunk;
     const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
     Ring1 r{0, 0, 0, 0};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
         step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
@@ -829,7 +833,7 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
     else if constexpr (MODEL == 1)
       e0 = hrg_below<D>(g, load_rec<D, 1>(v.rec, cd.su), load_rec<D, 1>(v.rec, cd.sv), cd.apb);
     else e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
-    if (e0) p0 = make_uint2(v.id[cd.su], v.id[cd.sv]);
+    if (e0) p0 = make_uint2(cd.su, cd.sv);
   }
   emit(e0, false, p0, p0, sg, out);
   r.ch += take;
@@ -1039,7 +1043,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     bool act = false;
     QItem2 cur{};
     PB cpe{0.0, 0.0, 0.0f};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
     for (uint64_t base = sb; base < se; base += kWave) {
       // one source per lane: its candidate cells
       const uint64_t si = base + lane;
@@ -1154,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     bool act = false;
     QItem2 cur{};
     PB cpe{0.0, 0.0, 0.0f};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26)};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       if (r.qt - r.qh > (uint32_t)(kQCap - 64))
         draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
