@@ -197,6 +197,70 @@ def cpu_baseline_batch(params: list, budget_s: float = 15.0) -> dict:
             "sample": f"the first {k} of {len(params)} instances, whole graphs; {m} edges in {dt:.2f} s"}
 
 
+# stage groups of the sweep, after the paper's breakdown of a run (Sec. 5.1)
+SWEEP_GROUPS = {
+    "points": ("points",),
+    "constant": ("c_solve",),
+    "pre": ("layer_key", "sort", "gather", "tables", "cells", "sources_count", "sources_fill"),
+    "edges": ("type1", "type2", "split_prep", "split1", "segment_prep", "segments2", "order"),
+}
+
+
+def sweep(steps: int, warmup: int) -> int:
+    """Scaling sweep in the manner of the paper's Fig. 2: one parameter at a
+    time around the base case d=1, n=2^15, T=0, beta=2.5, average degree 10
+    (n up to 2^24, the degree, T, d), each graph counted but not stored (null
+    edge buffer, capacity 0), as the paper measures.  Prints one JSON line
+    with ms/step and ns/edge per stage group for every configuration."""
+    import torch
+    import paper_1905_06706_amd as hg
+    L = hg.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    base = dict(n=2**15, d=1, beta=2.5, T=0.0, deg=10.0)
+    series = [("n", "n", [2**k for k in range(12, 25, 2)]),
+              ("avg_deg", "deg", [5.0, 10.0, 20.0, 40.0, 80.0]),
+              ("T", "T", [0.0, 0.1, 0.3, 0.5, 0.7, 0.9]),
+              ("d", "d", [1, 2, 3, 4])]
+    rows = []
+    for name, key, values in series:
+        for val in values:
+            cfg = dict(base)
+            cfg[key] = val
+            if name != "n":
+                cfg["n"] = 2**20
+            p = hg.make_params(cfg["n"], cfg["d"], cfg["beta"], cfg["T"], cfg["deg"], 0.0, 7, 0)
+            m = ctypes.c_uint64(0)
+            for _ in range(warmup):
+                L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), None, sp)
+            hg.set_profiling(True)
+            groups = {g: 0.0 for g in SWEEP_GROUPS}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st = L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), None, sp)
+                if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
+                    hg._check(st)
+                for stage, ms in hg.stage_times():
+                    for g, members in SWEEP_GROUPS.items():
+                        if stage in members:
+                            groups[g] += ms / steps
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            hg.set_profiling(False)
+            edges = max(int(m.value), 1)
+            row = {"series": name, **cfg, "edges": int(m.value), "ms_per_step": dt * 1e3,
+                   "ns_per_edge": dt * 1e9 / edges,
+                   "ns_per_edge_by_stage": {g: v * 1e6 / edges for g, v in groups.items()}}
+            rows.append(row)
+            print(f"[sweep] {name}={val}: n={cfg['n']} m={m.value} {dt*1e3:.3f} ms "
+                  f"{row['ns_per_edge']:.3f} ns/edge "
+                  + " ".join(f"{g}={v:.3f}" for g, v in row["ns_per_edge_by_stage"].items()),
+                  file=sys.stderr, flush=True)
+    print(json.dumps({"sweep": rows, "steps": steps, "warmup": warmup, "data": "synthetic",
+                      "mode": "count only (no edge store)"}), flush=True)
+    return 0
+
+
 def hbm_copy(mib: int, steps: int, warmup: int) -> int:
     """A plain device-to-device copy of a known size: the reference that
     scales the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of the sampling
@@ -227,6 +291,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hbm-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (HBM calibration)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="scaling sweep over n, degree, T and d (count only), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler has no "
@@ -234,6 +300,8 @@ def main() -> int:
         return 2
     if args.hbm_copy:
         return hbm_copy(args.hbm_copy, args.steps, args.warmup)
+    if args.sweep:
+        return sweep(min(args.steps, 5), min(args.warmup, 1))
 
     import torch
     import paper_1905_06706_amd as hg

@@ -803,7 +803,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     cx.mark("-", st);
     HIPCHK(launch_iota(perm, nd, st));
     HIPCHK(hipMemcpyAsync(kt, dkey[q], nd * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    HIPCHK(radix_sort(ar, kt, perm, nd, 48, st));
+    // keys chunk << 24 | sequence, chunk < nchunks of the pass that deferred them
+    HIPCHK(radix_sort(ar, kt, perm, nd, 24 + bitlen(sch[q == 0 ? 0 : 2].nchunks), st));
     HIPCHK(launch_rec_gather(drec[q], perm, nd, dsorted, st));
     HIPCHK(launch_rec_units(dsorted, nd, q == 0 ? 1 : 2, uoff, st));
     HIPCHK(scan_u64(ar, uoff, uoff, nd, uoff + nd, st));
@@ -831,7 +832,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(hipStreamSynchronize(st));
   *m_out = mtot;
   if (info) info->m = mtot;
-  if (mtot > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
+  if (mtot > cap) {
+    cx.collect();  // stage times of a counting call (null buffer, capacity 0)
+    return fail(GIRG_EOVERFLOW, "edge capacity too small");
+  }
   if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
   if (place) edges = (*place)(mtot);
 
@@ -843,8 +847,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge order)");
     cx.mark("-", st);
     HIPCHK(launch_iota(perm, nrec, st));
-    HIPCHK(hipMemcpyAsync(kt, rkey, nrec * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    HIPCHK(radix_sort(ar, kt, perm, nrec, 64, st));
+    uint32_t maxch = 1;
+    for (int q = 0; q < 4; ++q) maxch = std::max(maxch, sch[q].nchunks);
+    const int cb = bitlen(maxch);
+    HIPCHK(launch_rec_repack(rkey, kt, nrec, cb, st));
+    HIPCHK(radix_sort(ar, kt, perm, nrec, 28 + cb, st));
     HIPCHK(launch_stage_counts(rcnt, perm, nrec, off, st));
     HIPCHK(scan_u64(ar, off, off, nrec, off + nrec, st));
     HIPCHK(launch_stage_copy(stage, rpos, rcnt, perm, off, nrec, reinterpret_cast<uint2*>(edges), st));

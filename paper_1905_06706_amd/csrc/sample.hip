@@ -1226,6 +1226,16 @@ __global__ __launch_bounds__(256) void k_rec_gather(const ItemRec* __restrict__ 
 
 // staged blocks -> final order: count of sorted record w, then copy (one wave
 // per record)
+// flush keys pass << 58 | chunk << 26 | flush repacked to pass << (cb + 26) |
+// chunk << 26 | flush (chunk < 2^cb), same order, fewer bits to sort
+__global__ __launch_bounds__(256) void k_rec_repack(const uint64_t* __restrict__ in,
+                                                    uint64_t* __restrict__ out, uint32_t n, int cb) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = in[i];
+  out[i] = ((k >> 58) << (cb + 26)) | (((k >> 26) & 0xFFFFFFFFull) << 26) | (k & ((1ull << 26) - 1));
+}
+
 __global__ __launch_bounds__(256) void k_stage_counts(const uint32_t* __restrict__ rcnt,
                                                       const uint32_t* __restrict__ perm,
                                                       uint32_t nrec, uint64_t* __restrict__ cnt) {
@@ -1367,6 +1377,12 @@ hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_
 hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_rec_gather, dim3((nrec + 255) / 256), dim3(256), 0, st, in, perm, nrec, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_repack(const uint64_t* in, uint64_t* out, uint32_t n, int cb, hipStream_t st) {
+  if (n)
+    hipLaunchKernelGGL(k_rec_repack, dim3((n + 255) / 256), dim3(256), 0, st, in, out, n, cb);
   return hipGetLastError();
 }
 

@@ -102,6 +102,8 @@ hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const It
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
                          int nlev, const Stage& sg, hipStream_t st);
+// flush keys repacked to 28 + cb bits (chunk indices < 2^cb)
+hipError_t launch_rec_repack(const uint64_t* in, uint64_t* out, uint32_t n, int cb, hipStream_t st);
 // staged blocks in record order
 hipError_t launch_stage_counts(const uint32_t* rcnt, const uint32_t* perm, uint32_t nrec,
                                uint64_t* cnt, hipStream_t st);
