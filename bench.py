@@ -261,6 +261,81 @@ def sweep(steps: int, warmup: int) -> int:
     return 0
 
 
+def coupling(n: int = 10**6, deg: float = 100.0, alpha: float = 0.75, seed: int = 11) -> int:
+    """The HRG / GIRG comparison of the paper's Sec. 5.3 (threshold variants):
+    an HRG with average degree `deg` and the GIRG on the same points through
+    the mapping of Sec. 2.3 (w = exp((R - r) / 2), x = angle / 2 pi, d = 1).
+    Reports the edges the GIRG of expected degree `deg` lacks (HRG \ GIRG)
+    and adds (GIRG \ HRG), the largest GIRG degree whose graph is a subgraph
+    of the HRG (bisection; GIRG edge sets grow with c), and the smallest
+    degree of a supergraph (from the largest c any HRG edge needs: r <=
+    c w_u w_v / W).  One JSON line."""
+    import torch
+    import paper_1905_06706_amd as hg
+    t_start = time.perf_counter()
+    R = hg.hrg_solve_R(n, alpha, 0.0, deg)
+    r, x = hg.points(n, model=1, alpha=alpha, R=R, seed=seed)
+    eh = hg.from_points(r, x, T=0.0, model=1, R=R, alpha=alpha, seed=seed).edges.long()
+
+    def keys(e):
+        lo = torch.minimum(e[:, 0], e[:, 1])
+        hi = torch.maximum(e[:, 0], e[:, 1])
+        return torch.sort(lo * (1 << 32) + hi).values
+
+    kh = keys(eh)
+    w = torch.exp((R - r) * 0.5).contiguous()
+    W = float(w.sum())
+    xg = x.contiguous()
+
+    def girg_keys(avg_deg=0.0, c=0.0):
+        res = hg.from_points(w, xg, T=0.0, c=c, avg_deg=avg_deg, seed=seed)
+        return keys(res.edges.long()), res.info["c"]
+
+    def count_not_in(a, b):
+        """entries of sorted a that are not in sorted b"""
+        if len(a) == 0:
+            return 0
+        if len(b) == 0:
+            return len(a)
+        i = torch.searchsorted(b, a).clamp(max=len(b) - 1)
+        return int((b[i] != a).sum())
+
+    kg, c100 = girg_keys(avg_deg=deg)
+    missing = count_not_in(kh, kg)
+    additional = count_not_in(kg, kh)
+    # largest degree with GIRG subset of HRG: bisection on the expected degree
+    lo, hi = 0.01 * deg, deg
+    for _ in range(24):
+        mid = (lo * hi) ** 0.5
+        km, _ = girg_keys(avg_deg=mid)
+        if count_not_in(km, kh) == 0:
+            lo = mid
+        else:
+            hi = mid
+    d_sub = lo
+    # supergraph: the largest c needed by an HRG edge (d = 1 torus distance)
+    u, v = eh[:, 0], eh[:, 1]
+    df = (x[0, u] - x[0, v]).abs()
+    dist = torch.minimum(df, 1.0 - df)
+    c_super = float((dist * W / (w[u] * w[v])).max())
+    D_super = hg.expected_degree(w.cpu().numpy(), 1, 0.0, c_super)
+    d_hrg = 2.0 * len(kh) / n
+    # the GIRG whose expected degree is the HRG's realised one
+    km, cm = girg_keys(avg_deg=d_hrg)
+    matched = {"girg_expected_degree": d_hrg, "girg_c": cm, "girg_edges": len(km),
+               "missing_hrg_minus_girg": count_not_in(kh, km),
+               "additional_girg_minus_hrg": count_not_in(km, kh)}
+    out = {"experiment": "HRG vs GIRG coupling (threshold variants)", "n": n, "alpha": alpha,
+           "beta": 2 * alpha + 1, "R": R, "seed": seed, "hrg_edges": len(kh), "hrg_avg_degree": d_hrg,
+           "girg_expected_degree": deg, "girg_c": c100, "girg_edges": len(kg),
+           "missing_hrg_minus_girg": missing, "additional_girg_minus_hrg": additional,
+           "subgraph_expected_degree": d_sub, "supergraph_c": c_super,
+           "supergraph_expected_degree": D_super, "at_hrg_degree": matched,
+           "seconds": time.perf_counter() - t_start}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def hbm_copy(mib: int, steps: int, warmup: int) -> int:
     """A plain device-to-device copy of a known size: the reference that
     scales the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of the sampling
@@ -293,6 +368,8 @@ def main() -> int:
                     help="only time a plain device copy of MIB MiB (HBM calibration)")
     ap.add_argument("--sweep", action="store_true",
                     help="scaling sweep over n, degree, T and d (count only), one JSON line")
+    ap.add_argument("--coupling", action="store_true",
+                    help="HRG vs GIRG sub/supergraph experiment (threshold, n = 10^6), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler has no "
@@ -302,6 +379,8 @@ def main() -> int:
         return hbm_copy(args.hbm_copy, args.steps, args.warmup)
     if args.sweep:
         return sweep(min(args.steps, 5), min(args.warmup, 1))
+    if args.coupling:
+        return coupling()
 
     import torch
     import paper_1905_06706_amd as hg
