@@ -901,7 +901,7 @@ struct IEnt {
   uint32_t sidx;  // source of the X side
   uint32_t Y;     // the other cell
   uint32_t ridx;  // record (first, count) of V_j^Y
-  uint32_t jg;    // layer j of the Y side | gap << 8
+  uint32_t jg;    // layer j of the Y side | gap << 8 | layer i of X << 16 | level << 24
 };
 
 template <int D, int MODEL, bool MX>
@@ -930,9 +930,13 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   PB pe{0.0, 0.0, 0.0f};
   ItemRec rec{};
   if (have) {
+    const uint32_t lj = e.jg & 255u, gp = (e.jg >> 8) & 255u, li = (e.jg >> 16) & 255u,
+                   lvl = e.jg >> 24;
+    // three independent loads; the pbar table is symmetric in the layer pair
+    // (it depends on w_i w_j only), so it is indexed before the orientation
+    const uint32_t pidx = (uint32_t)((((uint64_t)li * g->L + lj) * nlev + lvl) * 2 + (gp - 1));
+    const Pbar pv = pbt[pidx];
     const Src sr = src[e.sidx];
-    const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
-    const uint32_t lj = e.jg & 255u, gp = (e.jg >> 8) & 255u;
     const uint2 cr = crec[e.ridx];
     const uint32_t b0 = cr.x, nb = cr.y;
     // orientation: the smaller cell is the A side
@@ -941,19 +945,17 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
     const uint32_t ci = fwd ? li : lj, cj = fwd ? lj : li;
     const uint32_t ca0 = fwd ? sr.s : b0, cna = fwd ? sr.na : nb;
     const uint32_t cb0 = fwd ? b0 : sr.s, cnb = fwd ? nb : sr.na;
-    const uint32_t pidx = (uint32_t)((((uint64_t)ci * g->L + cj) * nlev + lvl) * 2 + (gp - 1));
-    const Pbar e = pbt[pidx];
-    if (e.pbar > 0.0 && nb > 0) {
+    if (pv.pbar > 0.0 && nb > 0) {
       const uint64_t N = (uint64_t)cna * cnb;
       uint64_t G, nseg;
-      segment_size(N, e.e, &G, &nseg);
+      segment_size(N, pv.e, &G, &nseg);
       if (nseg > 1) {
         rec = ItemRec{ca0, cna, cb0, cnb, cA, cB, lvl | (ci << 8) | (cj << 16) | (gp << 24),
-                      (uint32_t)e.e};
+                      (uint32_t)pv.e};
         hv = true;
       } else {
         it = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), ca0, cb0, cnb, 0u, pidx, 0ull, N};
-        pe = PB{e.pbar, e.lg, e.qscale};
+        pe = PB{pv.pbar, pv.lg, pv.qscale};
         fresh = true;
       }
     }
@@ -983,7 +985,7 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
 // append the items of mask m (lane's cell Y, gap) to the list; take 64 when full
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void push_items2(uint64_t m, uint64_t fm, uint32_t base, uint32_t sidx,
-                                            uint32_t Y, uint32_t gap,
+                                            uint32_t Y, uint32_t tag,
                                             const Graph* __restrict__ g, const Verts& v,
                                             const uint2* __restrict__ crec,
                                             const Src* __restrict__ src,
@@ -1003,7 +1005,7 @@ __device__ __forceinline__ void push_items2(uint64_t m, uint64_t fm, uint32_t ba
     const uint64_t mb = __ballot(has);
     if (has)
       ib[in + lanes_below(mb)] =
-          IEnt{sidx, Y, base + (uint32_t)__popcll(fm & ((1ull << j) - 1ull)), j | (gap << 8)};
+          IEnt{sidx, Y, base + (uint32_t)__popcll(fm & ((1ull << j) - 1ull)), j | (tag << 8)};
     in += (uint32_t)__popcll(mb);
     if (in >= 64)
       take_items2<D, MODEL, MX>(g, v, crec, src, pbt, nlev, ib, in, q, cq, r, act, cur, cpe, chunk,
@@ -1075,7 +1077,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
         const uint32_t k = k0 + lane;
         uint64_t m = 0, fm = 0;
-        uint32_t Y = 0, gap = 0, sidx = 0, base = 0;
+        uint32_t Y = 0, gap = 0, sidx = 0, base = 0, tli = 0, tlvl = 0;
         if (k < total) {
           // slot = number of inclusive prefixes <= k
           uint32_t lo = 0, hi = 64;
@@ -1088,6 +1090,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
           const uint32_t lvl = sl.info & 255u, par = (sl.info >> 8) & 255u, li = sl.info >> 16;
           sidx = sl.sidx;
+          tli = li;
+          tlvl = lvl;
           bool ok;
           if (par != 255u) {
             uint32_t qa[D], b[D];
@@ -1111,8 +1115,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             m = fm & g->jII[li][lvl];
           }
         }
-        push_items2<D, MODEL, MX>(m, fm, base, sidx, Y, gap, g, v, crec, src, pbt, nlev, ib, in, q, cq,
-                                  r, act, cur, cpe, c, dseq, dfo, sg, out, ndraws, ncand, nre);
+        push_items2<D, MODEL, MX>(m, fm, base, sidx, Y, gap | (tli << 8) | (tlvl << 16), g, v, crec,
+                                  src, pbt, nlev, ib, in, q, cq, r, act, cur, cpe, c, dseq, dfo, sg,
+                                  out, ndraws, ncand, nre);
       }
     }
     while (in)
