@@ -186,17 +186,18 @@ struct CSolve {
   double out_w = 0.0, out_q1 = 0.0, out_p = 0.0, out_q2 = 0.0;
   double wcut;  // every weight not in h is <= wcut
 
-  // h must already be in descending order
-  void prepare() {
+  // h must already be in descending order; hp (h^(1/T), same order) may be
+  // given, else it is computed here
+  void prepare(bool have_hp = false) {
     const size_t K = h.size();
-    hp.assign(K, 0.0);
+    if (!have_hp) hp.assign(K, 0.0);
     sw.assign(K + 1, 0.0);
     sw2.assign(K + 1, 0.0);
     sp.assign(K + 1, 0.0);
     sp2.assign(K + 1, 0.0);
     long double a = 0.0L, b = 0.0L, e = 0.0L, f = 0.0L;
     for (size_t k = K; k-- > 0;) {
-      hp[k] = T > 0.0 ? std::pow(h[k], 1.0 / T) : 0.0;
+      if (!have_hp) hp[k] = T > 0.0 ? std::pow(h[k], 1.0 / T) : 0.0;
       a += h[k];
       b += (long double)h[k] * h[k];
       e += hp[k];
@@ -610,7 +611,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
       // heaviest layers first; grow the tail until E_R is complete
       int i0 = g.L;
       uint64_t tail = 0;
-      while (i0 > 0 && tail < 4096) { --i0; tail += (uint64_t)g.count[i0]; }
+      while (i0 > 0 && tail < 1024) { --i0; tail += (uint64_t)g.count[i0]; }
       for (;;) {
         // the tail of the layer-sorted weights, sorted by value on the device
         const uint64_t K = n - g.lstart[i0];
@@ -621,22 +622,30 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         HIPCHK(hipMemcpyAsync(tk, sw + g.lstart[i0], K * sizeof(double), hipMemcpyDeviceToDevice, st));
         HIPCHK(launch_iota(tv, K, st));
         HIPCHK(radix_sort(ar, tk, tv, K, 64, st));  // positive doubles order as integers
-        std::vector<double> asc(K);
+        double* tp = p.T > 0.0 ? ar.get<double>(K) : nullptr;
+        if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
+        if (tp) HIPCHK(launch_pow_bits(tk, tp, K, 1.0 / p.T, st));
+        std::vector<double> asc(K), ascp(tp ? K : 0);
         HIPCHK(hipMemcpyAsync(asc.data(), tk, K * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (tp) HIPCHK(hipMemcpyAsync(ascp.data(), tp, K * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         ar.reset(mk);
         cs.h.assign(asc.rbegin(), asc.rend());
+        cs.hp.assign(ascp.rbegin(), ascp.rend());
+        if (!tp) cs.hp.assign(K, 0.0);
         girg_status s = csolve_out_sums(cx, sw, g.lstart[i0], p.T, g.W, &cs, st);
         if (s != GIRG_OK) return s;
         cs.wcut = 0.0;
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
-        cs.prepare();
+        cs.prepare(true);
         if (cs.solve(p.avg_deg, &c) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
         if (cs.complete_at(c) || i0 == 0) break;
-        // take layers until the tail at least doubles
-        const uint64_t want = 2 * cs.h.size();
-        while (i0 > 0 && n - g.lstart[i0] < want) --i0;
+        // take every layer whose largest weight could pair with the heaviest
+        // vertex inside E_R at this c, with a factor 2 of margin for the next
+        // solve's c (the next lower layer fails that test, so this grows)
+        const double cut = 0.5 * cs.th(c) / cs.h[0];
+        while (i0 > 0 && (g.count[i0 - 1] == 0 || g.ext[i0 - 1] > cut)) --i0;
       }
     }
     g.c = c;

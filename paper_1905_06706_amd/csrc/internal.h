@@ -60,6 +60,8 @@ hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, ui
 hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
                         double invT, double* out6, hipStream_t st);
 hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t st);
+// out[i] = x_i^e, x_i positive doubles given as bit patterns (u64)
+hipError_t launch_pow_bits(const uint64_t* xb, double* out, uint64_t n, double e, hipStream_t st);
 hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
                       hipStream_t st);
 

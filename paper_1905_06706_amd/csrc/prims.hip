@@ -250,6 +250,19 @@ hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int 
   return hipGetLastError();
 }
 
+// out[i] = x_i^e for positive doubles x_i stored as their bit patterns
+__global__ void k_pow_bits(const uint64_t* __restrict__ xb, double* __restrict__ out, uint64_t n,
+                           double e) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = pow(__longlong_as_double((long long)xb[i]), e);
+}
+
+hipError_t launch_pow_bits(const uint64_t* xb, double* out, uint64_t n, double e, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pow_bits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xb, out, n, e);
+  return hipGetLastError();
+}
+
 __global__ void k_iota(uint32_t* __restrict__ p, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (uint32_t)i;

@@ -209,3 +209,16 @@ def test_mixed_precision_ignored_where_undefined(hg):
     b = hg.generate(20000, d=2, beta=2.5, T=0.0, avg_deg=10.0, seed=3, precision=1)
     assert np.array_equal(a.edges.cpu().numpy(), b.edges.cpu().numpy())
     assert b.info["rechecks"] == 0
+
+
+@pytest.mark.parametrize("n,d,beta,T,deg,seed", [(2**16, 3, 2.1, 0.8, 30.0, 41), (2**17, 1, 2.05, 0.3, 40.0, 42),
+                                                 (2**15, 2, 2.2, 0.0, 60.0, 43)])
+def test_c_solve_with_a_large_heavy_tail(hg, orc, n, d, beta, T, deg, seed):
+    """Heavy tails whose E_R reaches far below the heaviest layers: the device
+    c solve must grow its tail and still agree with the oracle."""
+    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
+    w, x = orc.points_girg(n, d, beta, seed)
+    c = orc.solve_c(w, d, T, deg)
+    assert res.info["c"] == pytest.approx(c, rel=1e-12)
+    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True)
+    compare(res.edges.cpu().numpy().view(np.uint32), run)
