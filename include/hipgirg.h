@@ -139,7 +139,11 @@ girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, do
 /* girg_generate_batch: `count` independent GIRGs p[0..count-1]; graph b's
  * edges occupy edges[2*offsets[b] .. 2*offsets[b+1]) and carry its own vertex
  * ids.  offsets: host pointer to count+1 entries; infos: host array of count
- * or NULL.  GIRG_EOVERFLOW leaves offsets[count] = edges needed. */
+ * or NULL.  GIRG_EOVERFLOW leaves offsets[count] = edges needed.  Instances
+ * run concurrently, each on a worker with its own device scratch and
+ * non-blocking stream (16 workers; the environment variable
+ * GIRG_BATCH_WORKERS = 1..64 overrides); `stream` orders only the final
+ * placement of the edges. */
 girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
                                 uint64_t* offsets, girg_info* infos, void* stream);
 

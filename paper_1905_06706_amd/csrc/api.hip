@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -134,7 +135,7 @@ struct Ctx {
 
 // contexts per (device, slot): slot 0 serves the single-graph calls, slots
 // 1.. the workers of girg_generate_batch (each with its own stream)
-constexpr int kBatchWorkers = 8;  // concurrent instances of a batch
+constexpr int kBatchWorkers = 16;  // concurrent instances of a batch
 static std::mutex g_ctx_mu;
 static std::map<std::pair<int, int>, std::unique_ptr<Ctx>> g_ctx;
 
@@ -1041,7 +1042,12 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   // stream; an instance's edges go to the caller's buffer at a position
   // reserved once its count is known (completion order), and are put into
   // instance order at the end
-  const int nw = std::min<int>(count, kBatchWorkers);
+  int workers = kBatchWorkers;
+  if (const char* ev = std::getenv("GIRG_BATCH_WORKERS")) {
+    const int v = std::atoi(ev);
+    if (v >= 1 && v <= 64) workers = v;
+  }
+  const int nw = std::min<int>(count, workers);
   std::atomic<int32_t> next{0};
   std::atomic<bool> stop{false};
   std::mutex cur_mu;
