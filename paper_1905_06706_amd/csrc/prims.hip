@@ -339,9 +339,51 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
 
 // Sorts (keys, vals) by the low `bits` bits of the key, stably.  Results end
 // in (keys, vals); tmp buffers come from the arena.
+// one workgroup, bitonic network in LDS over (key, value) pairs ordered
+// lexicographically (padding sorts last).  With distinct values (indices in
+// ascending order, as every caller passes) this is the stable sort by key.
+constexpr int kSmallSort = 4096;
+__global__ __launch_bounds__(1024) void k_small_sort(uint64_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals, uint32_t n,
+                                                     uint32_t np) {
+  __shared__ uint64_t sk[kSmallSort];
+  __shared__ uint32_t sv[kSmallSort];
+  for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) {
+    sk[i] = i < n ? keys[i] : ~0ull;
+    sv[i] = i < n ? vals[i] : ~0u;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= np; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < np / 2; t += blockDim.x) {
+        const uint32_t i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint64_t ki = sk[i], kj = sk[j];
+        const uint32_t vi = sv[i], vj = sv[j];
+        const bool gt = ki > kj || (ki == kj && vi > vj);
+        if (gt == up) {
+          sk[i] = kj; sk[j] = ki;
+          sv[i] = vj; sv[j] = vi;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    keys[i] = sk[i];
+    vals[i] = sv[i];
+  }
+}
+
 hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
                       hipStream_t st) {
   if (n <= 1 || bits <= 0) return hipSuccess;
+  if (n <= (uint64_t)kSmallSort) {
+    uint32_t np = 2;
+    while (np < n) np <<= 1;
+    hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, st, keys, vals, (uint32_t)n, np);
+    return hipGetLastError();
+  }
   Arena::Mark m = ar.mark();
   const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
   uint64_t* k2 = ar.get<uint64_t>(n);
