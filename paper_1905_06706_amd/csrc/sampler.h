@@ -8,7 +8,7 @@
 namespace hg {
 
 constexpr int kPersistBlocks = 1024;  // persistent grids: 4096 waves
-constexpr uint32_t kBigTests = 256;   // type-I items with more tests are split
+constexpr uint32_t kBigTests = 64;    // type-I items with more tests are split
 constexpr uint32_t kTestChunk = 64;   // tests per unit of a split type-I item
 
 // one run of a layer's cell: sorted position s of its first vertex, its cell
