@@ -202,7 +202,7 @@ SWEEP_GROUPS = {
     "points": ("points",),
     "constant": ("c_solve",),
     "pre": ("layer_key", "sort", "gather", "tables", "cells", "sources_count", "sources_fill"),
-    "edges": ("type1", "type2", "split_prep", "split1", "segment_prep", "segments2", "order"),
+    "edges": ("type1", "type2", "deferred_prep", "split1", "segments2", "order"),
 }
 
 

@@ -734,37 +734,48 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   Verts v{rec, ids, smort, slayer};
   const bool binomial = p.T > 0.0;
 
-  // staging of the edges: capacity = the caller's; flush records
-  unsigned int* tickets = ar.get<unsigned int>(8);
-  unsigned int* dcount = ar.get<unsigned int>(2);
-  unsigned int* nrec_d = ar.get<unsigned int>(1);
-  unsigned long long* cursor = ar.get<unsigned long long>(1);
+  // staging of the edges: capacity = the caller's; flush records.  The
+  // counters sit in one block, cleared by one memset per attempt, 256 bytes
+  // apart (atomics of all waves on one cache line slow every pass down):
+  // tickets[0..7], deferred counts[64..65], flush records[128], cursor (u64) at 192
+  unsigned int* ctr = ar.get<unsigned int>(256);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (counters)");
+  unsigned int* tickets = ctr;
+  unsigned int* dcount = ctr + 64;
+  unsigned int* nrec_d = ctr + 128;
+  unsigned long long* cursor = reinterpret_cast<unsigned long long*>(ctr + 192);
   auto make_sched = [&](uint64_t nunits, int pass) {
     uint64_t ch = (nunits + 16383) / 16384;
     ch = ((ch + 63) / 64) * 64;
     ch = std::max<uint64_t>(64, std::min<uint64_t>(4096, ch));
-    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass,
+             nullptr, nullptr};
     return sc;
   };
-  // type-II chunks are runs of whole sources
+  // type-I and type-II chunks are runs of whole sources
   auto make_sched_src = [&](uint64_t nunits, int pass) {
     uint64_t ch = (nunits + 32767) / 32768;
     ch = std::max<uint64_t>(1, std::min<uint64_t>(64, ch));
-    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass};
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass,
+             nullptr, nullptr};
     return sc;
   };
   Sched sch[4] = {make_sched_src(nsrc, 0), make_sched(0, 1),
                   make_sched_src(binomial ? nsrc : 0, 2), make_sched(0, 3)};
+  for (int q = 0; q <= 2; q += 2) {
+    sch[q].ctot = ar.get<uint64_t>(sch[q].nchunks);
+    sch[q].dtot = ar.get<uint64_t>(sch[q].nchunks);
+  }
   uint2* stage = cap ? ar.get<uint2>(cap) : nullptr;
   // every flush but the last of a chunk holds more than 128 edges
   const uint64_t rcap64 = cap / 128 + 2ull * (sch[0].nchunks + sch[2].nchunks) + (1u << 16);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(rcap64, 0xFFFFFFF0ull);
-  uint64_t* rkey = ar.get<uint64_t>(rcap);
+  uint64_t* rtag = ar.get<uint64_t>(rcap);
+  uint64_t* roff = ar.get<uint64_t>(rcap);
   uint64_t* rpos = ar.get<uint64_t>(rcap);
   uint32_t* rcnt = ar.get<uint32_t>(rcap);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge staging)");
-  Stage sg{stage, cap, cursor, rkey, rpos, rcnt, nrec_d, rcap, cx.stats};
+  Stage sg{stage, cap, cursor, rtag, roff, rpos, rcnt, nrec_d, rcap, cx.stats};
 
   // type-I and type-II passes (deferred lists grown once if too small)
   uint32_t dcap[2] = {(uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024),
@@ -779,10 +790,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
       dkey[q] = ar.get<uint64_t>(dcap[q]);
     }
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
-    HIPCHK(hipMemsetAsync(dcount, 0, 2 * sizeof(unsigned int), st));
-    HIPCHK(hipMemsetAsync(tickets, 0, 8 * sizeof(unsigned int), st));
-    HIPCHK(hipMemsetAsync(nrec_d, 0, sizeof(unsigned int), st));
-    HIPCHK(hipMemsetAsync(cursor, 0, sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(ctr, 0, 256 * sizeof(unsigned int), st));
     HIPCHK(hipMemsetAsync(cx.stats, 0, 16 * sizeof(unsigned long long), st));
     DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
     DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
@@ -792,6 +800,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (sch[2].nchunks)
       HIPCHK(launch_type2(g, cx.gd, v, cl, crec, src, sch[2], pbt, nlev, cx.dtab[d], sg, df1, st));
     cx.mark("type2", st);
+    // where each chunk's deferred items start
+    HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
+                                {sch[0].nchunks, sch[2].nchunks, 0, 0}, 3u},
+                        st));
     HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (dn[0] <= dcap[0] && dn[1] <= dcap[1]) break;
@@ -801,38 +813,37 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     dcap[1] = std::max(dcap[1], dn[1]);
   }
 
-  // deferred items in a deterministic order, then their passes
+  // deferred items in (chunk, sequence) order, their work units, then their passes
+  ItemRec* dsorted[2] = {nullptr, nullptr};
+  uint64_t* uoff[2] = {nullptr, nullptr};
+  uint64_t nunits[2] = {0, 0};
+  cx.mark("-", st);
   for (int q = 0; q < 2; ++q) {
     const uint32_t nd = dn[q];
     if (!nd) continue;
-    uint32_t* perm = ar.get<uint32_t>(nd);
-    uint64_t* kt = ar.get<uint64_t>(nd);
-    ItemRec* dsorted = ar.get<ItemRec>(nd);
-    uint64_t* uoff = ar.get<uint64_t>(nd + 1);
-    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred sort)");
-    cx.mark("-", st);
-    HIPCHK(launch_iota(perm, nd, st));
-    HIPCHK(hipMemcpyAsync(kt, dkey[q], nd * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    // keys chunk << 24 | sequence, chunk < nchunks of the pass that deferred them
-    HIPCHK(radix_sort(ar, kt, perm, nd, 24 + bitlen(sch[q == 0 ? 0 : 2].nchunks), st));
-    HIPCHK(launch_rec_gather(drec[q], perm, nd, dsorted, st));
-    HIPCHK(launch_rec_units(dsorted, nd, q == 0 ? 1 : 2, uoff, st));
-    HIPCHK(scan_u64(ar, uoff, uoff, nd, uoff + nd, st));
-    uint64_t nunits = 0;
-    HIPCHK(hipMemcpyAsync(&nunits, uoff + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    cx.mark(q == 0 ? "split_prep" : "segment_prep", st);
-    if (q == 0) {
-      sch[1] = make_sched(nunits, 1);
-      if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted, uoff, nd, sch[1], sg, st));
-      cx.mark("split1", st);
-    } else {
-      sch[3] = make_sched(nunits, 3);
-      if (sch[3].nchunks)
-        HIPCHK(launch_heavy2(g, cx.gd, v, dsorted, uoff, nd, sch[3], pbt, nlev, sg, st));
-      cx.mark("segments2", st);
-    }
+    dsorted[q] = ar.get<ItemRec>(nd);
+    uoff[q] = ar.get<uint64_t>(nd + 1);
+    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
+    HIPCHK(launch_defer_place(drec[q], dkey[q], nd, sch[q == 0 ? 0 : 2].dtot, dsorted[q], st));
+    HIPCHK(launch_rec_units(dsorted[q], nd, q == 0 ? 1 : 2, uoff[q], st));
+    HIPCHK(scan_u64(ar, uoff[q], uoff[q], nd, uoff[q] + nd, st));
+    HIPCHK(hipMemcpyAsync(nunits + q, uoff[q] + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   }
+  if (dn[0] || dn[1]) HIPCHK(hipStreamSynchronize(st));
+  cx.mark("deferred_prep", st);
+  sch[1] = make_sched(nunits[0], 1);
+  sch[3] = make_sched(nunits[1], 3);
+  for (int q = 1; q <= 3; q += 2) sch[q].ctot = ar.get<uint64_t>(sch[q].nchunks);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred passes)");
+  if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, st));
+  cx.mark("split1", st);
+  if (sch[3].nchunks)
+    HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], dn[1], sch[3], pbt, nlev, sg, st));
+  cx.mark("segments2", st);
+  // where each chunk's edges start, in pass order
+  HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot},
+                              {sch[0].nchunks, sch[1].nchunks, sch[2].nchunks, sch[3].nchunks}, 1u},
+                      st));
 
   // total, capacity, records
   unsigned long long mtot = 0;
@@ -849,22 +860,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
   if (place) edges = (*place)(mtot);
 
-  // staged blocks in (pass, chunk, flush) order
+  // staged blocks to their places: chunk start + edges of the chunk before
   if (nrec && edges) {
-    uint32_t* perm = ar.get<uint32_t>(nrec);
-    uint64_t* kt = ar.get<uint64_t>(nrec);
-    uint64_t* off = ar.get<uint64_t>(nrec + 1);
-    if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge order)");
-    cx.mark("-", st);
-    HIPCHK(launch_iota(perm, nrec, st));
-    uint32_t maxch = 1;
-    for (int q = 0; q < 4; ++q) maxch = std::max(maxch, sch[q].nchunks);
-    const int cb = bitlen(maxch);
-    HIPCHK(launch_rec_repack(rkey, kt, nrec, cb, st));
-    HIPCHK(radix_sort(ar, kt, perm, nrec, 28 + cb, st));
-    HIPCHK(launch_stage_counts(rcnt, perm, nrec, off, st));
-    HIPCHK(scan_u64(ar, off, off, nrec, off + nrec, st));
-    HIPCHK(launch_stage_copy(stage, rpos, rcnt, perm, off, nrec, reinterpret_cast<uint2*>(edges), st));
+    const ChunkBases cbs{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot}};
+    HIPCHK(launch_stage_copy(stage, rtag, roff, rpos, rcnt, nrec, cbs, mtot,
+                             reinterpret_cast<uint2*>(edges), st));
     cx.mark("order", st);
   }
 

@@ -59,6 +59,15 @@ hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, ui
 // out6 (device): sums of terms mode0..mode0+nterms-1, then min, max of w
 hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
                         double invT, double* out6, hipStream_t st);
+// in-place exclusive scans of up to four u64 arrays by one workgroup; the
+// running sum carries from array k - 1 into array k unless bit k of `reset`
+// is set (array 0 always starts at zero).  Arrays with n = 0 may be null.
+struct SegScan {
+  uint64_t* p[4];
+  uint64_t n[4];
+  uint32_t reset;
+};
+hipError_t seg_scan_u64(Arena& ar, const SegScan& s, hipStream_t st);
 hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t st);
 // out[i] = x_i^e, x_i positive doubles given as bit patterns (u64)
 hipError_t launch_pow_bits(const uint64_t* xb, double* out, uint64_t n, double e, hipStream_t st);

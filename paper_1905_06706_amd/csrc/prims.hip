@@ -115,6 +115,123 @@ hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, ui
   return e;
 }
 
+// one workgroup, 1024 threads x 8 items per tile, the carry in a register:
+// for the short per-chunk count arrays, where one launch beats several
+constexpr int kSegThreads = 1024;
+constexpr int kSegItems = 8;
+
+__global__ __launch_bounds__(kSegThreads) void k_seg_scan(SegScan s) {
+  __shared__ uint64_t wsum[kSegThreads / 64];
+  const int w = threadIdx.x / 64, lane = lane_id();
+  uint64_t carry = 0;
+  for (int k = 0; k < 4; ++k) {
+    if ((s.reset >> k) & 1u) carry = 0;
+    uint64_t* p = s.p[k];
+    const uint64_t n = s.n[k];
+    for (uint64_t t0 = 0; t0 < n; t0 += (uint64_t)kSegThreads * kSegItems) {
+      const uint64_t b = t0 + (uint64_t)threadIdx.x * kSegItems;
+      uint64_t v[kSegItems];
+      uint64_t acc = 0;
+#pragma unroll
+      for (int j = 0; j < kSegItems; ++j) {
+        v[j] = b + j < n ? p[b + j] : 0ull;
+        acc += v[j];
+      }
+      const uint64_t inc = wave_incl_scan(acc);
+      if (lane == 63) wsum[w] = inc;
+      __syncthreads();
+      uint64_t base = carry, tot = 0;
+#pragma unroll
+      for (int q = 0; q < kSegThreads / 64; ++q) {
+        if (q < w) base += wsum[q];
+        tot += wsum[q];
+      }
+      __syncthreads();
+      uint64_t run = base + inc - acc;
+#pragma unroll
+      for (int j = 0; j < kSegItems; ++j) {
+        if (b + j < n) p[b + j] = run;
+        run += v[j];
+      }
+      carry += tot;
+    }
+  }
+}
+
+// long arrays: tiles of kScanTile scanned locally (tiles never straddle two
+// arrays), the tile sums scanned by k_seg_scan with the same resets, then
+// added back
+__global__ __launch_bounds__(kScanThreads) void k_seg_tiles(SegScan s, uint4 tstart,
+                                                            uint64_t* __restrict__ sums) {
+  const uint32_t b = blockIdx.x;
+  const uint32_t ts[4] = {tstart.x, tstart.y, tstart.z, tstart.w};
+  int k = 0;
+  while (k < 3 && b >= ts[k + 1]) ++k;
+  uint64_t* p = s.p[k];
+  const uint64_t n = s.n[k];
+  const uint64_t base = (uint64_t)(b - ts[k]) * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < n ? p[base + j] : 0ull;
+    acc += v[j];
+  }
+  uint64_t total;
+  uint64_t run = block_excl_scan(acc, &total);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) p[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) sums[b] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_add(SegScan s, uint4 tstart,
+                                                          const uint64_t* __restrict__ sums) {
+  const uint32_t b = blockIdx.x;
+  const uint32_t ts[4] = {tstart.x, tstart.y, tstart.z, tstart.w};
+  int k = 0;
+  while (k < 3 && b >= ts[k + 1]) ++k;
+  uint64_t* p = s.p[k];
+  const uint64_t n = s.n[k];
+  const uint64_t base = (uint64_t)(b - ts[k]) * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  const uint64_t o = sums[b];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j < n) p[base + j] += o;
+}
+
+hipError_t seg_scan_u64(Arena& ar, const SegScan& s, hipStream_t st) {
+  const uint64_t tot = s.n[0] + s.n[1] + s.n[2] + s.n[3];
+  if (tot == 0) return hipSuccess;
+  if (tot <= (uint64_t)kSegThreads * kSegItems * 8) {
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(kSegThreads), 0, st, s);
+    return hipGetLastError();
+  }
+  uint64_t tiles[4], start[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k) {
+    tiles[k] = (s.n[k] + kScanTile - 1) / kScanTile;
+    start[k + 1] = start[k] + tiles[k];
+  }
+  if (start[4] >= (1ull << 31)) return hipErrorInvalidValue;
+  Arena::Mark m = ar.mark();
+  uint64_t* sums = ar.get<uint64_t>(start[4]);
+  if (!sums) {
+    ar.reset(m);
+    return hipErrorOutOfMemory;
+  }
+  const uint4 ts = make_uint4((uint32_t)start[0], (uint32_t)start[1], (uint32_t)start[2], (uint32_t)start[3]);
+  hipLaunchKernelGGL(k_seg_tiles, dim3((uint32_t)start[4]), dim3(kScanThreads), 0, st, s, ts, sums);
+  SegScan ss{{sums + start[0], sums + start[1], sums + start[2], sums + start[3]},
+             {tiles[0], tiles[1], tiles[2], tiles[3]}, s.reset};
+  hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(kSegThreads), 0, st, ss);
+  hipLaunchKernelGGL(k_seg_add, dim3((uint32_t)start[4]), dim3(kScanThreads), 0, st, s, ts, sums);
+  const hipError_t e = hipGetLastError();
+  ar.reset(m);
+  return e;
+}
+
 // ---------------------------------------------------------------------------
 // reductions: fixed grid, fixed order => bitwise reproducible
 // ---------------------------------------------------------------------------

@@ -21,10 +21,11 @@
 // Pair decisions read one packed record (w, x) per vertex.
 // Accepted edges are appended (wave ballots) to an LDS buffer that is flushed
 // in blocks of at least 128 edges to a staging array at an atomically reserved
-// position, with a record (pass, chunk, flush number) -> position.  Sorting
-// the records and copying the blocks in that order gives an edge array that
-// is a pure function of the inputs and the seed, whatever wave ran which
-// chunk, in one sampling pass.
+// position, with a record of its chunk and of the chunk's edges flushed
+// before it.  A chunk's wave also stores the chunk's edge total; a scan of the
+// totals in (pass, chunk) order places every block, so the edge array is a
+// pure function of the inputs and the seed, whatever wave ran which chunk, in
+// one sampling pass.
 #include "sampler.h"
 
 namespace hg {
@@ -272,8 +273,8 @@ constexpr uint32_t kEdgeBuf2 = 192;  // the same for waves that emit at most one
 struct Out {
   uint2* lb;           // LDS buffer of this wave: sorted positions of the edges
   uint32_t bn;         // edges in it
-  uint32_t seq;        // flushes of the current chunk
-  uint64_t key;        // pass << 58 | chunk << 26
+  uint64_t off;        // edges of the current chunk flushed so far
+  uint64_t tag;        // pass << 32 | chunk
   const uint32_t* id;  // original ids of the sorted positions (applied at the flush)
 };
 
@@ -289,16 +290,26 @@ __device__ __forceinline__ void flush(const Stage& sg, Out& o) {
       sg.buf[pos + i] = make_uint2(o.id[e.x], o.id[e.y]);
     }
   if (lane == 0) {
-    atomicAdd(&sg.stats[8 + (o.key >> 58)], (unsigned long long)o.bn);  // edges per pass
     const unsigned int slot = atomicAdd(sg.nrec, 1u);
     if (slot < sg.rcap) {
-      sg.rkey[slot] = o.key | o.seq;
+      sg.rtag[slot] = o.tag;
+      sg.roff[slot] = o.off;
       sg.rpos[slot] = pos;
       sg.rcnt[slot] = o.bn;
     }
   }
-  ++o.seq;
+  o.off += o.bn;
   o.bn = 0;
+}
+
+// the last flush of chunk c, then its totals: edges, and items deferred
+__device__ __forceinline__ void end_chunk(const Stage& sg, Out& o, const Sched& sc, uint32_t c,
+                                          uint32_t ndef) {
+  flush(sg, o);
+  if (lane_id() == 0) {
+    sc.ctot[c] = o.off;
+    if (sc.dtot) sc.dtot[c] = ndef;
+  }
 }
 
 // append up to two edges per lane (order: all first edges, then all second)
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   QItem1* q = qs[wv];
   SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0, nre = 0;
+  uint64_t ntests = 0, nre = 0, nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -592,7 +603,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint64_t se = sb + sc.chunk < sc.nunits ? sb + sc.chunk : sc.nunits;
     uint32_t in = 0, dseq = 0;
     Ring1 r{0, 0, 0, 0};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t base = sb; base < se; base += kWave) {
       // one source per lane: its neighbour cells
       const uint64_t si = base + lane;
@@ -674,11 +685,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     while (in)
       take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests, nre);
     while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
-    flush(sg, out);
+    end_chunk(sg, out, sc, c, dseq);
+    nedge += out.off;
   }
   ntests = wave_sum(ntests);
   nre = wave_sum(nre);
   if (lane == 0) {
+    if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
     if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
   }
@@ -695,14 +708,14 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
   const uint32_t wv = threadIdx.x / kWave;
   QItem1* q = qs[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0, nre = 0;
+  uint64_t ntests = 0, nre = 0, nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
     const uint64_t ub = (uint64_t)c * sc.chunk;
     const uint64_t ue = ub + sc.chunk < sc.nunits ? ub + sc.chunk : sc.nunits;
     Ring1 r{0, 0, 0, 0};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
         step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
@@ -729,11 +742,13 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
       enqueue1(enq, it, q, r);
     }
     while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
-    flush(sg, out);
+    end_chunk(sg, out, sc, c, 0);
+    nedge += out.off;
   }
   ntests = wave_sum(ntests);
   nre = wave_sum(nre);
   if (lane == 0) {
+    if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
     if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
   }
@@ -1034,7 +1049,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
   const uint32_t dstride = dtab[0];
-  uint64_t ndraws = 0, ncand = 0, nre = 0;
+  uint64_t ndraws = 0, ncand = 0, nre = 0, nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -1045,7 +1060,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     bool act = false;
     QItem2 cur{};
     PB cpe{0.0, 0.0, 0.0f};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t base = sb; base < se; base += kWave) {
       // one source per lane: its candidate cells
       const uint64_t si = base + lane;
@@ -1125,12 +1140,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                 dfo, sg, out, ndraws, ncand, nre);
     draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
     while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
-    flush(sg, out);
+    end_chunk(sg, out, sc, c, dseq);
+    nedge += out.off;
   }
   ndraws = wave_sum(ndraws);
   ncand = wave_sum(ncand);
   nre = wave_sum(nre);
   if (lane == 0) {
+    if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
     atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
     atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
@@ -1153,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
   Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
   const int L = g->L;
-  uint64_t ndraws = 0, ncand = 0, nre = 0;
+  uint64_t ndraws = 0, ncand = 0, nre = 0, nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -1163,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     bool act = false;
     QItem2 cur{};
     PB cpe{0.0, 0.0, 0.0f};
-    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 58) | ((uint64_t)c << 26), v.id};
+    Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       if (r.qt - r.qh > (uint32_t)(kQCap - 64))
         draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
@@ -1193,12 +1210,14 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     }
     draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
     while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
-    flush(sg, out);
+    end_chunk(sg, out, sc, c, 0);
+    nedge += out.off;
   }
   ndraws = wave_sum(ndraws);
   ncand = wave_sum(ncand);
   nre = wave_sum(nre);
   if (lane == 0) {
+    if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
     atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
     atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
@@ -1222,45 +1241,37 @@ __global__ __launch_bounds__(256) void k_rec_units(const ItemRec* __restrict__ r
   }
 }
 
-__global__ __launch_bounds__(256) void k_rec_gather(const ItemRec* __restrict__ in,
-                                                    const uint32_t* __restrict__ perm, uint32_t nrec,
-                                                    ItemRec* __restrict__ out) {
+// deferred items to their (chunk, sequence) order; dbase = exclusive scan of
+// the per-chunk deferred counts
+__global__ __launch_bounds__(256) void k_defer_place(const ItemRec* __restrict__ rec,
+                                                     const uint64_t* __restrict__ key, uint32_t n,
+                                                     const uint64_t* __restrict__ dbase,
+                                                     ItemRec* __restrict__ out) {
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < nrec) out[h] = in[perm[h]];
+  if (h >= n) return;
+  const uint64_t k = key[h];
+  const uint64_t dst = dbase[k >> 24] + (k & 0xFFFFFFull);
+  if (dst < n) out[dst] = rec[h];
 }
 
-// staged blocks -> final order: count of sorted record w, then copy (one wave
-// per record)
-// flush keys pass << 58 | chunk << 26 | flush repacked to pass << (cb + 26) |
-// chunk << 26 | flush (chunk < 2^cb), same order, fewer bits to sort
-__global__ __launch_bounds__(256) void k_rec_repack(const uint64_t* __restrict__ in,
-                                                    uint64_t* __restrict__ out, uint32_t n, int cb) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t k = in[i];
-  out[i] = ((k >> 58) << (cb + 26)) | (((k >> 26) & 0xFFFFFFFFull) << 26) | (k & ((1ull << 26) - 1));
-}
-
-__global__ __launch_bounds__(256) void k_stage_counts(const uint32_t* __restrict__ rcnt,
-                                                      const uint32_t* __restrict__ perm,
-                                                      uint32_t nrec, uint64_t* __restrict__ cnt) {
-  const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < nrec) cnt[h] = rcnt[perm[h]];
-}
-
+// staged blocks -> final order (one wave per record): chunk start + the
+// edges of the chunk flushed before the block
 __global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ stage,
+                                                    const uint64_t* __restrict__ rtag,
+                                                    const uint64_t* __restrict__ roff,
                                                     const uint64_t* __restrict__ rpos,
-                                                    const uint32_t* __restrict__ rcnt,
-                                                    const uint32_t* __restrict__ perm,
-                                                    const uint64_t* __restrict__ off, uint32_t nrec,
+                                                    const uint32_t* __restrict__ rcnt, uint32_t nrec,
+                                                    ChunkBases cb, uint64_t m,
                                                     uint2* __restrict__ out) {
   const uint32_t lane = lane_id();
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / kWave);
   for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < nrec; w += nw) {
-    const uint32_t r = perm[w];
-    const uint64_t src = rpos[r], dst = off[w];
-    const uint32_t cnt = rcnt[r];
-    for (uint32_t i = lane; i < cnt; i += kWave) out[dst + i] = stage[src + i];
+    const uint64_t t = rtag[w];
+    const uint64_t dst = cb.base[t >> 32][(uint32_t)t] + roff[w];
+    const uint64_t src = rpos[w];
+    const uint32_t cnt = rcnt[w];
+    for (uint32_t i = lane; i < cnt; i += kWave)
+      if (dst + i < m) out[dst + i] = stage[src + i];
   }
 }
 
@@ -1379,30 +1390,18 @@ hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_
   return hipGetLastError();
 }
 
-hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_rec_gather, dim3((nrec + 255) / 256), dim3(256), 0, st, in, perm, nrec, out);
+hipError_t launch_defer_place(const ItemRec* rec, const uint64_t* key, uint32_t n,
+                              const uint64_t* dbase, ItemRec* out, hipStream_t st) {
+  if (n) hipLaunchKernelGGL(k_defer_place, dim3((n + 255) / 256), dim3(256), 0, st, rec, key, n, dbase, out);
   return hipGetLastError();
 }
 
-hipError_t launch_rec_repack(const uint64_t* in, uint64_t* out, uint32_t n, int cb, hipStream_t st) {
-  if (n)
-    hipLaunchKernelGGL(k_rec_repack, dim3((n + 255) / 256), dim3(256), 0, st, in, out, n, cb);
-  return hipGetLastError();
-}
-
-hipError_t launch_stage_counts(const uint32_t* rcnt, const uint32_t* perm, uint32_t nrec,
-                               uint64_t* cnt, hipStream_t st) {
-  hipLaunchKernelGGL(k_stage_counts, dim3((nrec + 255) / 256), dim3(256), 0, st, rcnt, perm, nrec, cnt);
-  return hipGetLastError();
-}
-
-hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rpos, const uint32_t* rcnt,
-                             const uint32_t* perm, const uint64_t* off, uint32_t nrec, uint2* out,
-                             hipStream_t st) {
+hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rtag, const uint64_t* roff,
+                             const uint64_t* rpos, const uint32_t* rcnt, uint32_t nrec,
+                             const ChunkBases& cb, uint64_t m, uint2* out, hipStream_t st) {
   const uint32_t blocks = std::min<uint32_t>((nrec + 3) / 4, 8192u);
-  hipLaunchKernelGGL(k_stage_copy, dim3(blocks ? blocks : 1), dim3(256), 0, st, stage, rpos, rcnt,
-                     perm, off, nrec, out);
+  hipLaunchKernelGGL(k_stage_copy, dim3(blocks ? blocks : 1), dim3(256), 0, st, stage, rtag, roff, rpos,
+                     rcnt, nrec, cb, m, out);
   return hipGetLastError();
 }
 

@@ -24,22 +24,29 @@ struct ItemRec {
   uint32_t a0, na, b0, nb, A, B, meta, e;
 };
 
-// dynamic chunk scheduling: waves take chunks of `chunk` units by ticket
+// dynamic chunk scheduling: waves take chunks of `chunk` units by ticket.
+// The wave that finishes chunk c stores the edges it produced in ctot[c] and
+// the items it deferred in dtot[c] (null for passes that defer nothing);
+// exclusive scans of these give every chunk its output range.
 struct Sched {
   unsigned int* next;  // ticket counter (zeroed before each launch)
   uint64_t nunits;
   uint32_t chunk;
   uint32_t nchunks;
   uint32_t pass;       // 0 type-I, 1 split type-I, 2 type-II, 3 segmented type-II
+  uint64_t* ctot;
+  uint64_t* dtot;
 };
 
 // staged output: waves flush blocks of edges to buf at atomically reserved
-// positions and record (pass, chunk, flush) -> (position, count)
+// positions and record, per flush, (pass, chunk), the edges of the chunk
+// flushed before it, its position in buf and its size
 struct Stage {
   uint2* buf;
   uint64_t cap;                  // edges that fit in buf
   unsigned long long* cursor;    // edges produced so far
-  uint64_t* rkey;                // pass << 58 | chunk << 26 | flush
+  uint64_t* rtag;                // pass << 32 | chunk
+  uint64_t* roff;                // edges of the chunk before this flush
   uint64_t* rpos;
   uint32_t* rcnt;
   unsigned int* nrec;
@@ -55,6 +62,12 @@ struct DeferOut {
   uint64_t* key;
   unsigned int* count;
   uint32_t cap;
+};
+
+// chunk edge totals of the four passes, scanned in pass order: the start of
+// every chunk's edges in the output
+struct ChunkBases {
+  const uint64_t* base[4];
 };
 
 hipError_t launch_points(const Graph& g, double beta, double* w, double* x, hipStream_t st);
@@ -94,21 +107,18 @@ hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const C
 // deferred items: units per record (kind 1: test pieces, kind 2: segments)
 hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
                             hipStream_t st);
-hipError_t launch_rec_gather(const ItemRec* in, const uint32_t* perm, uint32_t nrec, ItemRec* out,
-                             hipStream_t st);
 hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                        const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Stage& sg,
                        hipStream_t st);
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
                          int nlev, const Stage& sg, hipStream_t st);
-// flush keys repacked to 28 + cb bits (chunk indices < 2^cb)
-hipError_t launch_rec_repack(const uint64_t* in, uint64_t* out, uint32_t n, int cb, hipStream_t st);
-// staged blocks in record order
-hipError_t launch_stage_counts(const uint32_t* rcnt, const uint32_t* perm, uint32_t nrec,
-                               uint64_t* cnt, hipStream_t st);
-hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rpos, const uint32_t* rcnt,
-                             const uint32_t* perm, const uint64_t* off, uint32_t nrec, uint2* out,
-                             hipStream_t st);
+// deferred items in (chunk, sequence) order: out[dbase[chunk] + seq] = rec
+hipError_t launch_defer_place(const ItemRec* rec, const uint64_t* key, uint32_t n,
+                              const uint64_t* dbase, ItemRec* out, hipStream_t st);
+// staged blocks to their final positions (one wave per record)
+hipError_t launch_stage_copy(const uint2* stage, const uint64_t* rtag, const uint64_t* roff,
+                             const uint64_t* rpos, const uint32_t* rcnt, uint32_t nrec,
+                             const ChunkBases& cb, uint64_t cap, uint2* out, hipStream_t st);
 
 }  // namespace hg
