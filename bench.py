@@ -136,12 +136,16 @@ def make_call(hg, wl: dict):
         def call(buf, cap, m, info, stream):
             return L.girg_hrg(wl["n"], wl["alpha"], wl["T"], 0.0, wl["avg_deg"], wl["seed"], buf, cap,
                               m, info, stream)
+        # the same graph as girg_generate parameters (R solved from the degree)
+        call.params = hg.make_params(wl["n"], 1, 0.0, wl["T"], wl["avg_deg"], 0.0, wl["seed"], model=1,
+                                     alpha=wl["alpha"])
         return call
     p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"],
                        wl["precision"])
 
     def call(buf, cap, m, info, stream):
         return L.girg_generate(ctypes.byref(p), buf, cap, m, info, stream)
+    call.params = p
     return call
 
 
@@ -195,6 +199,33 @@ def cpu_baseline_batch(params: list, budget_s: float = 15.0) -> dict:
     dt = time.perf_counter() - t0
     return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"the first {k} of {len(params)} instances, whole graphs; {m} edges in {dt:.2f} s"}
+
+
+def single_calls(hg, params: list, sp) -> dict:
+    """The batch's instances through girg_generate one after another (the
+    plain single-graph path, one call per instance, edges written): edges/s
+    and ms, after one untimed pass, to set against the batched call."""
+    import torch
+    L = hg.load()
+    m = ctypes.c_uint64(0)
+    info = hg.Info()
+    caps = []
+    for p in params:
+        st = L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), ctypes.byref(info), sp)
+        if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
+            hg._check(st)
+        caps.append(int(m.value))
+    buf = torch.empty((max(max(caps), 1), 2), dtype=torch.int32, device="cuda")
+    bp = ctypes.c_void_p(buf.data_ptr())
+    total = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, c in zip(params, caps):
+        hg._check(L.girg_generate(ctypes.byref(p), bp, c, ctypes.byref(m), ctypes.byref(info), sp))
+        total += m.value
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "edges/s", "ms": dt * 1e3, "calls": len(params)}
 
 
 # stage groups of the sweep, after the paper's breakdown of a run (Sec. 5.1)
@@ -364,6 +395,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shapes (no autotuning before the warm-up)")
     ap.add_argument("--hbm-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (HBM calibration)")
     ap.add_argument("--sweep", action="store_true",
@@ -400,6 +433,16 @@ def main() -> int:
     cap = int(m.value)
     buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
     bp = ctypes.c_void_p(buf.data_ptr())
+    # launch shapes (persistent grid size, batch workers) tuned on this
+    # workload before the warm-up; they change no edge, only the speed
+    if args.no_autotune:
+        tuning = {"autotuned": False}
+    elif "batch" in wl:
+        b, w = hg.autotune_batch(call.params, reps=1)
+        tuning = {"autotuned": True, "blocks": b, "workers": w}
+    else:
+        tuning = {"autotuned": True, "blocks": hg.autotune(call.params, reps=2)}
+    print(f"[bench] tuning {tuning}", file=sys.stderr)
     for _ in range(args.warmup):
         hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
     hg.set_profiling(True)
@@ -434,22 +477,32 @@ def main() -> int:
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                 "launch_ms": dt / args.steps * 1e3, "ops_per_launch": ops}
     else:
-        # dominant sampling kernel and its roofline (VALU-bound: lane-operations)
-        kernel_pass = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
-        kstages = {k: v for k, v in stages.items() if k in kernel_pass}
-        dom = max(kstages, key=kstages.get)
-        dom_ms = stages[dom]
-        q = kernel_pass[dom]
-        if q < 2:
-            units = {"tests": info_d["pass_work"][q]}
-            ops = units["tests"] * (OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM)
-        else:
-            units = {"draws": info_d["pass_work"][q], "candidates": info_d["pass_cands"][q]}
-            ops = units["draws"] * OPS_DRAW + units["candidates"] * OPS_CAND
-        achieved = ops / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": STAGE_KERNEL[dom] + "...>", "achieved": achieved,
-                "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": profiled_traffic(args.workload, dom), "launch_ms": dom_ms,
+        # The sampling kernels run in two phases, each with two kernels on two
+        # streams at once: type I beside type II, then the split type-I pass
+        # beside the segmented type-II pass.  The dominant phase is the unit:
+        # its lane-operations over its wall time (both kernels start at the
+        # fork, so the wall time is the longer of the two kernel times, each
+        # timed by HIP events on its own stream).
+        tb = OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM
+        pw, pc = info_d["pass_work"], info_d["pass_cands"]
+        phases = {
+            "sampling": (("type1", "type2"), pw[0] * tb + pw[2] * OPS_DRAW + pc[2] * OPS_CAND,
+                         {"tests": pw[0], "draws": pw[2], "candidates": pc[2]}),
+            "deferred": (("split1", "segments2"), pw[1] * tb + pw[3] * OPS_DRAW + pc[3] * OPS_CAND,
+                         {"tests": pw[1], "draws": pw[3], "candidates": pc[3]}),
+        }
+        wall = {ph: max(stages.get(k, 0.0) for k in ks) for ph, (ks, _, _) in phases.items()}
+        dom = max(wall, key=wall.get)
+        kstages, ops, units = phases[dom]
+        achieved = ops / (wall[dom] * 1e-3) / 1e12
+        kinds = [k for k in kstages if stages.get(k, 0.0) > 0.0]
+        traffic = [profiled_traffic(args.workload, k) for k in kinds]
+        roof = {"bound": "alu", "kernel": " + ".join(STAGE_KERNEL[k] + "...>" for k in kinds)
+                + (" (concurrent streams)" if len(kinds) > 1 else ""),
+                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": sum(traffic) if traffic and None not in traffic else None,
+                "launch_ms": wall[dom], "kernels_ms": {STAGE_KERNEL[k][:-1]: stages[k] for k in kinds},
                 "units_per_launch": units, "ops_per_launch": ops}
     value = edges / dt
     out = {
@@ -471,6 +524,10 @@ def main() -> int:
         "roofline": roof,
         "stages_ms": stages,
     }
+    out["tuning"] = tuning
+    if "batch" in wl:
+        out["single_calls"] = single_calls(hg, call.params, sp)
+        print(f"[bench] single calls {out['single_calls']}", file=sys.stderr)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(call.params) if "batch" in wl else cpu_baseline(wl)
     print(json.dumps(out), flush=True)

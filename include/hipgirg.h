@@ -141,14 +141,51 @@ girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, do
  * ids.  offsets: host pointer to count+1 entries; infos: host array of count
  * or NULL.  GIRG_EOVERFLOW leaves offsets[count] = edges needed.  Instances
  * run concurrently, each on a worker with its own device scratch and
- * non-blocking stream (16 workers; the environment variable
- * GIRG_BATCH_WORKERS = 1..64 overrides); `stream` orders only the final
- * placement of the edges. */
+ * non-blocking stream (the tuned worker count, 16 by default; the
+ * environment variable GIRG_BATCH_WORKERS = 1..64 overrides the table);
+ * `stream` orders only the final placement of the edges. */
 girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
                                 uint64_t* offsets, girg_info* infos, void* stream);
 
+/* Launch-shape tuning.  The sampling passes run as persistent grids whose
+ * waves take chunks of work by ticket; every chunk's edges are placed by the
+ * chunk's index, so the number of workgroups changes the speed but never an
+ * edge or its position.  The library keeps a table: workgroups per workload
+ * class (model, d, T > 0, floor(log2 n)) for single graphs, and one
+ * (workgroups, workers) pair for batches.  Defaults: 512 workgroups below
+ * n = 2^22, else 1024; batches 256 and 16 workers.  At the first call the
+ * JSON file named by GIRG_TUNING_FILE, if set, is loaded.
+ *
+ * girg_autotune: times count-only runs of *p (every sampling pass, no edge
+ * array) with 256, 512, 768, 1024, 1536 and 2048 workgroups, `reps` runs
+ * each (1..100) after one warm-up, and stores the fastest for p's class;
+ * *blocks_out (may be NULL) receives it.  Uses the device and `stream` of a
+ * girg_generate call.
+ * girg_autotune_batch: the same for a batch (p[0..count-1]): 128, 256, 512,
+ * 768 and 1024 workgroups per instance with 8 and 16 workers.
+ * girg_tuning_get: the values the next call with *p would use (batch != 0:
+ * as a batch instance); girg_tuning_set stores them (batch: workers 0 keeps
+ * the current count; blocks in 1..8192, workers in 0..64).
+ * girg_tuning_save / girg_tuning_load: the table as JSON, {"version": 1,
+ * "single": [{"model", "d", "binomial", "log2n", "blocks"}, ...], "batch":
+ * {"blocks", "workers"}}; a load that fails leaves the table unchanged
+ * (GIRG_EINVAL with the reason).  girg_tuning_reset restores the defaults.
+ * Tuning calls on one process share the table; autotuning while other calls
+ * run changes their speed, not their results. */
+girg_status girg_autotune(const girg_params* p, int32_t reps, void* stream, int32_t* blocks_out);
+girg_status girg_autotune_batch(const girg_params* p, int32_t count, int32_t reps, int32_t* blocks_out,
+                                int32_t* workers_out);
+girg_status girg_tuning_get(const girg_params* p, int32_t batch, int32_t* blocks_out, int32_t* workers_out);
+girg_status girg_tuning_set(const girg_params* p, int32_t batch, int32_t blocks, int32_t workers);
+girg_status girg_tuning_save(const char* path);
+girg_status girg_tuning_load(const char* path);
+girg_status girg_tuning_reset(void);
+
 /* Profiling: with girg_set_profiling(1), every later call on this device
- * records HIP events around its stages on the call's own stream.
+ * records HIP events around its stages on the call's own stream; type I and
+ * its split pass, which run concurrently with type II and its segmented pass
+ * on a second stream of the library's, are timed on that stream, so their
+ * times overlap.
  * girg_stage_times copies the durations (milliseconds) and names of the last
  * call's stages (at most `max`; either array may be NULL) and returns how many
  * there were, or -1 on error.  Names stay valid until the next call. */

@@ -26,6 +26,8 @@ EXPORTS = (
     "girg_generate", "girg_hrg", "girg_from_points", "girg_points", "girg_solve_c",
     "girg_expected_degree", "hrg_solve_R", "hrg_expected_degree", "girg_generate_batch",
     "girg_release", "girg_last_error", "girg_version", "girg_set_profiling", "girg_stage_times",
+    "girg_autotune", "girg_autotune_batch", "girg_tuning_get", "girg_tuning_set", "girg_tuning_save",
+    "girg_tuning_load", "girg_tuning_reset",
 )
 
 
@@ -93,6 +95,14 @@ def load() -> ctypes.CDLL:
     L.girg_release.argtypes = []
     L.girg_set_profiling.argtypes = [ctypes.c_int32]
     L.girg_stage_times.argtypes = [P(dbl), P(ctypes.c_char_p), ctypes.c_int32]
+    i32 = ctypes.c_int32
+    L.girg_autotune.argtypes = [P(Params), i32, vp, P(i32)]
+    L.girg_autotune_batch.argtypes = [P(Params), i32, i32, P(i32), P(i32)]
+    L.girg_tuning_get.argtypes = [P(Params), i32, P(i32), P(i32)]
+    L.girg_tuning_set.argtypes = [P(Params), i32, i32, i32]
+    L.girg_tuning_save.argtypes = [ctypes.c_char_p]
+    L.girg_tuning_load.argtypes = [ctypes.c_char_p]
+    L.girg_tuning_reset.argtypes = []
     for name in EXPORTS:
         if name == "girg_stage_times":
             L.girg_stage_times.restype = ctypes.c_int32
@@ -261,6 +271,48 @@ def generate_batch(params: list, cap: int | None = None, stream=None, device="cu
         _check(st)
         return buf[: offs[cnt]], list(offs), [i.as_dict() for i in infos]
     _check(GIRG_EOVERFLOW)
+
+
+def autotune(params: Params, reps: int = 3, stream=None) -> int:
+    """girg_autotune: the fastest persistent grid (workgroups) for params'
+    workload class, now stored in the library's tuning table."""
+    b = ctypes.c_int32(0)
+    _check(load().girg_autotune(ctypes.byref(params), reps, _stream(stream), ctypes.byref(b)))
+    return b.value
+
+
+def autotune_batch(params: list, reps: int = 2) -> tuple:
+    """girg_autotune_batch: (workgroups per instance, workers) of the fastest
+    batch configuration, now stored in the tuning table."""
+    cnt = len(params)
+    arr = (Params * cnt)(*params)
+    b, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().girg_autotune_batch(arr, cnt, reps, ctypes.byref(b), ctypes.byref(w)))
+    return b.value, w.value
+
+
+def tuning_get(params: Params, batch: bool = False) -> tuple:
+    """(workgroups, batch workers) that the next call with params would use."""
+    b, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().girg_tuning_get(ctypes.byref(params), 1 if batch else 0, ctypes.byref(b), ctypes.byref(w)))
+    return b.value, w.value
+
+
+def tuning_set(params: Params | None, blocks: int, batch: bool = False, workers: int = 0):
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().girg_tuning_set(p, 1 if batch else 0, blocks, workers))
+
+
+def tuning_save(path: str):
+    _check(load().girg_tuning_save(os.fsencode(path)))
+
+
+def tuning_load(path: str):
+    _check(load().girg_tuning_load(os.fsencode(path)))
+
+
+def tuning_reset():
+    _check(load().girg_tuning_reset())
 
 
 def set_profiling(on: bool):

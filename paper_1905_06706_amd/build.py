@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libhipgirg.so")
-SOURCES = ["api.hip", "prep.hip", "sample.hip", "prims.hip"]
+SOURCES = ["api.hip", "prep.hip", "sample.hip", "prims.hip", "tune.hip"]
 HEADERS = ["device_common.h", "internal.h", "sampler.h"]
 
 FLAGS = [

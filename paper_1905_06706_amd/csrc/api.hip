@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -26,6 +27,7 @@
 
 #include "../../include/hipgirg.h"
 #include "sampler.h"
+#include "tune.h"
 
 namespace hg {
 
@@ -90,8 +92,15 @@ struct Ctx {
   unsigned int* hcount = nullptr;
   uint32_t* dtab[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // distant offsets per d
   hipStream_t own = nullptr;  // batch workers: the slot's own stream
+  bool batch = false;         // a batch worker's context
+  // a second stream on which type I and the split type-I pass run beside
+  // type II and the segmented type-II pass (fork/join by events)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   std::mutex mu;
-  // stage timing (HIP events on the call's stream), enabled by girg_set_profiling
+  // stage timing (HIP events), enabled by girg_set_profiling: a stage's time
+  // runs from the event before it to its own, both on the stream it ran on;
+  // the passes that overlap are timed on their own streams
   bool profiling = false;
   std::vector<hipEvent_t> ev;
   std::vector<std::string> ev_name;
@@ -129,13 +138,15 @@ struct Ctx {
     for (auto t : dtab)
       if (t) (void)hipFree(t);
     if (own) (void)hipStreamDestroy(own);
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
 // contexts per (device, slot): slot 0 serves the single-graph calls, slots
 // 1.. the workers of girg_generate_batch (each with its own stream)
-constexpr int kBatchWorkers = 16;  // concurrent instances of a batch
 static std::mutex g_ctx_mu;
 static std::map<std::pair<int, int>, std::unique_ptr<Ctx>> g_ctx;
 
@@ -156,9 +167,44 @@ static girg_status get_ctx(Ctx** out, int slot = 0) {
   HIPCHK(hipMalloc(&c->stats, 16 * sizeof(unsigned long long)));
   HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
   if (slot > 0) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+  c->batch = slot > 0;
+  // single-graph calls only: the batch's workers already fill the GPU, and
+  // twice as many streams on the few hardware queues slowed the batch down
+  if (slot == 0) {
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+  }
   *out = c.get();
   g_ctx[{dev, slot}] = std::move(c);
   return GIRG_OK;
+}
+
+// side stream: starts after the work queued on st so far; st continues only
+// after the work queued on the side stream
+// If a call returns between a fork and its join (an error), the guard waits
+// for the side stream, so that no kernel still reads scratch memory that the
+// next call reuses.
+struct SideGuard {
+  Ctx& cx;
+  bool armed = false;
+  ~SideGuard() {
+    if (armed) (void)hipStreamSynchronize(cx.side);
+  }
+};
+static hipError_t fork_side(Ctx& cx, hipStream_t st, bool on, SideGuard& gd) {
+  if (!on) return hipSuccess;
+  gd.armed = true;
+  hipError_t e = hipEventRecord(cx.fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(cx.side, cx.fork, 0);
+  return e;
+}
+static hipError_t join_side(Ctx& cx, hipStream_t st, bool on, SideGuard& gd) {
+  if (!on) return hipSuccess;
+  hipError_t e = hipEventRecord(cx.join, cx.side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, cx.join, 0);
+  if (e == hipSuccess) gd.armed = false;
+  return e;
 }
 
 static int bitlen(uint64_t v) {
@@ -744,20 +790,31 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   unsigned int* dcount = ctr + 64;
   unsigned int* nrec_d = ctr + 128;
   unsigned long long* cursor = reinterpret_cast<unsigned long long*>(ctr + 192);
+  // type I (and its split pass) on the side stream, concurrently with type II
+  // (and its segments); profiled calls time each pass on its own stream
+  const bool overlap = cx.side != nullptr;
+  hipStream_t s1 = overlap ? cx.side : st;
+  SideGuard sguard{cx};
+  // persistent grids: the tuned number of workgroups, at most one wave per chunk
+  const uint32_t gblocks = tuned_blocks(tune_key(p.model, g.d, p.T, p.n), cx.batch);
+  auto grid_for = [&](uint32_t nchunks) {
+    const uint32_t need = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    return std::max<uint32_t>(1u, std::min<uint32_t>(gblocks, need));
+  };
   auto make_sched = [&](uint64_t nunits, int pass) {
     uint64_t ch = (nunits + 16383) / 16384;
     ch = ((ch + 63) / 64) * 64;
     ch = std::max<uint64_t>(64, std::min<uint64_t>(4096, ch));
-    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass,
-             nullptr, nullptr};
+    const uint32_t nch = (uint32_t)((nunits + ch - 1) / ch);
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, nch, (uint32_t)pass, nullptr, nullptr, grid_for(nch)};
     return sc;
   };
   // type-I and type-II chunks are runs of whole sources
   auto make_sched_src = [&](uint64_t nunits, int pass) {
     uint64_t ch = (nunits + 32767) / 32768;
     ch = std::max<uint64_t>(1, std::min<uint64_t>(64, ch));
-    Sched sc{tickets + pass, nunits, (uint32_t)ch, (uint32_t)((nunits + ch - 1) / ch), (uint32_t)pass,
-             nullptr, nullptr};
+    const uint32_t nch = (uint32_t)((nunits + ch - 1) / ch);
+    Sched sc{tickets + pass, nunits, (uint32_t)ch, nch, (uint32_t)pass, nullptr, nullptr, grid_for(nch)};
     return sc;
   };
   Sched sch[4] = {make_sched_src(nsrc, 0), make_sched(0, 1),
@@ -795,11 +852,15 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
     DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
     cx.mark("-", st);
-    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, cl, crec, src, sch[0], sg, df0, st));
-    cx.mark("type1", st);
+    HIPCHK(fork_side(cx, st, overlap, sguard));
+    cx.mark("-", s1);
+    if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, cl, crec, src, sch[0], sg, df0, s1));
+    cx.mark("type1", s1);
+    cx.mark("-", st);
     if (sch[2].nchunks)
       HIPCHK(launch_type2(g, cx.gd, v, cl, crec, src, sch[2], pbt, nlev, cx.dtab[d], sg, df1, st));
     cx.mark("type2", st);
+    HIPCHK(join_side(cx, st, overlap, sguard));
     // where each chunk's deferred items start
     HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
                                 {sch[0].nchunks, sch[2].nchunks, 0, 0}, 3u},
@@ -835,11 +896,16 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   sch[3] = make_sched(nunits[1], 3);
   for (int q = 1; q <= 3; q += 2) sch[q].ctot = ar.get<uint64_t>(sch[q].nchunks);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred passes)");
-  if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, st));
-  cx.mark("split1", st);
+  HIPCHK(fork_side(cx, st, overlap, sguard));
+  cx.mark("-", s1);
+  if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, s1));
+  cx.mark("split1", s1);
+  cx.mark("-", st);
   if (sch[3].nchunks)
     HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], dn[1], sch[3], pbt, nlev, sg, st));
   cx.mark("segments2", st);
+  HIPCHK(join_side(cx, st, overlap, sguard));
+  cx.mark("-", st);
   // where each chunk's edges start, in pass order
   HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot},
                               {sch[0].nchunks, sch[1].nchunks, sch[2].nchunks, sch[3].nchunks}, 1u},
@@ -1042,12 +1108,7 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   // stream; an instance's edges go to the caller's buffer at a position
   // reserved once its count is known (completion order), and are put into
   // instance order at the end
-  int workers = kBatchWorkers;
-  if (const char* ev = std::getenv("GIRG_BATCH_WORKERS")) {
-    const int v = std::atoi(ev);
-    if (v >= 1 && v <= 64) workers = v;
-  }
-  const int nw = std::min<int>(count, workers);
+  const int nw = std::min<int>(count, tuned_batch_workers());
   std::atomic<int32_t> next{0};
   std::atomic<bool> stop{false};
   std::mutex cur_mu;
@@ -1115,6 +1176,127 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
     (void)hipFree(tmp);
     return s;
   }
+  return GIRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times the candidate grids (and, for batches, worker counts) on
+// count-only calls, which run every sampling pass in full but write no edge
+// array, and keeps the fastest in the tuning table
+// ---------------------------------------------------------------------------
+static const uint32_t kSingleCands[] = {256, 512, 768, 1024, 1536, 2048};
+static const uint32_t kBatchBlockCands[] = {128, 256, 512, 768, 1024};
+static const int kBatchWorkerCands[] = {8, 16};
+
+// RAII: candidate values forced while timing, cleared on every exit
+struct ForceGuard {
+  ForceGuard(uint32_t sb, uint32_t bb, int bw) { tune_force(sb, bb, bw); }
+  ~ForceGuard() { tune_force(0, 0, 0); }
+};
+
+static girg_status time_min(const std::function<girg_status()>& call, int reps, double* best_ms) {
+  girg_status s = call();  // warm-up
+  if (s != GIRG_OK && s != GIRG_EOVERFLOW) return s;
+  double best = 1e300;
+  for (int r = 0; r < reps; ++r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    s = call();
+    const auto t1 = std::chrono::steady_clock::now();
+    if (s != GIRG_OK && s != GIRG_EOVERFLOW) return s;
+    best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+  }
+  *best_ms = best;
+  return GIRG_OK;
+}
+
+girg_status girg_autotune(const girg_params* p, int32_t reps, void* stream, int32_t* blocks_out) {
+  if (!p || reps < 1 || reps > 100) return fail(GIRG_EINVAL, "null argument or reps outside 1..100");
+  girg_status s = validate(*p, p->model == 0);
+  if (s != GIRG_OK) return s;
+  uint32_t best = 0;
+  double best_ms = 1e300;
+  for (uint32_t cand : kSingleCands) {
+    ForceGuard fg(cand, 0, 0);
+    double ms = 0.0;
+    s = time_min([&] {
+          uint64_t m = 0;
+          return generate_impl(p, nullptr, 0, &m, nullptr, stream);
+        }, reps, &ms);
+    if (s != GIRG_OK) return s;
+    if (ms < best_ms) { best_ms = ms; best = cand; }
+  }
+  const int d = p->model == 1 ? 1 : p->d;
+  tune_set_single(tune_key(p->model, d, p->T, p->n), best);
+  if (blocks_out) *blocks_out = (int32_t)best;
+  return GIRG_OK;
+}
+
+girg_status girg_autotune_batch(const girg_params* p, int32_t count, int32_t reps, int32_t* blocks_out,
+                                int32_t* workers_out) {
+  if (!p || count < 1 || reps < 1 || reps > 100)
+    return fail(GIRG_EINVAL, "null argument, count < 1 or reps outside 1..100");
+  std::vector<uint64_t> offs((size_t)count + 1);
+  uint32_t best_b = 0;
+  int best_w = 0;
+  double best_ms = 1e300;
+  for (int w : kBatchWorkerCands)
+    for (uint32_t b : kBatchBlockCands) {
+      ForceGuard fg(0, b, w);
+      double ms = 0.0;
+      girg_status s = time_min([&] {
+            return girg_generate_batch(p, count, nullptr, 0, offs.data(), nullptr, nullptr);
+          }, reps, &ms);
+      if (s != GIRG_OK) return s;
+      if (ms < best_ms) { best_ms = ms; best_b = b; best_w = w; }
+    }
+  tune_set_batch(best_b, best_w);
+  if (blocks_out) *blocks_out = (int32_t)best_b;
+  if (workers_out) *workers_out = best_w;
+  return GIRG_OK;
+}
+
+girg_status girg_tuning_get(const girg_params* p, int32_t batch, int32_t* blocks_out,
+                            int32_t* workers_out) {
+  if (!p) return fail(GIRG_EINVAL, "null argument");
+  const int d = p->model == 1 ? 1 : p->d;
+  if (blocks_out) *blocks_out = (int32_t)tuned_blocks(tune_key(p->model, d, p->T, p->n), batch != 0);
+  if (workers_out) *workers_out = tuned_batch_workers();
+  return GIRG_OK;
+}
+
+girg_status girg_tuning_set(const girg_params* p, int32_t batch, int32_t blocks, int32_t workers) {
+  if (blocks < 1 || blocks > (int32_t)kMaxBlocks) return fail(GIRG_EINVAL, "blocks outside 1..8192");
+  if (batch) {
+    if (workers < 0 || workers > kMaxWorkers) return fail(GIRG_EINVAL, "workers outside 0..64");
+    tune_set_batch((uint32_t)blocks, workers);
+    return GIRG_OK;
+  }
+  if (!p) return fail(GIRG_EINVAL, "null argument");
+  if (p->model != 0 && p->model != 1) return fail(GIRG_EINVAL, "model must be 0 or 1");
+  if (p->model == 0 && (p->d < 1 || p->d > 4)) return fail(GIRG_EINVAL, "d must be in 1..4");
+  const int d = p->model == 1 ? 1 : p->d;
+  tune_set_single(tune_key(p->model, d, p->T, p->n), (uint32_t)blocks);
+  return GIRG_OK;
+}
+
+girg_status girg_tuning_reset(void) {
+  tune_reset();
+  return GIRG_OK;
+}
+
+girg_status girg_tuning_save(const char* path) {
+  if (!path) return fail(GIRG_EINVAL, "null path");
+  tune_init();
+  std::string err;
+  if (!tune_save(path, &err)) return fail(GIRG_EINVAL, err);
+  return GIRG_OK;
+}
+
+girg_status girg_tuning_load(const char* path) {
+  if (!path) return fail(GIRG_EINVAL, "null path");
+  tune_init();
+  std::string err;
+  if (!tune_load(path, &err)) return fail(GIRG_EINVAL, "tuning file " + std::string(path) + ": " + err);
   return GIRG_OK;
 }
 

@@ -1295,7 +1295,7 @@ static bool use_mixed(const Graph& g) { return g.precision == 1 && g.model == 0 
 hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
                         const uint2* crec, const Src* src, const Sched& sc, const Stage& sg,
                         const DeferOut& dfo, hipStream_t st) {
-  const dim3 grid(kPersistBlocks), block(256);
+  const dim3 grid(sc.blocks), block(kWavesPerBlock * kWave);
   const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
     if (t0) hipLaunchKernelGGL((k_type1<DD, MM, true, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, sg, dfo);
@@ -1310,7 +1310,7 @@ hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const C
 hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                        const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Stage& sg,
                        hipStream_t st) {
-  const dim3 grid(kPersistBlocks), block(256);
+  const dim3 grid(sc.blocks), block(kWavesPerBlock * kWave);
   const bool t0 = !(g.T > 0.0), mx = use_mixed(g);
   HG_DISPATCH_D({
     if (t0) hipLaunchKernelGGL((k_big1<DD, MM, true, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, sg);
@@ -1326,7 +1326,7 @@ hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const C
                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
                         int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
                         hipStream_t st) {
-  const dim3 grid(kPersistBlocks), block(256);
+  const dim3 grid(sc.blocks), block(kWavesPerBlock * kWave);
   const bool mx = use_mixed(g);
   HG_DISPATCH_D({
     if constexpr (MM == 0) {
@@ -1373,7 +1373,7 @@ std::vector<uint32_t> distant_table(int d) {
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,
                          const uint64_t* uoff, uint32_t nrec, const Sched& sc, const Pbar* pbt,
                          int nlev, const Stage& sg, hipStream_t st) {
-  const dim3 grid(kPersistBlocks), block(256);
+  const dim3 grid(sc.blocks), block(kWavesPerBlock * kWave);
   const bool mx = use_mixed(g);
   HG_DISPATCH_D({
     if constexpr (MM == 0) {

@@ -7,7 +7,9 @@
 
 namespace hg {
 
-constexpr int kPersistBlocks = 1024;  // persistent grids: 4096 waves
+// persistent grids: workgroups of 4 waves; the number of workgroups comes
+// from the tuning table (tune.hip), capped at one wave per chunk
+constexpr int kWavesPerBlock = 4;
 constexpr uint32_t kBigTests = 64;    // type-I items with more tests are split
 constexpr uint32_t kTestChunk = 64;   // tests per unit of a split type-I item
 
@@ -36,6 +38,7 @@ struct Sched {
   uint32_t pass;       // 0 type-I, 1 split type-I, 2 type-II, 3 segmented type-II
   uint64_t* ctot;
   uint64_t* dtot;
+  uint32_t blocks;     // workgroups of the launch
 };
 
 // staged output: waves flush blocks of edges to buf at atomically reserved
