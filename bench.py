@@ -395,8 +395,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's default launch shapes (no autotuning before the warm-up)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the launch shapes on this workload before the warm-up "
+                         "(default: the library's tuning table)")
     ap.add_argument("--hbm-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (HBM calibration)")
     ap.add_argument("--sweep", action="store_true",
@@ -433,10 +434,12 @@ def main() -> int:
     cap = int(m.value)
     buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
     bp = ctypes.c_void_p(buf.data_ptr())
-    # launch shapes (persistent grid size, batch workers) tuned on this
-    # workload before the warm-up; they change no edge, only the speed
-    if args.no_autotune:
-        tuning = {"autotuned": False}
+    # launch shapes (persistent grid size, batch workers): the library's table,
+    # or tuned on this workload before the warm-up; they change no edge, only
+    # the speed
+    if not args.autotune:
+        b, w = hg.tuning_get(call.params[0] if "batch" in wl else call.params, batch="batch" in wl)
+        tuning = {"autotuned": False, "blocks": b, **({"workers": w} if "batch" in wl else {})}
     elif "batch" in wl:
         b, w = hg.autotune_batch(call.params, reps=1)
         tuning = {"autotuned": True, "blocks": b, "workers": w}

@@ -97,6 +97,11 @@ struct Ctx {
   // type II and the segmented type-II pass (fork/join by events)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // pinned host memory for readbacks: a copy into pageable memory blocks the
+  // host once per copy (about 12 us each), into pinned memory the copies of a
+  // group complete with one stream synchronisation
+  void* pin = nullptr;
+  size_t pin_size = 0;
   std::mutex mu;
   // stage timing (HIP events), enabled by girg_set_profiling: a stage's time
   // runs from the event before it to its own, both on the stream it ran on;
@@ -141,9 +146,57 @@ struct Ctx {
     if (side) (void)hipStreamDestroy(side);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (pin) (void)hipHostFree(pin);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
+
+// A group of device-to-host copies staged in the context's pinned buffer:
+// begin(bytes) makes room (no copy of an earlier group may be in flight, so
+// every group ends with wait()), add() queues one copy, wait() synchronises
+// the stream once and moves the data to its destinations.
+class Readback {
+ public:
+  Readback(Ctx& cx, hipStream_t st) : cx_(cx), st_(st) {}
+  hipError_t begin(size_t bytes) {
+    items_.clear();
+    used_ = 0;
+    bytes = (bytes + 4095) & ~(size_t)4095;
+    if (bytes <= cx_.pin_size) return hipSuccess;
+    if (cx_.pin) (void)hipHostFree(cx_.pin);
+    cx_.pin = nullptr;
+    cx_.pin_size = 0;
+    hipError_t e = hipHostMalloc(&cx_.pin, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) cx_.pin_size = bytes;
+    return e;
+  }
+  hipError_t add(void* dst, const void* src, size_t bytes) {
+    const size_t off = (used_ + 15) & ~(size_t)15;
+    if (off + bytes > cx_.pin_size) return hipErrorInvalidValue;  // begin() reserved too little
+    items_.push_back(Item{dst, off, bytes});
+    used_ = off + bytes;
+    return hipMemcpyAsync(static_cast<char*>(cx_.pin) + off, src, bytes, hipMemcpyDeviceToHost, st_);
+  }
+  hipError_t wait() {
+    hipError_t e = hipStreamSynchronize(st_);
+    if (e != hipSuccess) return e;
+    for (const Item& it : items_) std::memcpy(it.dst, static_cast<char*>(cx_.pin) + it.off, it.bytes);
+    items_.clear();
+    used_ = 0;
+    return hipSuccess;
+  }
+
+ private:
+  struct Item {
+    void* dst;
+    size_t off, bytes;
+  };
+  Ctx& cx_;
+  hipStream_t st_;
+  std::vector<Item> items_;
+  size_t used_ = 0;
+};
+constexpr size_t kSmallReadback = 1 << 16;
 
 // contexts per (device, slot): slot 0 serves the single-graph calls, slots
 // 1.. the workers of girg_generate_batch (each with its own stream)
@@ -349,23 +402,23 @@ struct CSolve {
 
 // sums over the first `cnt` layer-sorted weights (those outside the tail), on
 // the device: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
+// queues the sums over the weights outside the tail (the first cnt of the
+// layer-sorted weights) and their readback into r[0..5]
 static girg_status csolve_out_sums(Ctx& cx, const double* sw, uint64_t cnt, double T, double W,
-                                   CSolve* cs, hipStream_t st) {
-  cs->out_w = cs->out_q1 = cs->out_p = cs->out_q2 = 0.0;
+                                   double* r, Readback& rb, hipStream_t st) {
+  for (int k = 0; k < 6; ++k) r[k] = 0.0;
   if (cnt == 0) return GIRG_OK;
   const double invT = T > 0.0 ? 1.0 / T : 0.0;
   const int nterms = T > 0.0 ? 4 : 2;
   HIPCHK(reduce_terms(cx.ar, sw, cnt, nterms, 0, W, invT, cx.red, st));
-  double r[6];
-  HIPCHK(hipMemcpyAsync(r, cx.red, sizeof(r), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(rb.add(r, cx.red, 6 * sizeof(double)));
+  return GIRG_OK;
+}
+static void csolve_take_sums(const double* r, double T, CSolve* cs) {
   cs->out_w = r[0];
   cs->out_q1 = r[1];
-  if (T > 0.0) {
-    cs->out_p = r[2];
-    cs->out_q2 = r[3];
-  }
-  return GIRG_OK;
+  cs->out_p = T > 0.0 ? r[2] : 0.0;
+  cs->out_q2 = T > 0.0 ? r[3] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -593,8 +646,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   // exact sum W and min / max of w (GIRG) or r (HRG)
   HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
   double red[6];
-  HIPCHK(hipMemcpyAsync(red, cx.red, sizeof(red), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  Readback rb(cx, st);
+  HIPCHK(rb.begin(kSmallReadback));
+  HIPCHK(rb.add(red, cx.red, sizeof(red)));
+  HIPCHK(rb.wait());
   if (p.model == 0) {
     if (!(red[4] > 0.0) || !std::isfinite(red[5]))
       return fail(GIRG_EINVAL, "weights must be finite and > 0");
@@ -619,10 +674,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
   cx.mark("layer_key", st);
   uint32_t flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, cx.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(g.count, cx.gd->count, sizeof(g.count), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(g.ext, cx.gd->ext, sizeof(g.ext), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(rb.begin(kSmallReadback));
+  HIPCHK(rb.add(&flag, cx.flag, sizeof(uint32_t)));
+  HIPCHK(rb.add(g.count, cx.gd->count, sizeof(g.count)));
+  HIPCHK(rb.add(g.ext, cx.gd->ext, sizeof(g.ext)));
+  HIPCHK(rb.wait());
   if (flag & 1u) return fail(GIRG_EINVAL, p.model == 0 ? "weights must be finite and > 0" : "radii must lie in [0, R]");
   if (flag & 2u) return fail(GIRG_EINVAL, "more than 64 weight layers");
   if (flag & 4u) return fail(GIRG_EINVAL, "positions must lie in [0,1)");
@@ -672,16 +728,20 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         double* tp = p.T > 0.0 ? ar.get<double>(K) : nullptr;
         if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
         if (tp) HIPCHK(launch_pow_bits(tk, tp, K, 1.0 / p.T, st));
+        // the tail, its powers and the sums over the rest: one readback
         std::vector<double> asc(K), ascp(tp ? K : 0);
-        HIPCHK(hipMemcpyAsync(asc.data(), tk, K * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (tp) HIPCHK(hipMemcpyAsync(ascp.data(), tp, K * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        double rs[6];
+        HIPCHK(rb.begin(2 * K * sizeof(double) + 4096));
+        HIPCHK(rb.add(asc.data(), tk, K * sizeof(double)));
+        if (tp) HIPCHK(rb.add(ascp.data(), tp, K * sizeof(double)));
+        girg_status s = csolve_out_sums(cx, sw, g.lstart[i0], p.T, g.W, rs, rb, st);
+        if (s != GIRG_OK) return s;
+        HIPCHK(rb.wait());
         ar.reset(mk);
+        csolve_take_sums(rs, p.T, &cs);
         cs.h.assign(asc.rbegin(), asc.rend());
         cs.hp.assign(ascp.rbegin(), ascp.rend());
         if (!tp) cs.hp.assign(K, 0.0);
-        girg_status s = csolve_out_sums(cx, sw, g.lstart[i0], p.T, g.W, &cs, st);
-        if (s != GIRG_OK) return s;
         cs.wcut = 0.0;
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
@@ -716,8 +776,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   cx.mark("-", st);
   HIPCHK(launch_tables(cx.gd, Dcap, pbt, st));
   cx.mark("tables", st);
-  HIPCHK(hipMemcpyAsync(&g, cx.gd, sizeof(Graph), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(rb.begin(kSmallReadback));
+  HIPCHK(rb.add(&g, cx.gd, sizeof(Graph)));
+  HIPCHK(rb.wait());
 
   // prefix sums per layer at its insertion level
   uint64_t cells = 0;
@@ -751,8 +812,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(scan_u32(ar, scnt, scnt, n, scnt + n, st));
   cx.mark("sources_count", st);
   uint32_t nsrc = 0;
-  HIPCHK(hipMemcpyAsync(&nsrc, scnt + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(rb.begin(kSmallReadback));
+  HIPCHK(rb.add(&nsrc, scnt + n, sizeof(uint32_t)));
+  HIPCHK(rb.wait());
   Src* src = ar.get<Src>(std::max<uint64_t>(nsrc, 1));
   const uint64_t ncl = g.moff[kMaxLevels];
   CellL* cl = ar.get<CellL>(ncl);
@@ -865,8 +927,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
                                 {sch[0].nchunks, sch[2].nchunks, 0, 0}, 3u},
                         st));
-    HIPCHK(hipMemcpyAsync(dn, dcount, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(rb.begin(kSmallReadback));
+    HIPCHK(rb.add(dn, dcount, 2 * sizeof(unsigned int)));
+    HIPCHK(rb.wait());
     if (dn[0] <= dcap[0] && dn[1] <= dcap[1]) break;
     if (attempt == 1) return fail(GIRG_ENOMEM, "deferred item lists overflowed");
     ar.reset(mk);
@@ -879,6 +942,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint64_t* uoff[2] = {nullptr, nullptr};
   uint64_t nunits[2] = {0, 0};
   cx.mark("-", st);
+  HIPCHK(rb.begin(kSmallReadback));
   for (int q = 0; q < 2; ++q) {
     const uint32_t nd = dn[q];
     if (!nd) continue;
@@ -888,9 +952,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     HIPCHK(launch_defer_place(drec[q], dkey[q], nd, sch[q == 0 ? 0 : 2].dtot, dsorted[q], st));
     HIPCHK(launch_rec_units(dsorted[q], nd, q == 0 ? 1 : 2, uoff[q], st));
     HIPCHK(scan_u64(ar, uoff[q], uoff[q], nd, uoff[q] + nd, st));
-    HIPCHK(hipMemcpyAsync(nunits + q, uoff[q] + nd, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(rb.add(nunits + q, uoff[q] + nd, sizeof(uint64_t)));
   }
-  if (dn[0] || dn[1]) HIPCHK(hipStreamSynchronize(st));
+  if (dn[0] || dn[1]) HIPCHK(rb.wait());
   cx.mark("deferred_prep", st);
   sch[1] = make_sched(nunits[0], 1);
   sch[3] = make_sched(nunits[1], 3);
@@ -911,12 +975,15 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
                               {sch[0].nchunks, sch[1].nchunks, sch[2].nchunks, sch[3].nchunks}, 1u},
                       st));
 
-  // total, capacity, records
+  // total, capacity, records, and the counters (final once the passes end)
   unsigned long long mtot = 0;
   unsigned int nrec = 0;
-  HIPCHK(hipMemcpyAsync(&mtot, cursor, sizeof(mtot), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&nrec, nrec_d, sizeof(nrec), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  unsigned long long stt[16];
+  HIPCHK(rb.begin(kSmallReadback));
+  HIPCHK(rb.add(&mtot, cursor, sizeof(mtot)));
+  HIPCHK(rb.add(&nrec, nrec_d, sizeof(nrec)));
+  HIPCHK(rb.add(stt, cx.stats, sizeof(stt)));
+  HIPCHK(rb.wait());
   *m_out = mtot;
   if (info) info->m = mtot;
   if (mtot > cap) {
@@ -934,8 +1001,6 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     cx.mark("order", st);
   }
 
-  unsigned long long stt[16];
-  HIPCHK(hipMemcpyAsync(stt, cx.stats, sizeof(stt), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   cx.collect();
   if (info) {

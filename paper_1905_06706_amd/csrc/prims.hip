@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_add(SegScan s, uint4 tstar
 hipError_t seg_scan_u64(Arena& ar, const SegScan& s, hipStream_t st) {
   const uint64_t tot = s.n[0] + s.n[1] + s.n[2] + s.n[3];
   if (tot == 0) return hipSuccess;
-  if (tot <= (uint64_t)kSegThreads * kSegItems * 8) {
+  if (tot <= (uint64_t)kSegThreads * kSegItems) {
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(kSegThreads), 0, st, s);
     return hipGetLastError();
   }
