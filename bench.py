@@ -494,11 +494,14 @@ def main() -> int:
             "deferred": (("split1", "segments2"), pw[1] * tb + pw[3] * OPS_DRAW + pc[3] * OPS_CAND,
                          {"tests": pw[1], "draws": pw[3], "candidates": pc[3]}),
         }
-        wall = {ph: max(stages.get(k, 0.0) for k in ks) for ph, (ks, _, _) in phases.items()}
+        ran = {k for k, q in (("type1", 0), ("split1", 1), ("type2", 2), ("segments2", 3)) if pw[q] > 0}
+        wall = {ph: max([stages.get(k, 0.0) for k in ks if k in ran] or [0.0])
+                for ph, (ks, _, _) in phases.items()}
         dom = max(wall, key=wall.get)
         kstages, ops, units = phases[dom]
         achieved = ops / (wall[dom] * 1e-3) / 1e12
-        kinds = [k for k in kstages if stages.get(k, 0.0) > 0.0]
+        pass_of = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
+        kinds = [k for k in kstages if pw[pass_of[k]] > 0]  # kernels that ran
         traffic = [profiled_traffic(args.workload, k) for k in kinds]
         roof = {"bound": "alu", "kernel": " + ".join(STAGE_KERNEL[k] + "...>" for k in kinds)
                 + (" (concurrent streams)" if len(kinds) > 1 else ""),
