@@ -873,7 +873,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   };
   // type-I and type-II chunks are runs of whole sources
   auto make_sched_src = [&](uint64_t nunits, int pass) {
-    uint64_t ch = (nunits + 32767) / 32768;
+    uint64_t ch = (nunits + 16383) / 16384;
     ch = std::max<uint64_t>(1, std::min<uint64_t>(64, ch));
     const uint32_t nch = (uint32_t)((nunits + ch - 1) / ch);
     Sched sc{tickets + pass, nunits, (uint32_t)ch, nch, (uint32_t)pass, nullptr, nullptr, grid_for(nch)};
