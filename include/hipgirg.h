@@ -153,7 +153,8 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
  * edge or its position.  The library keeps a table: workgroups per workload
  * class (model, d, T > 0, floor(log2 n)) for single graphs, and one
  * (workgroups, workers) pair for batches.  Defaults: 512 workgroups below
- * n = 2^22, else 1024; batches 256 and 16 workers.  At the first call the
+ * n = 2^22 for T > 0 and below n = 2^17 for T = 0, else 1024; batches 256
+ * and 16 workers.  At the first call the
  * JSON file named by GIRG_TUNING_FILE, if set, is loaded.
  *
  * girg_autotune: times count-only runs of *p (every sampling pass, no edge

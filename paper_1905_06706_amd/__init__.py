@@ -80,6 +80,13 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1905_06706_amd.build)")
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes the library bind to that one, so the process holds a single
+    # runtime (loading the library first mixes two and hides the device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, vp, u64, dbl = ctypes.POINTER, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double
     st = ctypes.c_int

@@ -911,8 +911,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
     HIPCHK(hipMemsetAsync(ctr, 0, 256 * sizeof(unsigned int), st));
     HIPCHK(hipMemsetAsync(cx.stats, 0, 16 * sizeof(unsigned long long), st));
-    DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0]};
-    DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1]};
+    DeferOut df0{drec[0], dkey[0], dcount + 0, dcap[0], p.T > 0.0 ? kBigTests : kBigTestsT0};
+    DeferOut df1{drec[1], dkey[1], dcount + 1, dcap[1], 0u};
     cx.mark("-", st);
     HIPCHK(fork_side(cx, st, overlap, sguard));
     cx.mark("-", s1);
@@ -1293,6 +1293,7 @@ girg_status girg_autotune(const girg_params* p, int32_t reps, void* stream, int3
   const int d = p->model == 1 ? 1 : p->d;
   tune_set_single(tune_key(p->model, d, p->T, p->n), best);
   if (blocks_out) *blocks_out = (int32_t)best;
+  g_err.clear();  // the count-only runs leave "edge capacity too small"
   return GIRG_OK;
 }
 
@@ -1317,6 +1318,7 @@ girg_status girg_autotune_batch(const girg_params* p, int32_t count, int32_t rep
   tune_set_batch(best_b, best_w);
   if (blocks_out) *blocks_out = (int32_t)best_b;
   if (workers_out) *workers_out = best_w;
+  g_err.clear();
   return GIRG_OK;
 }
 

@@ -563,7 +563,7 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
     const bool tri = cA == cB && ci == cj;
     const uint64_t tot = tri ? (uint64_t)cna * (cna - 1) / 2 : (uint64_t)cna * cnb;
     if (nb && tot) {
-      if (tot > kBigTests) {
+      if (tot > dfo.big) {
         rec = ItemRec{ca0, cna, cb0, cnb, cA, cB,
                       lvl | (ci << 8) | (cj << 16) | (tri ? 1u << 31 : 0u), 0u};
         big = true;

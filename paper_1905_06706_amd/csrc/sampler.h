@@ -10,7 +10,11 @@ namespace hg {
 // persistent grids: workgroups of 4 waves; the number of workgroups comes
 // from the tuning table (tune.hip), capped at one wave per chunk
 constexpr int kWavesPerBlock = 4;
-constexpr uint32_t kBigTests = 64;    // type-I items with more tests are split
+// type-I items with more tests are split into pieces of kTestChunk tests:
+// binomial tests are costly, so smaller items are split than for threshold
+// tests, where a piece costs more to schedule than to test
+constexpr uint32_t kBigTests = 64;
+constexpr uint32_t kBigTestsT0 = 256;
 constexpr uint32_t kTestChunk = 64;   // tests per unit of a split type-I item
 
 // one run of a layer's cell: sorted position s of its first vertex, its cell
@@ -59,12 +63,14 @@ struct Stage {
   unsigned long long* stats;
 };
 
-// deferred items: key = chunk << 24 | sequence in chunk
+// deferred items: key = chunk << 24 | sequence in chunk; big = the type-I
+// split threshold (tests)
 struct DeferOut {
   ItemRec* rec;
   uint64_t* key;
   unsigned int* count;
   uint32_t cap;
+  uint32_t big;
 };
 
 // chunk edge totals of the four passes, scanned in pass order: the start of

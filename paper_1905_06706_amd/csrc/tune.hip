@@ -1,8 +1,9 @@
 // tune.hip -- the tuning table of the persistent sampling grids (host code).
-// Defaults come from autotuned runs on MI355X: up to n = 2^22 graphs finish
-// sooner with 512 workgroups per pass (two passes share the GPU at a time;
-// fewer workgroups also dispatch and drain faster), larger ones with 1024,
-// and the graphs of a batch with 256, since 16 instances share the GPU.  The
+// Defaults come from autotuned runs on MI355X: binomial graphs up to
+// n = 2^22 finish sooner with 512 workgroups per pass (type I and type II
+// share the GPU), larger ones with 1024; threshold graphs (one pass) with
+// 1024 from n = 2^17 on and 512 below (less dispatch and drain); the graphs
+// of a batch with 256, since 16 instances share the GPU.  The
 // autotuner (api.hip) times candidates and stores the best here; the table
 // can be saved to and loaded from a JSON file (GIRG_TUNING_FILE is loaded at
 // the first lookup).
@@ -34,7 +35,12 @@ std::once_flag g_env_once;
 constexpr uint32_t kDefaultBatchBlocks = 256;
 constexpr int kDefaultBatchWorkers = 16;
 
-uint32_t default_single(const TuneKey& k) { return k.log2n < 22 ? 512u : 1024u; }
+// binomial graphs run two passes at once, so each takes fewer workgroups;
+// threshold graphs have no type-II pass and fill the GPU with one
+uint32_t default_single(const TuneKey& k) {
+  if (k.binomial) return k.log2n < 22 ? 512u : 1024u;
+  return k.log2n < 17 ? 512u : 1024u;
+}
 
 }  // namespace
 

@@ -22,6 +22,9 @@ def lib(monkeypatch):
 
 def test_defaults(lib):
     assert lib.tuning_get(lib.make_params(10**4, 1, 2.5, 0.0, 10.0)) == (512, 16)
+    assert lib.tuning_get(lib.make_params(2**17 - 1, 1, 2.5, 0.0, 10.0))[0] == 512
+    assert lib.tuning_get(lib.make_params(2**17, 1, 2.5, 0.0, 10.0))[0] == 1024
+    assert lib.tuning_get(lib.make_params(2**20, 3, 2.5, 0.0, 10.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(2**22 - 1, 2, 2.7, 0.5, 16.0))[0] == 512
     assert lib.tuning_get(lib.make_params(2**22, 2, 2.7, 0.5, 16.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(10**7, 3, 2.3, 0.8, 20.0))[0] == 1024
@@ -35,7 +38,7 @@ def test_set_get_by_class(lib):
     # same class: floor(log2 n), d, T > 0, model
     assert lib.tuning_get(lib.make_params(2**21 - 1, 2, 2.1, 0.9, 8.0))[0] == 2048
     assert lib.tuning_get(lib.make_params(2**21, 2, 2.7, 0.5, 16.0))[0] == 512
-    assert lib.tuning_get(lib.make_params(2**20, 2, 2.7, 0.0, 16.0))[0] == 512
+    assert lib.tuning_get(lib.make_params(2**20, 2, 2.7, 0.0, 16.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(2**20, 3, 2.7, 0.5, 16.0))[0] == 512
     h = lib.make_params(2**20, 1, 0.0, 0.5, 10.0, model=1, alpha=0.75)
     assert lib.tuning_get(h)[0] == 512
