@@ -774,7 +774,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   }
   HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
   cx.mark("-", st);
-  HIPCHK(launch_tables(cx.gd, Dcap, pbt, st));
+  HIPCHK(launch_tables(cx.gd, g.L, Dcap, pbt, st));
   cx.mark("tables", st);
   HIPCHK(rb.begin(kSmallReadback));
   HIPCHK(rb.add(&g, cx.gd, sizeof(Graph)));

@@ -76,38 +76,63 @@ __global__ __launch_bounds__(256) void k_layer_key(Graph* __restrict__ g,
     sext[threadIdx.x] = model == 0 ? 0ull : ~0ull;
   }
   __syncthreads();
-  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = g->n;
-  uint32_t bad = 0;
-  if (u < n) {
-    const double wu = w[u];
+  const double scale = ldexp(1.0, g->Dmax);
+  // grid-stride over the vertices: few workgroups, so few global atomics on
+  // the same layer counters at the end
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t u_end = ((uint64_t)n + blockDim.x - 1) / blockDim.x * blockDim.x;  // whole waves
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < u_end; u += stride) {
+    uint32_t bad = 0;
     int layer = 0;
-    if (model == 0) {
-      if (!(wu > 0.0) || !(wu < __builtin_inf())) bad |= 1u;
-      else layer = ilogb(wu / g->w0);
-    } else {
-      if (!(wu >= 0.0 && wu <= g->R)) bad |= 1u;
-      else layer = (int)floor((g->R - wu) / (2.0 * 0.6931471805599453));
-    }
-    if (!bad && (layer < 0 || layer >= kMaxLayers)) bad |= 2u;
-    uint32_t q[D];
-    const double scale = ldexp(1.0, g->Dmax);
+    double wu = 0.0;
+    if (u < n) {
+      wu = w[u];
+      if (model == 0) {
+        if (!(wu > 0.0) || !(wu < __builtin_inf())) bad |= 1u;
+        else layer = ilogb(wu / g->w0);
+      } else {
+        if (!(wu >= 0.0 && wu <= g->R)) bad |= 1u;
+        else layer = (int)floor((g->R - wu) / (2.0 * 0.6931471805599453));
+      }
+      if (!bad && (layer < 0 || layer >= kMaxLayers)) bad |= 2u;
+      uint32_t q[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double xk = x[(uint64_t)k * n + u];
-      if (!(xk >= 0.0 && xk < 1.0)) bad |= 4u;
-      q[k] = bad ? 0u : (uint32_t)(xk * scale);
+      for (int k = 0; k < D; ++k) {
+        const double xk = x[(uint64_t)k * n + u];
+        if (!(xk >= 0.0 && xk < 1.0)) bad |= 4u;
+        q[k] = bad ? 0u : (uint32_t)(xk * scale);
+      }
+      if (bad) {
+        atomicOr(flag, bad);
+      } else {
+        const uint32_t m = morton_encode<D>(q);
+        keys[u] = ((uint64_t)layer << g->bits) | m;
+        ids[u] = (uint32_t)u;
+      }
     }
-    if (bad) {
-      atomicOr(flag, bad);
-    } else {
-      const uint32_t m = morton_encode<D>(q);
-      keys[u] = ((uint64_t)layer << g->bits) | m;
-      ids[u] = (uint32_t)u;
-      atomicAdd(&scount[layer], 1);
-      const unsigned long long bw = (unsigned long long)__double_as_longlong(wu);
-      if (model == 0) atomicMax(&sext[layer], bw);  // positive doubles order as integers
-      else atomicMin(&sext[layer], bw);
+    // one LDS update per distinct layer of the wave: most lanes share a layer,
+    // and same-address LDS atomics serialise
+    const bool ok = u < n && !bad;
+    const int lay = ok ? layer : -1;
+    const unsigned long long bw = ok ? (unsigned long long)__double_as_longlong(wu) : 0ull;
+    uint64_t pending = __ballot(ok);
+    while (pending) {
+      const int L0 = __shfl(lay, __ffsll((unsigned long long)pending) - 1, 64);
+      const bool mine = lay == L0;
+      const uint64_t same = __ballot(mine);
+      // extreme weight of the layer over the wave (positive doubles order as integers)
+      unsigned long long v = mine ? bw : (model == 0 ? 0ull : ~0ull);
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(v, o, 64);
+        v = model == 0 ? (t > v ? t : v) : (t < v ? t : v);
+      }
+      if ((int)lane_id() == __ffsll((unsigned long long)same) - 1) {
+        atomicAdd(&scount[L0], (int)__popcll(same));
+        if (model == 0) atomicMax(&sext[L0], v);
+        else atomicMin(&sext[L0], v);
+      }
+      pending &= ~same;
     }
   }
   __syncthreads();
@@ -120,7 +145,7 @@ __global__ __launch_bounds__(256) void k_layer_key(Graph* __restrict__ g,
 
 hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const double* x,
                             uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st) {
-  const unsigned blocks = (unsigned)((g.n + 255) / 256);
+  const unsigned blocks = (unsigned)std::min<uint64_t>((g.n + 255) / 256, 512);
   switch (g.d) {
     case 1: hipLaunchKernelGGL(k_layer_key<1>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
     case 2: hipLaunchKernelGGL(k_layer_key<2>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
@@ -176,8 +201,7 @@ hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, 
 // cell pairs (loop swap, Sec. 3.3), and the type-II bounds pbar.
 // One block; the sizes are tiny (<= 64 x 64 layer pairs).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
-                                                Pbar* __restrict__ pb) {
+__global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap) {
   __shared__ int dmax;
   __shared__ int8_t scl[kMaxLayers][kMaxLayers];
   const int L = g->L, d = g->d;
@@ -225,7 +249,7 @@ __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
   for (int p = threadIdx.x; p < kMaxLayers * kMaxLevels; p += blockDim.x) {
     const int i = p / kMaxLevels, l = p % kMaxLevels;
     uint64_t m1 = 0, m2 = 0;
-    for (int j = 0; j < kMaxLayers; ++j) {
+    for (int j = 0; j < (i < L ? L : 0); ++j) {  // CL is -1 outside the L x L block
       const int cl = scl[i][j];
       if (cl < 0) continue;
       if (cl == l) m1 |= 1ull << j;
@@ -234,12 +258,19 @@ __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
     g->jI[i][l] = m1;
     g->jII[i][l] = g->T > 0.0 ? m2 : 0ull;  // threshold: distant cells hold no edges
   }
-  if (!(g->T > 0.0) || pb == nullptr) return;
-  // pbar for (i, j, level, gap): largest weights, smallest distance gap 2^-level
+}
+
+// pbar for (i, j, level, gap): largest weights, smallest distance gap
+// 2^-level; one entry per thread over the whole grid (after k_tables)
+__global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int Dcap,
+                                              Pbar* __restrict__ pb, int total) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const int L = g->L, d = g->d;
   const int nl = Dcap + 1;
-  for (int p = threadIdx.x; p < L * L * nl * 2; p += blockDim.x) {
+  {
     const int gi = p & 1, l = (p >> 1) % nl, ij = (p >> 1) / nl, i = ij / L, j = ij % L;
-    const int cl = (i < L && j < L) ? scl[i][j] : -1;
+    const int cl = (i < L && j < L) ? g->CL[i][j] : -1;
     Pbar e{0.0, 0.0, 0, 0};
     if (cl >= l && l >= 2) {
       const double dist = ldexp((double)(gi + 1), -l);
@@ -263,8 +294,12 @@ __global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap,
   }
 }
 
-hipError_t launch_tables(Graph* gd, int Dcap, Pbar* pb, hipStream_t st) {
-  hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, st, gd, Dcap, pb);
+hipError_t launch_tables(Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st) {
+  hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, st, gd, Dcap);
+  if (pb && L > 0) {
+    const int total = L * L * (Dcap + 1) * 2;
+    hipLaunchKernelGGL(k_pbar, dim3((total + 255) / 256), dim3(256), 0, st, gd, Dcap, pb, total);
+  }
   return hipGetLastError();
 }
 

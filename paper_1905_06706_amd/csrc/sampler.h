@@ -85,7 +85,9 @@ hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const do
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* w, const double* x, double* sw, double* rec, uint32_t* smort,
                          uint8_t* slayer, hipStream_t st);
-hipError_t launch_tables(Graph* gd, int Dcap, Pbar* pb, hipStream_t st);
+// level tables (CL, D, I, layer masks) in one workgroup, then the pbar table
+// (pb non-null for T > 0; L * L * (Dcap + 1) * 2 entries) over a grid
+hipError_t launch_tables(Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st);
 hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* smort,
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
