@@ -102,6 +102,7 @@ struct Ctx {
   // group complete with one stream synchronisation
   void* pin = nullptr;
   size_t pin_size = 0;
+  void* pin_up = nullptr;  // uploads (the 40 KB Graph among them), kPinUpload bytes
   std::mutex mu;
   // stage timing (HIP events), enabled by girg_set_profiling: a stage's time
   // runs from the event before it to its own, both on the stream it ran on;
@@ -147,6 +148,7 @@ struct Ctx {
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     if (pin) (void)hipHostFree(pin);
+    if (pin_up) (void)hipHostFree(pin_up);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -183,8 +185,27 @@ class Readback {
     for (const Item& it : items_) std::memcpy(it.dst, static_cast<char*>(cx_.pin) + it.off, it.bytes);
     items_.clear();
     used_ = 0;
+    up_used_ = 0;  // the stream has drained: every staged upload has been read
     return hipSuccess;
   }
+  // host-to-device copy staged in the pinned upload buffer (a pageable source
+  // blocks the host once per copy); falls back to a direct copy when the
+  // buffer is full.  The staged bytes are reused only after wait().
+  hipError_t upload(void* dst, const void* src, size_t bytes) {
+    if (!cx_.pin_up) {
+      if (hipHostMalloc(&cx_.pin_up, kPinUpload, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        cx_.pin_up = nullptr;
+      }
+    }
+    const size_t off = (up_used_ + 255) & ~(size_t)255;
+    if (!cx_.pin_up || off + bytes > kPinUpload)
+      return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
+    std::memcpy(static_cast<char*>(cx_.pin_up) + off, src, bytes);
+    up_used_ = off + bytes;
+    return hipMemcpyAsync(dst, static_cast<char*>(cx_.pin_up) + off, bytes, hipMemcpyHostToDevice, st_);
+  }
+  static constexpr size_t kPinUpload = 256 << 10;
 
  private:
   struct Item {
@@ -195,6 +216,7 @@ class Readback {
   hipStream_t st_;
   std::vector<Item> items_;
   size_t used_ = 0;
+  size_t up_used_ = 0;
 };
 constexpr size_t kSmallReadback = 1 << 16;
 
@@ -643,12 +665,31 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   const int d = g.d;
   if (cx.ev_name.empty()) cx.mark("-", st);
 
-  // exact sum W and min / max of w (GIRG) or r (HRG)
-  HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
-  double red[6];
+  // exact sum W and min / max of w (GIRG) or r (HRG), then the layer and
+  // Morton keys.  W and w0 reach the device Graph from the reduction on the
+  // device, so both are read back in one group; the keys of invalid input are
+  // computed but never used (the checks below reject it first).
   Readback rb(cx, st);
+  for (int i = 0; i < kMaxLayers; ++i) {
+    g.ext[i] = p.model == 0 ? 0.0 : __builtin_inf();
+  }
+  HIPCHK(rb.upload(cx.gd, &g, sizeof(Graph)));
+  HIPCHK(hipMemsetAsync(cx.flag, 0, sizeof(uint32_t), st));
+  uint64_t* keys = ar.get<uint64_t>(n);
+  uint32_t* ids = ar.get<uint32_t>(n);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (keys)");
+  HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
+  if (p.model == 0) HIPCHK(launch_set_weight_sums(cx.gd, cx.red, st));
+  cx.mark("-", st);
+  HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
+  cx.mark("layer_key", st);
+  double red[6];
+  uint32_t flag = 0;
   HIPCHK(rb.begin(kSmallReadback));
   HIPCHK(rb.add(red, cx.red, sizeof(red)));
+  HIPCHK(rb.add(&flag, cx.flag, sizeof(uint32_t)));
+  HIPCHK(rb.add(g.count, cx.gd->count, sizeof(g.count)));
+  HIPCHK(rb.add(g.ext, cx.gd->ext, sizeof(g.ext)));
   HIPCHK(rb.wait());
   if (p.model == 0) {
     if (!(red[4] > 0.0) || !std::isfinite(red[5]))
@@ -660,25 +701,6 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   } else {
     if (!(red[4] >= 0.0) || !(red[5] <= p.R)) return fail(GIRG_EINVAL, "radii must lie in [0, R]");
   }
-
-  // layer + Morton keys
-  for (int i = 0; i < kMaxLayers; ++i) {
-    g.ext[i] = p.model == 0 ? 0.0 : __builtin_inf();
-  }
-  HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(cx.flag, 0, sizeof(uint32_t), st));
-  uint64_t* keys = ar.get<uint64_t>(n);
-  uint32_t* ids = ar.get<uint32_t>(n);
-  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (keys)");
-  cx.mark("-", st);
-  HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
-  cx.mark("layer_key", st);
-  uint32_t flag = 0;
-  HIPCHK(rb.begin(kSmallReadback));
-  HIPCHK(rb.add(&flag, cx.flag, sizeof(uint32_t)));
-  HIPCHK(rb.add(g.count, cx.gd->count, sizeof(g.count)));
-  HIPCHK(rb.add(g.ext, cx.gd->ext, sizeof(g.ext)));
-  HIPCHK(rb.wait());
   if (flag & 1u) return fail(GIRG_EINVAL, p.model == 0 ? "weights must be finite and > 0" : "radii must lie in [0, R]");
   if (flag & 2u) return fail(GIRG_EINVAL, "more than 64 weight layers");
   if (flag & 4u) return fail(GIRG_EINVAL, "positions must lie in [0,1)");
@@ -772,7 +794,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     pbt = ar.get<Pbar>((uint64_t)std::max(g.L, 1) * std::max(g.L, 1) * nlev * 2);
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (pbar)");
   }
-  HIPCHK(hipMemcpyAsync(cx.gd, &g, sizeof(Graph), hipMemcpyHostToDevice, st));
+  HIPCHK(rb.upload(cx.gd, &g, sizeof(Graph)));
   cx.mark("-", st);
   HIPCHK(launch_tables(cx.gd, g.L, Dcap, pbt, st));
   cx.mark("tables", st);
@@ -795,8 +817,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   g.moff[0] = 0;
   for (int l = 0; l < kMaxLevels; ++l)
     g.moff[l + 1] = g.moff[l] + (l <= maxI ? (1ull << (d * l)) : 0ull);
-  HIPCHK(hipMemcpyAsync(cx.gd->pbase, g.pbase, sizeof(g.pbase), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(cx.gd->moff, g.moff, sizeof(g.moff), hipMemcpyHostToDevice, st));
+  HIPCHK(rb.upload(cx.gd->pbase, g.pbase, sizeof(g.pbase)));
+  HIPCHK(rb.upload(cx.gd->moff, g.moff, sizeof(g.moff)));
   uint32_t* P = ar.get<uint32_t>(cells);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (cells)");
   cx.mark("-", st);

@@ -155,6 +155,20 @@ hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const do
   return hipGetLastError();
 }
 
+// W = sum of the weights and w0 = the smallest, from the reduction's results
+// (red[0], red[4]), into the device Graph before the layer keys need w0
+__global__ void k_set_weight_sums(Graph* __restrict__ g, const double* __restrict__ red) {
+  if (threadIdx.x == 0) {
+    g->W = red[0];
+    g->w0 = red[4];
+  }
+}
+
+hipError_t launch_set_weight_sums(Graph* gd, const double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_weight_sums, dim3(1), dim3(64), 0, st, gd, red);
+  return hipGetLastError();
+}
+
 // sorted structure-of-arrays copy
 __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
                                                 const uint64_t* __restrict__ keys,

@@ -80,6 +80,7 @@ struct ChunkBases {
 };
 
 hipError_t launch_points(const Graph& g, double beta, double* w, double* x, hipStream_t st);
+hipError_t launch_set_weight_sums(Graph* gd, const double* red, hipStream_t st);
 hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const double* x,
                             uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st);
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
