@@ -124,3 +124,31 @@ def test_missing_file(lib, tmp_path):
         lib.tuning_load(str(tmp_path / "nope.json"))
     with pytest.raises(lib.GirgError):
         lib.tuning_save(os.path.join(str(tmp_path), "no_dir", "x.json"))
+
+
+def test_env_tuning_file_loaded_at_first_call(tmp_path):
+    """GIRG_TUNING_FILE is read once, at the library's first tuning lookup (a
+    fresh process); a malformed file is reported on stderr and ignored."""
+    import subprocess
+    import sys
+    good = tmp_path / "good.json"
+    good.write_text('{"version": 1, "single": [{"model": 0, "d": 2, "binomial": 1, "log2n": 20, '
+                    '"blocks": 640}], "batch": {"blocks": 320, "workers": 6}}')
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"version": 1, "single": [{"model": 0}]}')
+    code = ("import paper_1905_06706_amd as hg\n"
+            "p = hg.make_params(2**20, 2, 2.7, 0.5, 16.0)\n"
+            "print(hg.tuning_get(p)[0], *hg.tuning_get(p, batch=True))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GIRG_TUNING_FILE=str(good))
+    env.pop("GIRG_BATCH_WORKERS", None)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["640", "320", "6"]
+    env["GIRG_TUNING_FILE"] = str(bad)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["512", "256", "16"]
+    assert "GIRG_TUNING_FILE ignored" in r.stderr
