@@ -160,7 +160,16 @@ struct Ctx {
 class Readback {
  public:
   Readback(Ctx& cx, hipStream_t st) : cx_(cx), st_(st) {}
+  // a call that returns early (an error) may leave copies in flight that
+  // read or write the pinned buffers: drain them before the buffers are reused
+  ~Readback() {
+    if (!items_.empty() || up_used_) (void)hipStreamSynchronize(st_);
+  }
   hipError_t begin(size_t bytes) {
+    if (!items_.empty()) {
+      hipError_t e = hipStreamSynchronize(st_);  // an unfinished group: let it land first
+      if (e != hipSuccess) return e;
+    }
     items_.clear();
     used_ = 0;
     bytes = (bytes + 4095) & ~(size_t)4095;
