@@ -58,7 +58,8 @@ def test_threshold_from_points(hg, orc, d, n, beta, seed):
     assert rep["gpu"] > n
 
 
-@pytest.mark.parametrize("d,n,T,seed", [(1, 8000, 0.5, 3), (2, 12000, 0.5, 2), (3, 6000, 0.8, 4), (2, 6000, 0.3, 9), (1, 5000, 0.9, 11)])
+@pytest.mark.parametrize("d,n,T,seed", [(1, 8000, 0.5, 3), (2, 12000, 0.5, 2), (3, 6000, 0.8, 4), (2, 6000, 0.3, 9),
+                                        (1, 5000, 0.9, 11), (4, 3000, 0.6, 12), (4, 2500, 0.2, 13)])
 def test_binomial_from_points(hg, orc, d, n, T, seed):
     w = synth.pareto_weights(n, 2.5, seed)
     x = synth.positions(n, d, seed)
@@ -93,7 +94,7 @@ def test_heavy_items_split_into_segments(hg, orc):
     assert info["draws"] == run.stats["draws"]
 
 
-@pytest.mark.parametrize("T", [0.0, 0.5])
+@pytest.mark.parametrize("T", [0.0, 0.5, 0.9])
 def test_hrg_from_points(hg, orc, T):
     n, alpha = 20000, 0.75
     R = orc.hrg_solve_R(n, alpha, T, 10.0)
