@@ -172,6 +172,23 @@ def test_empty_and_tiny_graphs(hg, orc):
     assert len(ge) == 0 and len(run.edges) == 0
 
 
+@pytest.mark.parametrize("T,d", [(0.0, 2), (0.5, 2), (0.5, 3), (0.9, 1)])
+def test_degenerate_one_point_one_layer(hg, orc, T, d):
+    """Every vertex at one position and of one weight: one layer, every pair in
+    one cell at every level (a single triangular type-I item per level pair,
+    split into pieces), distance 0 so p_uv = 1: the complete graph, by the
+    oracle and by the closed form n (n - 1) / 2."""
+    n = 1500
+    w = np.full(n, 3.0)
+    x = np.full((n, d), 0.3125)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=0.5, seed=7)
+    compare(ge, run)
+    assert len(ge) == n * (n - 1) // 2
+    assert info["split_items"] > 0
+    pairs = np.sort(ge.astype(np.int64), axis=1)
+    assert len(np.unique(pairs[:, 0] * n + pairs[:, 1])) == n * (n - 1) // 2
+
+
 @pytest.mark.parametrize("d,n,beta,T,seed", [(1, 2**16, 2.5, 0.5, 21), (2, 2**17, 2.7, 0.5, 22),
                                              (3, 2**17, 2.3, 0.8, 23), (4, 2**15, 2.6, 0.3, 24),
                                              (2, 2**16, 2.1, 0.9, 25)])

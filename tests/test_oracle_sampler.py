@@ -314,3 +314,19 @@ def test_power_law_degrees(orc):
     top = np.sort(deg)[::-1][:600].astype(float)
     hill = 1.0 / np.mean(np.log(top[:-1] / top[-1]))  # CCDF exponent beta - 1
     assert abs(hill + 1.0 - beta) < 0.35
+
+
+@pytest.mark.parametrize("T,d", [(0.0, 2), (0.5, 3), (0.9, 1)])
+def test_coincident_points_give_the_complete_graph(orc, T, d):
+    """All vertices at one position with one weight: distance 0, so p_uv = 1
+    (Eq. (1) saturates) and the threshold holds for every pair: the sampler
+    must return each of the n (n - 1) / 2 pairs exactly once, from a single
+    type-I item (one layer, one cell at every level)."""
+    n = 600
+    w = np.full(n, 3.0)
+    x = np.full((n, d), 0.3125)
+    run = orc.run(w, x, T=T, c=0.5, seed=7, keep=True)
+    e = np.sort(run.edges.astype(np.int64), axis=1)
+    assert len(e) == n * (n - 1) // 2
+    assert len(np.unique(e[:, 0] * n + e[:, 1])) == n * (n - 1) // 2
+    assert run.stats["type1_items"] == 1 and run.stats["type2_items"] == 0
