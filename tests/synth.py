@@ -46,3 +46,14 @@ def clustered_positions(n: int, d: int, seed: int, clusters: int = 4) -> np.ndar
     q = np.floor(x * 2.0**53).astype(np.int64)
     q = np.minimum(q, 2**53 - 1)
     return q.astype(np.float64) * 2.0**-53
+
+
+def seam_positions(n: int, d: int, seed: int, width: float = 2.0**-7) -> np.ndarray:
+    """Positions within `width` of the torus seam 0 = 1 in every coordinate,
+    half just above 0 and half just below 1 (exact multiples of 2^-53), so
+    that most close pairs are close only across the seam."""
+    g = rng(seed + 1013)
+    q = g.integers(0, int(width * 2**53), size=(n, d), dtype=np.int64)
+    hi = g.random((n, d)) < 0.5
+    q = np.where(hi, 2**53 - 1 - q, q)
+    return q.astype(np.float64) * 2.0**-53

@@ -172,6 +172,27 @@ def test_empty_and_tiny_graphs(hg, orc):
     assert len(ge) == 0 and len(run.edges) == 0
 
 
+@pytest.mark.parametrize("T,d", [(0.0, 2), (0.5, 2), (0.0, 3), (0.8, 3)])
+def test_torus_seam(hg, orc, T, d):
+    """Points within 2^-4 of the seam 0 = 1 in every coordinate (c scaled down
+    by 8 for the density): pairs on the two sides are near only through the
+    wrap-around of the torus distance, and their cells are neighbours (type
+    I) or distant (type II) only modulo 2^level."""
+    n = 4000
+    w = synth.pareto_weights(n, 2.5, 17)
+    x = synth.seam_positions(n, d, 17, width=2.0**-4)
+    c = orc.solve_c(w, d, T, 10.0) / 8.0
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=17)
+    compare(ge, run)
+    assert info["tests"] == run.stats["tests"] and info["draws"] == run.stats["draws"]
+    # a share of the edges joins the two sides of the seam (7-53 % here)
+    e = ge.astype(np.int64)
+    cross = np.any((x[e[:, 0]] < 0.5) != (x[e[:, 1]] < 0.5), axis=1)
+    assert cross.mean() > 0.05
+    if T > 0.0:
+        assert run.stats["type2_items"] > 1000
+
+
 @pytest.mark.parametrize("T,d", [(0.0, 2), (0.5, 2), (0.5, 3), (0.9, 1)])
 def test_degenerate_one_point_one_layer(hg, orc, T, d):
     """Every vertex at one position and of one weight: one layer, every pair in
