@@ -387,8 +387,11 @@ struct CSolve {
     return (double)(((long double)A * s1 - (long double)B * s2 + cnt) / (long double)n);
   }
 
-  // bracket by doubling / halving, then regula falsi (Illinois) on log c
-  // until the bracket is a few ulps wide; returns its upper end.  f is
+  // bracket by doubling / halving, then regula falsi on log c with the
+  // Anderson-Bjorck scaling of a stale end, until the bracket is a few ulps
+  // wide; returns its upper end.  When f hits the target exactly at the upper
+  // end (common once the bracket is narrow, and where the secant would stall),
+  // a point two ulps below closes the bracket.  f is
   // evaluated exactly wherever h is complete, i.e. at every c up to some
   // bound.  A lower end is only taken where f < target and an upper end where
   // f >= target, so when h is complete at the final upper end (checked by the
@@ -407,6 +410,15 @@ struct CSolve {
     int side = 0;
     for (it = 0; it < 200; ++it) {
       if (!(hi > lo) || hi - lo <= 4.0 * std::ldexp(hi, -52)) break;
+      if (fhi == 0.0) {
+        const double c = hi - 2.0 * std::ldexp(hi, -52);
+        if (!(c > lo)) break;
+        const double fc = f(c) - target;
+        if (fc < 0.0) { lo = c; a = std::log(c); flo = fc; }
+        else { hi = c; b = std::log(c); fhi = fc; }
+        side = 0;
+        continue;
+      }
       double x = (fhi == flo) ? 0.5 * (a + b) : b - fhi * (b - a) / (fhi - flo);
       if (!(x > a && x < b)) x = 0.5 * (a + b);
       double c = std::exp(x);
@@ -417,12 +429,12 @@ struct CSolve {
       }
       const double fc = f(c) - target;
       if (fc < 0.0) {
+        if (side == -1) { const double m = 1.0 - fc / flo; fhi *= m > 0.0 ? m : 0.5; }
         lo = c; a = x; flo = fc;
-        if (side == -1) fhi *= 0.5;
         side = -1;
       } else {
+        if (side == 1) { const double m = 1.0 - fc / fhi; flo *= m > 0.0 ? m : 0.5; }
         hi = c; b = x; fhi = fc;
-        if (side == 1) flo *= 0.5;
         side = 1;
       }
     }
