@@ -263,20 +263,24 @@ def sweep(steps: int, warmup: int) -> int:
             m = ctypes.c_uint64(0)
             for _ in range(warmup):
                 L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), None, sp)
-            hg.set_profiling(True)
-            groups = {g: 0.0 for g in SWEEP_GROUPS}
+            # whole calls timed without stage events, then the same calls profiled
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
                 st = L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), None, sp)
                 if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
                     hg._check(st)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            hg.set_profiling(True)
+            groups = {g: 0.0 for g in SWEEP_GROUPS}
+            for _ in range(steps):
+                L.girg_generate(ctypes.byref(p), None, 0, ctypes.byref(m), None, sp)
                 for stage, ms in hg.stage_times():
                     for g, members in SWEEP_GROUPS.items():
                         if stage in members:
                             groups[g] += ms / steps
             torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / steps
             hg.set_profiling(False)
             edges = max(int(m.value), 1)
             row = {"series": name, **cfg, "edges": int(m.value), "ms_per_step": dt * 1e3,
@@ -448,22 +452,28 @@ def main() -> int:
     print(f"[bench] tuning {tuning}", file=sys.stderr)
     for _ in range(args.warmup):
         hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
-    hg.set_profiling(True)
-    stage_sum: dict = {}
+    # the timed steps run without stage events; the stage and kernel times come
+    # from a few profiled steps after them (the same work, untimed)
     edges = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
         edges += m.value
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    hg.set_profiling(True)
+    stage_sum: dict = {}
+    nprof = max(1, min(args.steps, 5))
+    for _ in range(nprof):
+        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
         for name, ms in hg.stage_times():
             stage_sum[name] = stage_sum.get(name, 0.0) + ms
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     hg.set_profiling(False)
-    dt = t1 - t0
     info_d = info.as_dict()
-    stages = {k: v / args.steps for k, v in stage_sum.items()}
+    stages = {k: v / nprof for k, v in stage_sum.items()}
     print(f"[bench] {desc}: m={m.value} steps={args.steps} {dt / args.steps * 1e3:.3f} ms/step",
           file=sys.stderr)
     for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
