@@ -99,10 +99,25 @@ struct Ctx {
   hipEvent_t fork = nullptr, join = nullptr;
   // pinned host memory for readbacks: a copy into pageable memory blocks the
   // host once per copy (about 12 us each), into pinned memory the copies of a
-  // group complete with one stream synchronisation
-  void* pin = nullptr;
-  size_t pin_size = 0;
-  void* pin_up = nullptr;  // uploads (the 40 KB Graph among them), kPinUpload bytes
+  // group complete with one stream synchronisation.  One set per stream.
+  struct Pins {
+    void* pin = nullptr;
+    size_t pin_size = 0;
+    void* pin_up = nullptr;  // uploads (the 40 KB Graph among them)
+    Pins() = default;
+    Pins(const Pins&) = delete;
+    Pins& operator=(const Pins&) = delete;
+    ~Pins() {
+      if (pin) (void)hipHostFree(pin);
+      if (pin_up) (void)hipHostFree(pin_up);
+    }
+  };
+  Pins pins, pins_side;
+  // scratch of the c solve's first round, which runs on the side stream while
+  // the main stream sorts: an arena and result slots of its own, so that no
+  // allocation of the main stream reuses memory still in use there
+  Arena ar_side;
+  double* red_side = nullptr;  // 8 doubles
   std::mutex mu;
   // stage timing (HIP events), enabled by girg_set_profiling: a stage's time
   // runs from the event before it to its own, both on the stream it ran on;
@@ -147,8 +162,7 @@ struct Ctx {
     if (side) (void)hipStreamDestroy(side);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
-    if (pin) (void)hipHostFree(pin);
-    if (pin_up) (void)hipHostFree(pin_up);
+    if (red_side) (void)hipFree(red_side);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -159,7 +173,7 @@ struct Ctx {
 // the stream once and moves the data to its destinations.
 class Readback {
  public:
-  Readback(Ctx& cx, hipStream_t st) : cx_(cx), st_(st) {}
+  Readback(Ctx& cx, hipStream_t st, bool side = false) : cx_(side ? cx.pins_side : cx.pins), st_(st) {}
   // a call that returns early (an error) may leave copies in flight that
   // read or write the pinned buffers: drain them before the buffers are reused
   ~Readback() {
@@ -221,7 +235,7 @@ class Readback {
     void* dst;
     size_t off, bytes;
   };
-  Ctx& cx_;
+  Ctx::Pins& cx_;
   hipStream_t st_;
   std::vector<Item> items_;
   size_t used_ = 0;
@@ -247,6 +261,7 @@ static girg_status get_ctx(Ctx** out, int slot = 0) {
   c->device = dev;
   HIPCHK(hipMalloc(&c->gd, sizeof(Graph)));
   HIPCHK(hipMalloc(&c->red, 8 * sizeof(double)));
+  HIPCHK(hipMalloc(&c->red_side, 8 * sizeof(double)));
   HIPCHK(hipMalloc(&c->flag, sizeof(uint32_t)));
   HIPCHK(hipMalloc(&c->stats, 16 * sizeof(unsigned long long)));
   HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
@@ -443,20 +458,7 @@ struct CSolve {
   }
 };
 
-// sums over the first `cnt` layer-sorted weights (those outside the tail), on
-// the device: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
-// queues the sums over the weights outside the tail (the first cnt of the
-// layer-sorted weights) and their readback into r[0..5]
-static girg_status csolve_out_sums(Ctx& cx, const double* sw, uint64_t cnt, double T, double W,
-                                   double* r, Readback& rb, hipStream_t st) {
-  for (int k = 0; k < 6; ++k) r[k] = 0.0;
-  if (cnt == 0) return GIRG_OK;
-  const double invT = T > 0.0 ? 1.0 / T : 0.0;
-  const int nterms = T > 0.0 ? 4 : 2;
-  HIPCHK(reduce_terms(cx.ar, sw, cnt, nterms, 0, W, invT, cx.red, st));
-  HIPCHK(rb.add(r, cx.red, 6 * sizeof(double)));
-  return GIRG_OK;
-}
+// the sums over the weights outside the tail (w, w^2 / W, w^(1/T), (w^2 / W)^(1/T))
 static void csolve_take_sums(const double* r, double T, CSolve* cs) {
   cs->out_w = r[0];
   cs->out_q1 = r[1];
@@ -735,6 +737,58 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   g.lstart[kMaxLayers] = acc;
   const int lbits = bitlen((uint64_t)(g.L > 0 ? g.L - 1 : 0));
 
+  // constant c (App. B.2).  It needs only the heaviest weights (the tail,
+  // sorted by value) and sums over the others, both from the unsorted
+  // weights, so its first round runs on the side stream (with its own arena,
+  // result slots and pinned buffers) while the main stream sorts and gathers.
+  // Further rounds, when E_R needs a longer tail, run after the gather.
+  const bool csolve = p.model == 0 && !(p.c > 0.0);
+  hipStream_t scs = cx.side ? cx.side : st;
+  SideGuard cs_guard{cx};
+  Readback rbs(cx, scs, true);
+  CSolve cs;
+  int i0 = g.L;
+  std::vector<double> asc, ascp;
+  double rs[6];
+  auto cs_round = [&]() -> girg_status {
+    // the tail (layers >= i0), sorted by value, its powers w^(1/T), and the
+    // sums over the layers below i0: one readback
+    const uint64_t K = n - g.lstart[i0];
+    cx.ar_side.reset_all();
+    Arena& a2 = cx.ar_side;
+    uint64_t* tk = a2.get<uint64_t>(K);
+    uint32_t* tv = a2.get<uint32_t>(K);
+    unsigned int* tcnt = a2.get<unsigned int>(1);
+    double* tp = p.T > 0.0 ? a2.get<double>(K) : nullptr;
+    if (a2.failed()) {
+      a2.clear_failure();
+      return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
+    }
+    HIPCHK(hipMemsetAsync(tcnt, 0, sizeof(unsigned int), scs));
+    HIPCHK(launch_tail_collect(w, n, g.w0, i0, tk, tcnt, (uint32_t)K, scs));
+    HIPCHK(launch_iota(tv, K, scs));
+    HIPCHK(radix_sort(a2, tk, tv, K, 64, scs));  // positive doubles order as integers
+    if (tp) HIPCHK(launch_pow_bits(tk, tp, K, 1.0 / p.T, scs));
+    const double invT = p.T > 0.0 ? 1.0 / p.T : 0.0;
+    HIPCHK(reduce_terms(a2, w, n, p.T > 0.0 ? 4 : 2, 0, g.W, invT, cx.red_side, scs, g.w0, i0));
+    asc.assign(K, 0.0);
+    ascp.assign(tp ? K : 0, 0.0);
+    HIPCHK(rbs.begin(2 * K * sizeof(double) + 4096));
+    HIPCHK(rbs.add(asc.data(), tk, K * sizeof(double)));
+    if (tp) HIPCHK(rbs.add(ascp.data(), tp, K * sizeof(double)));
+    HIPCHK(rbs.add(rs, cx.red_side, 6 * sizeof(double)));
+    return GIRG_OK;
+  };
+  if (csolve) {
+    cs.n = n; cs.d = d; cs.T = p.T; cs.W = g.W;
+    // heaviest layers first, at least 1024 weights
+    uint64_t tail = 0;
+    while (i0 > 0 && tail < 1024) { --i0; tail += (uint64_t)g.count[i0]; }
+    HIPCHK(fork_side(cx, st, cx.side != nullptr, cs_guard));  // the weights are ready on st
+    girg_status s = cs_round();
+    if (s != GIRG_OK) return s;
+  }
+
   // stable sort by (layer, Morton code); ties keep id order
   cx.mark("-", st);
   HIPCHK(radix_sort(ar, keys, ids, n, g.bits + lbits, st));
@@ -747,44 +801,17 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, rec, smort, slayer, st));
   cx.mark("gather", st);
 
-  // constant c (App. B.2)
   cx.mark("-", st);
   if (p.model == 0) {
     double c = p.c;
-    if (!(c > 0.0)) {
-      CSolve cs;
-      cs.n = n; cs.d = d; cs.T = p.T; cs.W = g.W;
-      // heaviest layers first; grow the tail until E_R is complete
-      int i0 = g.L;
-      uint64_t tail = 0;
-      while (i0 > 0 && tail < 1024) { --i0; tail += (uint64_t)g.count[i0]; }
+    if (csolve) {
       for (;;) {
-        // the tail of the layer-sorted weights, sorted by value on the device
-        const uint64_t K = n - g.lstart[i0];
-        Arena::Mark mk = ar.mark();
-        uint64_t* tk = ar.get<uint64_t>(K);
-        uint32_t* tv = ar.get<uint32_t>(K);
-        if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
-        HIPCHK(hipMemcpyAsync(tk, sw + g.lstart[i0], K * sizeof(double), hipMemcpyDeviceToDevice, st));
-        HIPCHK(launch_iota(tv, K, st));
-        HIPCHK(radix_sort(ar, tk, tv, K, 64, st));  // positive doubles order as integers
-        double* tp = p.T > 0.0 ? ar.get<double>(K) : nullptr;
-        if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (c solve)");
-        if (tp) HIPCHK(launch_pow_bits(tk, tp, K, 1.0 / p.T, st));
-        // the tail, its powers and the sums over the rest: one readback
-        std::vector<double> asc(K), ascp(tp ? K : 0);
-        double rs[6];
-        HIPCHK(rb.begin(2 * K * sizeof(double) + 4096));
-        HIPCHK(rb.add(asc.data(), tk, K * sizeof(double)));
-        if (tp) HIPCHK(rb.add(ascp.data(), tp, K * sizeof(double)));
-        girg_status s = csolve_out_sums(cx, sw, g.lstart[i0], p.T, g.W, rs, rb, st);
-        if (s != GIRG_OK) return s;
-        HIPCHK(rb.wait());
-        ar.reset(mk);
+        HIPCHK(rbs.wait());  // the side stream's round (or st's, with no side stream)
+        const uint64_t K = asc.size();
         csolve_take_sums(rs, p.T, &cs);
         cs.h.assign(asc.rbegin(), asc.rend());
         cs.hp.assign(ascp.rbegin(), ascp.rend());
-        if (!tp) cs.hp.assign(K, 0.0);
+        if (p.T <= 0.0) cs.hp.assign(K, 0.0);
         cs.wcut = 0.0;
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
@@ -796,7 +823,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         // solve's c (the next lower layer fails that test, so this grows)
         const double cut = 0.5 * cs.th(c) / cs.h[0];
         while (i0 > 0 && (g.count[i0 - 1] == 0 || g.ext[i0 - 1] > cut)) --i0;
+        girg_status s = cs_round();
+        if (s != GIRG_OK) return s;
       }
+      HIPCHK(join_side(cx, st, cx.side != nullptr, cs_guard));
     }
     g.c = c;
     g.kappa = p.T > 0.0 ? std::pow(c, p.T) : std::pow(c, (double)d);

@@ -56,9 +56,14 @@ hipError_t scan_u32(Arena& ar, const uint32_t* in, uint32_t* out, uint64_t n, ui
                     hipStream_t st);
 hipError_t scan_u64(Arena& ar, const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* total,
                     hipStream_t st);
-// out6 (device): sums of terms mode0..mode0+nterms-1, then min, max of w
+// out6 (device): sums of terms mode0..mode0+nterms-1, then min, max of w;
+// with fi0 >= 0 only over the w with ilogb(w / fw0) < fi0 (the layers below fi0)
 hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
-                        double invT, double* out6, hipStream_t st);
+                        double invT, double* out6, hipStream_t st, double fw0 = 1.0, int fi0 = -1);
+// bit patterns of the weights with ilogb(w / w0) >= i0 into out (any order;
+// *cnt, zeroed by the caller, counts them; at most cap are stored)
+hipError_t launch_tail_collect(const double* w, uint64_t n, double w0, int i0, uint64_t* out,
+                               unsigned int* cnt, uint32_t cap, hipStream_t st);
 // in-place exclusive scans of up to four u64 arrays by one workgroup; the
 // running sum carries from array k - 1 into array k unless bit k of `reset`
 // is set (array 0 always starts at zero).  Arrays with n = 0 may be null.

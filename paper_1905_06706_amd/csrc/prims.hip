@@ -268,9 +268,11 @@ __device__ __forceinline__ double red_term(int mode, double w, double W, double 
 }
 
 // out layout per block: [hi, lo] for each of nterms sums, then min, max
+// fi0 >= 0: only the weights of the layers below fi0 (ilogb(w / fw0) < fi0)
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ w,
                                                                  uint64_t n, int nterms,
                                                                  int mode0, double W, double invT,
+                                                                 double fw0, int fi0,
                                                                  double* __restrict__ part) {
   __shared__ double shi[4][kRedThreads], slo[4][kRedThreads], smin[kRedThreads], smax[kRedThreads];
   const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* _
   double mn = __builtin_inf(), mx = -__builtin_inf();
   for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
     const double v = w[i];
+    if (fi0 >= 0 && ilogb(v / fw0) >= fi0) continue;
     mn = fmin(mn, v);
     mx = fmax(mx, v);
     for (int t = 0; t < nterms; ++t) dd_add(hi[t], lo[t], red_term(mode0 + t, v, W, invT));
@@ -357,13 +360,46 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double* __restrict__ 
 }
 
 hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int mode0, double W,
-                        double invT, double* out6, hipStream_t st) {
+                        double invT, double* out6, hipStream_t st, double fw0, int fi0) {
   Arena::Mark m = ar.mark();
   double* part = ar.get<double>((uint64_t)kRedBlocks * 10);
+  if (!part) {
+    ar.reset(m);
+    return hipErrorOutOfMemory;
+  }
   hipLaunchKernelGGL(k_reduce_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, n, nterms,
-                     mode0, W, invT, part);
+                     mode0, W, invT, fw0, fi0, part);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, part, kRedBlocks, out6);
   ar.reset(m);
+  return hipGetLastError();
+}
+
+// the weights of the layers from i0 up (ilogb(w / w0) >= i0, as the layer
+// keys), as bit patterns, in any order; one atomic per wave
+__global__ __launch_bounds__(256) void k_tail_collect(const double* __restrict__ w, uint64_t n,
+                                                      double w0, int i0, uint64_t* __restrict__ out,
+                                                      unsigned int* __restrict__ cnt, uint32_t cap) {
+  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = u < n ? w[u] : 0.0;
+  const bool in = u < n && ilogb(v / w0) >= i0;
+  const uint64_t mb = __ballot(in);
+  if (!mb) return;
+  const uint32_t lane = lane_id();
+  const int leader = __ffsll((unsigned long long)mb) - 1;
+  unsigned int base = 0;
+  if ((int)lane == leader) base = atomicAdd(cnt, (unsigned int)__popcll(mb));
+  base = __shfl(base, leader, 64);
+  if (in) {
+    const unsigned int pos = base + (unsigned int)__popcll(mb & ((1ull << lane) - 1ull));
+    if (pos < cap) out[pos] = (uint64_t)__double_as_longlong(v);
+  }
+}
+
+hipError_t launch_tail_collect(const double* w, uint64_t n, double w0, int i0, uint64_t* out,
+                               unsigned int* cnt, uint32_t cap, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tail_collect, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, n, w0, i0,
+                     out, cnt, cap);
   return hipGetLastError();
 }
 
