@@ -478,9 +478,8 @@ static void csolve_take_sums(const double* r, double T, CSolve* cs) {
 namespace rsolve {
 constexpr int kN = 12;
 static double X[kN], Wt[kN];
-static bool ready = false;
-static void init() {
-  if (ready) return;
+static std::once_flag ready;  // the batch's workers may solve radii concurrently
+static void init_nodes() {
   for (int i = 0; i < kN; ++i) {
     double z = std::cos(3.141592653589793 * (i + 0.75) / (kN + 0.5));
     for (int it = 0; it < 60; ++it) {
@@ -499,8 +498,8 @@ static void init() {
       }
     }
   }
-  ready = true;
 }
+static void init() { std::call_once(ready, init_nodes); }
 struct Q {
   double alpha, T, R, coshR, norm;
   double dens(double r) const { return alpha * std::sinh(alpha * r) / norm; }
