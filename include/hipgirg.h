@@ -193,7 +193,10 @@ girg_status girg_tuning_reset(void);
 girg_status girg_set_profiling(int32_t on);
 int32_t girg_stage_times(double* ms, const char** names, int32_t max);
 
-/* Frees the scratch memory cached for the current device. */
+/* Frees the scratch memory cached for the current device.  No other call of
+ * the library may be in progress on this device meanwhile.  (Other calls are
+ * safe to make from several host threads at once: single-graph calls on a
+ * device share one context and run one after another.) */
 girg_status girg_release(void);
 
 const char* girg_last_error(void);

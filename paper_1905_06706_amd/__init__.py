@@ -154,12 +154,21 @@ class Result:
     info: dict
 
 
-def _run_with_capacity(call, cap: int, device):
+def _on(stream):
+    """Allocations for work queued on `stream` are made on it, so that torch's
+    caching allocator hands their memory to another stream only after it."""
+    import contextlib
+    import torch
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
+
+
+def _run_with_capacity(call, cap: int, device, stream=None):
     """call(edges_ptr, cap, m_ref, info_ref) -> status; grows the buffer once
     on overflow (the sampler is deterministic, so the rerun is identical)."""
     import torch
     for _ in range(2):
-        buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=device)
+        with _on(stream):
+            buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=device)
         m = ctypes.c_uint64(0)
         info = Info()
         st = call(ctypes.c_void_p(buf.data_ptr()), cap, ctypes.byref(m), ctypes.byref(info))
@@ -181,7 +190,7 @@ def generate(n: int, d: int = 1, beta: float = 2.5, T: float = 0.0, avg_deg: flo
         cap = capacity_guess(n, avg_deg if avg_deg > 0 else 16.0)
     s = _stream(stream)
     return _run_with_capacity(lambda e, k, m, i: L.girg_generate(ctypes.byref(p), e, k, m, i, s),
-                              cap, device)
+                              cap, device, stream)
 
 
 def hrg(n: int, alpha: float, T: float = 0.0, R: float = 0.0, avg_deg: float = 0.0,
@@ -192,7 +201,8 @@ def hrg(n: int, alpha: float, T: float = 0.0, R: float = 0.0, avg_deg: float = 0
         cap = capacity_guess(n, avg_deg if avg_deg > 0 else 16.0)
     s = _stream(stream)
     return _run_with_capacity(
-        lambda e, k, m, i: L.girg_hrg(n, alpha, T, R, avg_deg, seed, e, k, m, i, s), cap, device)
+        lambda e, k, m, i: L.girg_hrg(n, alpha, T, R, avg_deg, seed, e, k, m, i, s), cap, device,
+        stream)
 
 
 def from_points(w, x, T: float, c: float = 0.0, avg_deg: float = 0.0, seed: int = 0,
@@ -210,7 +220,8 @@ def from_points(w, x, T: float, c: float = 0.0, avg_deg: float = 0.0, seed: int 
     s = _stream(stream)
     wp, xp = ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr())
     return _run_with_capacity(
-        lambda e, k, m, i: L.girg_from_points(ctypes.byref(p), wp, xp, e, k, m, i, s), cap, w.device)
+        lambda e, k, m, i: L.girg_from_points(ctypes.byref(p), wp, xp, e, k, m, i, s), cap, w.device,
+        stream)
 
 
 def points(n: int, d: int = 1, beta: float = 2.5, seed: int = 0, model: int = 0,
@@ -219,8 +230,9 @@ def points(n: int, d: int = 1, beta: float = 2.5, seed: int = 0, model: int = 0,
     import torch
     L = load()
     dd = 1 if model == 1 else d
-    w = torch.empty(n, dtype=torch.float64, device=device)
-    x = torch.empty((dd, n), dtype=torch.float64, device=device)
+    with _on(stream):
+        w = torch.empty(n, dtype=torch.float64, device=device)
+        x = torch.empty((dd, n), dtype=torch.float64, device=device)
     p = make_params(n, dd, beta, 0.0, 0.0, 0.0, seed, model=model, alpha=alpha, R=R)
     _check(L.girg_points(ctypes.byref(p), ctypes.c_void_p(w.data_ptr()),
                          ctypes.c_void_p(x.data_ptr()), _stream(stream)))
@@ -268,7 +280,8 @@ def generate_batch(params: list, cap: int | None = None, stream=None, device="cu
         cap = sum(capacity_guess(p.n, p.avg_deg if p.avg_deg > 0 else 16.0) for p in params)
     s = _stream(stream)
     for _ in range(2):
-        buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=device)
+        with _on(stream):
+            buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=device)
         offs = (ctypes.c_uint64 * (cnt + 1))()
         infos = (Info * cnt)()
         st = L.girg_generate_batch(arr, cnt, ctypes.c_void_p(buf.data_ptr()), cap, offs, infos, s)

@@ -1102,11 +1102,19 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   return GIRG_OK;
 }
 
-static girg_status with_ctx(Ctx** cx, int slot = 0) {
-  girg_status s = get_ctx(cx, slot);
+// The context of (device, slot), locked for the whole call, then its arena
+// cleared.  The reset must come after the lock: a call of another host thread
+// may still be allocating from this arena until it releases the lock.
+struct CtxLock {
+  Ctx* cx = nullptr;
+  std::unique_lock<std::mutex> lk;
+};
+static girg_status lock_ctx(CtxLock* out, int slot = 0) {
+  girg_status s = get_ctx(&out->cx, slot);
   if (s != GIRG_OK) return s;
-  (*cx)->ar.reset_all();
-  (*cx)->ar.clear_failure();
+  out->lk = std::unique_lock<std::mutex>(out->cx->mu);
+  out->cx->ar.reset_all();
+  out->cx->ar.clear_failure();
   return GIRG_OK;
 }
 
@@ -1162,9 +1170,9 @@ girg_status girg_from_points(const girg_params* p, const double* w, const double
   girg_status s = validate(*p, false);
   if (s != GIRG_OK) return s;
   if (p->model == 1 && !(p->R > 0.0)) return fail(GIRG_EINVAL, "girg_from_points needs R > 0 for an HRG");
-  Ctx* cx = nullptr;
-  if ((s = with_ctx(&cx)) != GIRG_OK) return s;
-  std::lock_guard<std::mutex> lk(cx->mu);
+  CtxLock cl;
+  if ((s = lock_ctx(&cl)) != GIRG_OK) return s;
+  Ctx* cx = cl.cx;
   if (info) std::memset(info, 0, sizeof(*info));
   cx->ev_name.clear();
   return run_graph(*cx, *p, w, x, edges, cap, m_out, info, static_cast<hipStream_t>(stream));
@@ -1180,9 +1188,9 @@ static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t
     s = solve_R_cached(q.n, q.alpha, q.T, q.avg_deg, &q.R);
     if (s != GIRG_OK) return s;
   }
-  Ctx* cx = nullptr;
-  if ((s = with_ctx(&cx, slot)) != GIRG_OK) return s;
-  std::lock_guard<std::mutex> lk(cx->mu);
+  CtxLock cl;
+  if ((s = lock_ctx(&cl, slot)) != GIRG_OK) return s;
+  Ctx* cx = cl.cx;
   if (info) std::memset(info, 0, sizeof(*info));
   hipStream_t st = slot > 0 ? cx->own : static_cast<hipStream_t>(stream);
   const int d = q.model == 1 ? 1 : q.d;
