@@ -58,7 +58,7 @@ OPS_CAND = 70.0         # candidate: distance, pow, compare
 # sources of the sampling kernels: HBM byte counters in profiles/ hold for
 # the kernels built from sources with this hash only
 KERNEL_SOURCES = ["paper_1905_06706_amd/csrc/sample.hip", "paper_1905_06706_amd/csrc/device_common.h",
-                  "paper_1905_06706_amd/csrc/sampler.h"]
+                  "paper_1905_06706_amd/csrc/sampler.h", "paper_1905_06706_amd/csrc/fastpow.h"]
 STAGE_KERNEL = {"type1": "k_type1<", "split1": "k_big1<", "type2": "k_type2<", "segments2": "k_heavy2<"}
 
 

@@ -27,6 +27,7 @@
 // pure function of the inputs and the seed, whatever wave ran which chunk, in
 // one sampling pass.
 #include "sampler.h"
+#include "fastpow.h"
 
 namespace hg {
 
@@ -89,12 +90,13 @@ __device__ __forceinline__ double pow_d(double r) {
   return rd;
 }
 
-// GIRG binomial probability of Eq. (1)
+// GIRG binomial probability of Eq. (1); the power 1/T by pow_pos (relative
+// error a few 2^-52, see fastpow.h)
 template <int D>
 __device__ __forceinline__ double girg_prob(const Graph* __restrict__ g, double wu, double wv,
                                            double r) {
   if (r == 0.0) return 1.0;
-  const double p = g->c * pow((wu * wv / g->W) / pow_d<D>(r), g->inv_T);
+  const double p = g->c * pow_pos((wu * wv / g->W) / pow_d<D>(r), g->inv_T);
   return p < 1.0 ? p : 1.0;
 }
 
@@ -807,7 +809,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   }
   if (!decided) {
     if (MX) ++nre;
-    const double q = log(S) / pe.lg;
+    const double q = log_pos(S) / pe.lg;
     if (q >= (double)rem) end = true;
     else skip = (uint64_t)q;
   }
