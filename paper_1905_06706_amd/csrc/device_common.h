@@ -175,7 +175,7 @@ struct Offs {
 // ---------------------------------------------------------------------------
 struct Pbar {
   double pbar;  // upper bound of the edge probability for (i, j, level, gap)
-  double lg;    // log1p(-pbar)
+  double ilg;   // 1 / log1p(-pbar): a skip is ln(S) * ilg
   int32_t e;    // segment exponent 5 - ilogb(pbar)
   float qscale; // 1 / log2(1 - pbar): a skip is log2(S) * qscale (FP32 filter)
 };

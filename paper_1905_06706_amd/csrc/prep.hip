@@ -300,9 +300,9 @@ __global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int D
         pbar = 1.0 / (exp((acosh(ch) - g->R) / (2.0 * g->T)) + 1.0);
       }
       e.pbar = pbar;
-      e.lg = log1p(-pbar);
+      e.ilg = 1.0 / log1p(-pbar);
       e.e = pbar > 0.0 ? kSegExp - ilogb(pbar) : 1 << 20;
-      e.qscale = pbar > 0.0 && pbar < 1.0 ? (float)(0.6931471805599453 / e.lg) : 0.0f;
+      e.qscale = pbar > 0.0 && pbar < 1.0 ? (float)(0.6931471805599453 * e.ilg) : 0.0f;
     }
     pb[p] = e;
   }

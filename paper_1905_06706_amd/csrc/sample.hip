@@ -96,7 +96,7 @@ template <int D>
 __device__ __forceinline__ double girg_prob(const Graph* __restrict__ g, double wu, double wv,
                                            double r) {
   if (r == 0.0) return 1.0;
-  const double p = g->c * pow_pos((wu * wv / g->W) / pow_d<D>(r), g->inv_T);
+  const double p = g->c * pow_pos((wu * wv) / (g->W * pow_d<D>(r)), g->inv_T);
   return p < 1.0 ? p : 1.0;
 }
 
@@ -360,12 +360,12 @@ struct QItem2 {
 // the pbar-table values an item's draws use, held in registers by the lane
 // that owns the item
 struct PB {
-  double pbar, lg;
+  double pbar, ilg;
   float qs;  // 1 / log2(1 - pbar)
 };
 __device__ __forceinline__ PB load_pb(const Pbar* __restrict__ pbt, uint32_t pidx) {
   const Pbar e = pbt[pidx];
-  return PB{e.pbar, e.lg, e.qscale};
+  return PB{e.pbar, e.ilg, e.qscale};
 }
 
 // type-II candidate: sorted indices and Acc * pbar
@@ -809,7 +809,10 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   }
   if (!decided) {
     if (MX) ++nre;
-    const double q = log_pos(S) / pe.lg;
+    // ln S * (1 / ln(1 - pbar)); S = 1 skips nothing (also where the
+    // reciprocal overflows to -inf)
+    const double ls = log_pos(S);
+    const double q = ls == 0.0 ? 0.0 : ls * pe.ilg;
     if (q >= (double)rem) end = true;
     else skip = (uint64_t)q;
   }
@@ -972,7 +975,7 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
         hv = true;
       } else {
         it = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), ca0, cb0, cnb, 0u, pidx, 0ull, N};
-        pe = PB{pv.pbar, pv.lg, pv.qscale};
+        pe = PB{pv.pbar, pv.ilg, pv.qscale};
         fresh = true;
       }
     }
