@@ -97,6 +97,7 @@ struct Ctx {
   // type II and the segmented type-II pass (fork/join by events)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t rb_done = nullptr;  // end of a readback group (Readback::end)
   // pinned host memory for readbacks: a copy into pageable memory blocks the
   // host once per copy (about 12 us each), into pinned memory the copies of a
   // group complete with one stream synchronisation.  One set per stream.
@@ -162,6 +163,7 @@ struct Ctx {
     if (side) (void)hipStreamDestroy(side);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (rb_done) (void)hipEventDestroy(rb_done);
     if (red_side) (void)hipFree(red_side);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -170,10 +172,13 @@ struct Ctx {
 // A group of device-to-host copies staged in the context's pinned buffer:
 // begin(bytes) makes room (no copy of an earlier group may be in flight, so
 // every group ends with wait()), add() queues one copy, wait() synchronises
-// the stream once and moves the data to its destinations.
+// the stream once and moves the data to its destinations.  end() marks the
+// end of the group with an event: wait() then waits for that point only, and
+// work queued after end() keeps the GPU busy meanwhile.
 class Readback {
  public:
-  Readback(Ctx& cx, hipStream_t st, bool side = false) : cx_(side ? cx.pins_side : cx.pins), st_(st) {}
+  Readback(Ctx& cx, hipStream_t st, bool side = false)
+      : cx_(side ? cx.pins_side : cx.pins), st_(st), ev_(side ? nullptr : cx.rb_done) {}
   // a call that returns early (an error) may leave copies in flight that
   // read or write the pinned buffers: drain them before the buffers are reused
   ~Readback() {
@@ -202,13 +207,24 @@ class Readback {
     used_ = off + bytes;
     return hipMemcpyAsync(static_cast<char*>(cx_.pin) + off, src, bytes, hipMemcpyDeviceToHost, st_);
   }
+  hipError_t end() {
+    if (!ev_) return hipSuccess;
+    hipError_t e = hipEventRecord(ev_, st_);
+    if (e != hipSuccess) return e;
+    ended_ = true;
+    up_end_ = up_used_;
+    return hipSuccess;
+  }
   hipError_t wait() {
-    hipError_t e = hipStreamSynchronize(st_);
+    const bool ev = ended_;
+    ended_ = false;
+    hipError_t e = ev ? hipEventSynchronize(ev_) : hipStreamSynchronize(st_);
     if (e != hipSuccess) return e;
     for (const Item& it : items_) std::memcpy(it.dst, static_cast<char*>(cx_.pin) + it.off, it.bytes);
     items_.clear();
     used_ = 0;
-    up_used_ = 0;  // the stream has drained: every staged upload has been read
+    // every staged upload queued before the waited point has been read
+    if (!ev || up_used_ == up_end_) up_used_ = 0;
     return hipSuccess;
   }
   // host-to-device copy staged in the pinned upload buffer (a pageable source
@@ -237,9 +253,11 @@ class Readback {
   };
   Ctx::Pins& cx_;
   hipStream_t st_;
+  hipEvent_t ev_;
+  bool ended_ = false;
   std::vector<Item> items_;
   size_t used_ = 0;
-  size_t up_used_ = 0;
+  size_t up_used_ = 0, up_end_ = 0;
 };
 constexpr size_t kSmallReadback = 1 << 16;
 
@@ -266,6 +284,7 @@ static girg_status get_ctx(Ctx** out, int slot = 0) {
   HIPCHK(hipMalloc(&c->stats, 16 * sizeof(unsigned long long)));
   HIPCHK(hipMalloc(&c->hcount, sizeof(unsigned int)));
   if (slot > 0) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->rb_done, hipEventDisableTiming));
   c->batch = slot > 0;
   // single-graph calls only: the batch's workers already fill the GPU, and
   // twice as many streams on the few hardware queues slowed the batch down
@@ -291,6 +310,17 @@ struct SideGuard {
     if (armed) (void)hipStreamSynchronize(cx.side);
   }
 };
+// work queued on a stream ahead of a host wait for an earlier point of it:
+// a call that returns meanwhile (an error) lets that work end first, since
+// it uses scratch memory that the next call reuses
+struct StreamGuard {
+  hipStream_t st;
+  bool armed = false;
+  ~StreamGuard() {
+    if (armed) (void)hipStreamSynchronize(st);
+  }
+};
+
 static hipError_t fork_side(Ctx& cx, hipStream_t st, bool on, SideGuard& gd) {
   if (!on) return hipSuccess;
   gd.armed = true;
@@ -712,6 +742,30 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(rb.add(&flag, cx.flag, sizeof(uint32_t)));
   HIPCHK(rb.add(g.count, cx.gd->count, sizeof(g.count)));
   HIPCHK(rb.add(g.ext, cx.gd->ext, sizeof(g.ext)));
+  HIPCHK(rb.end());
+
+  // Neither the c solve's first round (it reads the weights and the sums) nor
+  // the sort by (layer, Morton code) and the gather need this readback, so
+  // they are queued before the host waits for it: the side stream starts
+  // from here, and the main stream sorts while the host checks the input.
+  // The layer field of the keys is taken 6 bits wide (at most 64 layers); a
+  // key has at most 32 + 6 bits, which keeps the number of radix passes.
+  const bool csolve = p.model == 0 && !(p.c > 0.0);
+  hipStream_t scs = cx.side ? cx.side : st;
+  SideGuard cs_guard{cx};
+  StreamGuard early{st};
+  if (csolve) HIPCHK(fork_side(cx, st, cx.side != nullptr, cs_guard));
+  cx.mark("-", st);
+  early.armed = true;
+  HIPCHK(radix_sort(ar, keys, ids, n, g.bits + 6, st));
+  cx.mark("sort", st);
+  double* sw = ar.get<double>(n);
+  double* rec = ar.get<double>(n * (uint64_t)rec_stride(d, p.model));
+  uint32_t* smort = ar.get<uint32_t>(n);
+  uint8_t* slayer = ar.get<uint8_t>(n);
+  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, rec, smort, slayer, st));
+  cx.mark("gather", st);
   HIPCHK(rb.wait());
   if (p.model == 0) {
     if (!(red[4] > 0.0) || !std::isfinite(red[5]))
@@ -734,16 +788,12 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (g.count[i] > 0) g.L = i + 1;
   }
   g.lstart[kMaxLayers] = acc;
-  const int lbits = bitlen((uint64_t)(g.L > 0 ? g.L - 1 : 0));
 
   // constant c (App. B.2).  It needs only the heaviest weights (the tail,
   // sorted by value) and sums over the others, both from the unsorted
   // weights, so its first round runs on the side stream (with its own arena,
   // result slots and pinned buffers) while the main stream sorts and gathers.
   // Further rounds, when E_R needs a longer tail, run after the gather.
-  const bool csolve = p.model == 0 && !(p.c > 0.0);
-  hipStream_t scs = cx.side ? cx.side : st;
-  SideGuard cs_guard{cx};
   Readback rbs(cx, scs, true);
   CSolve cs;
   int i0 = g.L;
@@ -783,22 +833,9 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     // heaviest layers first, at least 1024 weights
     uint64_t tail = 0;
     while (i0 > 0 && tail < 1024) { --i0; tail += (uint64_t)g.count[i0]; }
-    HIPCHK(fork_side(cx, st, cx.side != nullptr, cs_guard));  // the weights are ready on st
-    girg_status s = cs_round();
+    girg_status s = cs_round();  // on the side stream, forked before the sort
     if (s != GIRG_OK) return s;
   }
-
-  // stable sort by (layer, Morton code); ties keep id order
-  cx.mark("-", st);
-  HIPCHK(radix_sort(ar, keys, ids, n, g.bits + lbits, st));
-  cx.mark("sort", st);
-  double* sw = ar.get<double>(n);
-  double* rec = ar.get<double>(n * (uint64_t)rec_stride(d, p.model));
-  uint32_t* smort = ar.get<uint32_t>(n);
-  uint8_t* slayer = ar.get<uint8_t>(n);
-  if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
-  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, rec, smort, slayer, st));
-  cx.mark("gather", st);
 
   cx.mark("-", st);
   if (p.model == 0) {
@@ -851,6 +888,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(rb.begin(kSmallReadback));
   HIPCHK(rb.add(&g, cx.gd, sizeof(Graph)));
   HIPCHK(rb.wait());
+  early.armed = false;  // the main stream has drained
 
   // prefix sums per layer at its insertion level
   uint64_t cells = 0;

@@ -109,7 +109,9 @@ __device__ __forceinline__ double hrg_coshd(const Rec<D, 1>& a, const Rec<D, 1>&
   return ch + 2.0 * a.v[3] * b.v[3] * s * s;
 }
 
-__device__ __forceinline__ double hrg_prob(const Graph* __restrict__ g, double coshd) {
+// (out of line: the distance filter below decides most pairs without it, and
+// inlined at every call site it made the type-II kernel spill registers)
+__device__ __noinline__ double hrg_prob(const Graph* __restrict__ g, double coshd) {
   return 1.0 / (exp((acosh(coshd) - g->R) * (0.5 * g->inv_T)) + 1.0);
 }
 
