@@ -441,24 +441,34 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
 }
 
 // one converged step over up to 64 queued Philox blocks
+// Lane l takes block bc + l.  The items whose blocks all lie below bc are
+// retired, so item qh holds block bc and every later item starts above it.
+// Items qh + 1 .. qh + 63 that start inside the window mark their first lane
+// (mk, one word per lane); a lane's item is the last mark at or below it.
 template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& v,
-                                      const QItem1* __restrict__ q, Ring1& r, const Stage& sg,
-                                      Out& out, uint64_t& ntests, uint64_t& nre) {
+                                      const QItem1* __restrict__ q, uint32_t* __restrict__ mk,
+                                      Ring1& r, const Stage& sg, Out& out, uint64_t& ntests,
+                                      uint64_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.bt - r.bc;
   const uint32_t take = avail < 64 ? avail : 64;
+  mk[lane] = 0u;
+  if (lane + 1 < r.qt - r.qh) {
+    const uint32_t off = q[(r.qh + lane + 1) & (kQCap - 1)].cs - r.bc;  // >= 1
+    if (off < take) mk[off] = lane + 1;
+  }
+  // the other lanes' marks: without the fence the compiler may return this
+  // lane's own zero from a register instead of reading the word back
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const uint32_t mv = mk[lane];
+  const uint64_t below = __ballot(mv != 0u) & (~0ull >> (63u - lane));
+  const uint32_t rel = __shfl(mv, below ? 63u - (uint32_t)__clzll((long long)below) : lane, 64);
   bool e0 = false, e1 = false;
   uint2 p0 = make_uint2(0, 0), p1 = make_uint2(0, 0);
   if (lane < take) {
     const uint32_t gb = r.bc + lane;
-    // last queued item whose first block is <= gb
-    uint32_t lo = r.qh, hi = r.qt;
-    while (hi - lo > 1) {
-      const uint32_t mid = lo + (hi - lo) / 2;
-      if (q[mid & (kQCap - 1)].cs <= gb) lo = mid; else hi = mid;
-    }
-    const QItem1 it = q[lo & (kQCap - 1)];
+    const QItem1 it = q[(r.qh + rel) & (kQCap - 1)];
     const uint64_t tot = it.tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
     const uint64_t kb = (uint64_t)it.kb + (gb - it.cs);
     const uint64_t kend = 2ull * ((uint64_t)it.kb + it.nbk) < tot ? 2ull * ((uint64_t)it.kb + it.nbk) : tot;
@@ -534,7 +544,8 @@ template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const Verts& v,
                                             const uint2* __restrict__ crec,
                                             const Src* __restrict__ src, IEnt1* ib, uint32_t& in,
-                                            QItem1* __restrict__ q, Ring1& r, uint32_t chunk,
+                                            QItem1* __restrict__ q, uint32_t* __restrict__ mk,
+                                            Ring1& r, uint32_t chunk,
                                             uint32_t& dseq, const DeferOut& dfo, const Stage& sg,
                                             Out& out, uint64_t& ntests, uint64_t& nre) {
   const uint32_t lane = lane_id();
@@ -549,7 +560,7 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
   in = rest;
   // room for 64 more items; consume blocks when there are several steps of them
   while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-    step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
+    step1<D, MODEL, T0, MX>(g, v, q, mk, r, sg, out, ntests, nre);
   bool enq = false, big = false;
   QItem1 it{};
   ItemRec rec{};
@@ -590,6 +601,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                DeferOut dfo) {
   __shared__ IEnt1 ibs[4][kICap];
   __shared__ QItem1 qs[4][kQCap];
+  __shared__ uint32_t mks[4][kWave];
   __shared__ uint2 ebs[4][kEdgeBuf];
   __shared__ SrcSlot sss[4][kWave];
   constexpr uint32_t NOFF = Offs<D>::n1;
@@ -597,6 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const uint32_t wv = threadIdx.x / kWave;
   IEnt1* ib = ibs[wv];
   QItem1* q = qs[wv];
+  uint32_t* mk = mks[wv];
   SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
   uint64_t ntests = 0, nre = 0, nedge = 0;
@@ -681,14 +694,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 IEnt1{sidx, Y, base + (uint32_t)__popcll(fm & ((1ull << j) - 1ull)), j};
           in += (uint32_t)__popcll(mb);
           if (in >= 64)
-            take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests,
+            take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, mk, r, c, dseq, dfo, sg, out, ntests,
                                           nre);
         }
       }
     }
     while (in)
-      take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, r, c, dseq, dfo, sg, out, ntests, nre);
-    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
+      take_items1<D, MODEL, T0, MX>(g, v, crec, src, ib, in, q, mk, r, c, dseq, dfo, sg, out, ntests, nre);
+    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, mk, r, sg, out, ntests, nre);
     end_chunk(sg, out, sc, c, dseq);
     nedge += out.off;
   }
@@ -708,9 +721,11 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
                                               const uint64_t* __restrict__ uoff, uint32_t nrec,
                                               Sched sc, Stage sg) {
   __shared__ QItem1 qs[4][kQCap];
+  __shared__ uint32_t mks[4][kWave];
   __shared__ uint2 ebs[4][kEdgeBuf];
   const uint32_t wv = threadIdx.x / kWave;
   QItem1* q = qs[wv];
+  uint32_t* mk = mks[wv];
   const uint32_t lane = lane_id();
   uint64_t ntests = 0, nre = 0, nedge = 0;
   for (;;) {
@@ -722,7 +737,7 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       while (r.qt - r.qh > (uint32_t)(kQCap - 64) || r.bt - r.bc >= 256)
-        step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
+        step1<D, MODEL, T0, MX>(g, v, q, mk, r, sg, out, ntests, nre);
       const uint64_t u = u0 + lane;
       bool enq = false;
       QItem1 it{};
@@ -745,7 +760,7 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
       }
       enqueue1(enq, it, q, r);
     }
-    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, r, sg, out, ntests, nre);
+    while (r.bc < r.bt) step1<D, MODEL, T0, MX>(g, v, q, mk, r, sg, out, ntests, nre);
     end_chunk(sg, out, sc, c, 0);
     nedge += out.off;
   }
