@@ -187,7 +187,7 @@ __device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, double w
 // type-I test: edge iff U < p_uv
 template <int D>
 __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double U, uint64_t& nre) {
+                                           uint32_t sv, double U, uint32_t& nre) {
   const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
   const double r = torus_r<D, 0>(a, b);
   float Lc, err;
@@ -203,7 +203,7 @@ __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Ve
 // type-II candidate: accepted iff Acc * pbar < p_uv (apb = Acc * pbar in FP64)
 template <int D>
 __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double apb, uint64_t& nre) {
+                                           uint32_t sv, double apb, uint32_t& nre) {
   const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
   const double r = torus_r<D, 0>(a, b);
   float Lc, err;
@@ -389,8 +389,8 @@ struct Ring1 {
 template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Verts& v,
                                            const QItem1& it, uint64_t k, uint64_t kend, bool& e0,
-                                           bool& e1, uint2& p0, uint2& p1, uint64_t& ntests,
-                                           uint64_t& nre) {
+                                           bool& e1, uint2& p0, uint2& p1, uint32_t& ntests,
+                                           uint32_t& nre) {
   const bool tri = it.tri != 0;
   uint32_t a, b;
   if (tri) {
@@ -448,8 +448,8 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
 template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& v,
                                       const QItem1* __restrict__ q, uint32_t* __restrict__ mk,
-                                      Ring1& r, const Stage& sg, Out& out, uint64_t& ntests,
-                                      uint64_t& nre) {
+                                      Ring1& r, const Stage& sg, Out& out, uint32_t& ntests,
+                                      uint32_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.bt - r.bc;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -547,7 +547,7 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
                                             QItem1* __restrict__ q, uint32_t* __restrict__ mk,
                                             Ring1& r, uint32_t chunk,
                                             uint32_t& dseq, const DeferOut& dfo, const Stage& sg,
-                                            Out& out, uint64_t& ntests, uint64_t& nre) {
+                                            Out& out, uint32_t& ntests, uint32_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t take = in < 64 ? in : 64;
   const bool have = lane < take;
@@ -612,7 +612,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   uint32_t* mk = mks[wv];
   SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0, nre = 0, nedge = 0;
+  uint32_t ntests = 0, nre = 0;
+  uint64_t nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -705,12 +706,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     end_chunk(sg, out, sc, c, dseq);
     nedge += out.off;
   }
-  ntests = wave_sum(ntests);
-  nre = wave_sum(nre);
+  // per-lane counts are 32-bit (a lane's share of one launch); the wave's sums 64-bit
+  const uint64_t stests = wave_sum((uint64_t)ntests), sre = wave_sum((uint64_t)nre);
   if (lane == 0) {
     if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
-    atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
-    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+    atomicAdd(&sg.stats[sc.pass], (unsigned long long)stests);  // tests of pass 0 / 1
+    if (sre) atomicAdd(&sg.stats[6], (unsigned long long)sre);
   }
 }
 
@@ -727,7 +728,8 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
   QItem1* q = qs[wv];
   uint32_t* mk = mks[wv];
   const uint32_t lane = lane_id();
-  uint64_t ntests = 0, nre = 0, nedge = 0;
+  uint32_t ntests = 0, nre = 0;
+  uint64_t nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -764,12 +766,12 @@ __global__ __launch_bounds__(256) void k_big1(const Graph* __restrict__ g, Verts
     end_chunk(sg, out, sc, c, 0);
     nedge += out.off;
   }
-  ntests = wave_sum(ntests);
-  nre = wave_sum(nre);
+  // per-lane counts are 32-bit (a lane's share of one launch); the wave's sums 64-bit
+  const uint64_t stests = wave_sum((uint64_t)ntests), sre = wave_sum((uint64_t)nre);
   if (lane == 0) {
     if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
-    atomicAdd(&sg.stats[sc.pass], (unsigned long long)ntests);  // tests of pass 0 / 1
-    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+    atomicAdd(&sg.stats[sc.pass], (unsigned long long)stests);  // tests of pass 0 / 1
+    if (sre) atomicAdd(&sg.stats[6], (unsigned long long)sre);
   }
 }
 
@@ -793,7 +795,7 @@ struct Ring2 {
 // otherwise from the FP64 quotient.
 template <bool MX>
 __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, const PB& pe,
-                                         bool& done, Cand& cd, uint64_t& nre) {
+                                         bool& done, Cand& cd, uint32_t& nre) {
   const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
   ++it.t;
   const uint64_t vv = (((uint64_t)o.y << 32) | o.x) >> 11;
@@ -858,7 +860,7 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Verts& v,
                                            const Cand* __restrict__ cq, Ring2& r, const Stage& sg,
-                                           Out& out, uint64_t& nre) {
+                                           Out& out, uint32_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t avail = r.ct - r.ch;
   const uint32_t take = avail < 64 ? avail : 64;
@@ -883,8 +885,8 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
                                        const Pbar* __restrict__ pbt,
                                        const QItem2* __restrict__ q, Cand* __restrict__ cq,
                                        Ring2& r, bool& act, QItem2& it, PB& pe, uint32_t need,
-                                       const Stage& sg, Out& out, uint64_t& ndraws,
-                                       uint64_t& ncand, uint64_t& nre) {
+                                       const Stage& sg, Out& out, uint32_t& ndraws,
+                                       uint32_t& ncand, uint32_t& nre) {
   const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
   for (;;) {
     const uint64_t mi = __ballot(!act);
@@ -950,7 +952,7 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
                                             Cand* __restrict__ cq, Ring2& r, bool& act,
                                             QItem2& cur, PB& cpe, uint32_t chunk, uint32_t& dseq,
                                             const DeferOut& dfo, const Stage& sg, Out& out,
-                                            uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
+                                            uint32_t& ndraws, uint32_t& ncand, uint32_t& nre) {
   const uint32_t lane = lane_id();
   const uint32_t take = in < 64 ? in : 64;
   const bool have = lane < take;
@@ -1031,7 +1033,7 @@ __device__ __forceinline__ void push_items2(uint64_t m, uint64_t fm, uint32_t ba
                                             Cand* __restrict__ cq, Ring2& r, bool& act,
                                             QItem2& cur, PB& cpe, uint32_t chunk, uint32_t& dseq,
                                             const DeferOut& dfo, const Stage& sg, Out& out,
-                                            uint64_t& ndraws, uint64_t& ncand, uint64_t& nre) {
+                                            uint32_t& ndraws, uint32_t& ncand, uint32_t& nre) {
   while (__any(m != 0)) {
     const bool has = m != 0;
     uint32_t j = 0;
@@ -1071,7 +1073,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   SrcSlot* ss = sss[wv];
   const uint32_t lane = lane_id();
   const uint32_t dstride = dtab[0];
-  uint64_t ndraws = 0, ncand = 0, nre = 0, nedge = 0;
+  uint32_t ndraws = 0, ncand = 0, nre = 0;
+  uint64_t nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -1165,15 +1168,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     end_chunk(sg, out, sc, c, dseq);
     nedge += out.off;
   }
-  ndraws = wave_sum(ndraws);
-  ncand = wave_sum(ncand);
-  nre = wave_sum(nre);
+  // per-lane counts are 32-bit (a lane's share of one launch); the wave's sums 64-bit
+  const uint64_t sdraws = wave_sum((uint64_t)ndraws), scand = wave_sum((uint64_t)ncand),
+                 sre = wave_sum((uint64_t)nre);
   if (lane == 0) {
     if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
-    atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
-    atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
-    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+    atomicAdd(&sg.stats[2 + sl], (unsigned long long)sdraws);
+    atomicAdd(&sg.stats[4 + sl], (unsigned long long)scand);
+    if (sre) atomicAdd(&sg.stats[6], (unsigned long long)sre);
   }
 }
 
@@ -1192,7 +1195,8 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
   Cand* cq = cqs[wv];
   const uint32_t lane = lane_id();
   const int L = g->L;
-  uint64_t ndraws = 0, ncand = 0, nre = 0, nedge = 0;
+  uint32_t ndraws = 0, ncand = 0, nre = 0;
+  uint64_t nedge = 0;
   for (;;) {
     const uint32_t c = next_chunk(sc.next);
     if (c >= sc.nchunks) break;
@@ -1235,15 +1239,15 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     end_chunk(sg, out, sc, c, 0);
     nedge += out.off;
   }
-  ndraws = wave_sum(ndraws);
-  ncand = wave_sum(ncand);
-  nre = wave_sum(nre);
+  // per-lane counts are 32-bit (a lane's share of one launch); the wave's sums 64-bit
+  const uint64_t sdraws = wave_sum((uint64_t)ndraws), scand = wave_sum((uint64_t)ncand),
+                 sre = wave_sum((uint64_t)nre);
   if (lane == 0) {
     if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);  // edges of the pass
     const int sl = sc.pass == 3 ? 1 : 0;  // draws / candidates of pass 2 / 3
-    atomicAdd(&sg.stats[2 + sl], (unsigned long long)ndraws);
-    atomicAdd(&sg.stats[4 + sl], (unsigned long long)ncand);
-    if (nre) atomicAdd(&sg.stats[6], (unsigned long long)nre);
+    atomicAdd(&sg.stats[2 + sl], (unsigned long long)sdraws);
+    atomicAdd(&sg.stats[4 + sl], (unsigned long long)scand);
+    if (sre) atomicAdd(&sg.stats[6], (unsigned long long)sre);
   }
 }
 
