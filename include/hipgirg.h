@@ -97,7 +97,12 @@ typedef struct {
 /* girg_generate: points (Sec. 2.1 weights and positions), constant c
  * (App. B.2) when avg_deg > 0, then the sampler of Sec. 3 (Algorithm 1 with
  * type-I tests and type-II geometric jumps).  edges: device pointer to
- * 2*cap uint32.  m_out: host pointer.  info: host pointer or NULL. */
+ * 2*cap uint32.  m_out: host pointer.  info: host pointer or NULL.
+ * The sampling passes defer long items to two lists of a first capacity of
+ * half an entry per source (at most 2^27); when one overflows, both passes
+ * run once more with the lists at their exact sizes (same result, more
+ * time).  The environment variable GIRG_DEFER_CAPACITY = 1..2^30, read at
+ * every call, sets that first capacity (e.g. to exercise the rerun). */
 girg_status girg_generate(const girg_params* p, uint32_t* edges, uint64_t cap, uint64_t* m_out,
                           girg_info* info, void* stream);
 

@@ -1007,8 +1007,15 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   Stage sg{stage, cap, cursor, rtag, roff, rpos, rcnt, nrec_d, rcap, cx.stats};
 
   // type-I and type-II passes (deferred lists grown once if too small)
-  uint32_t dcap[2] = {(uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024),
-                      (uint32_t)std::max<uint64_t>(1u << 16, nsrc / 8 + 1024)};
+  // first capacity: half an entry per source (the workloads measured defer up to
+  // about 0.1 per source and per list), at most 2^27; GIRG_DEFER_CAPACITY
+  // overrides it, e.g. to exercise the growth
+  uint64_t dcap0 = std::min<uint64_t>(std::max<uint64_t>(1u << 16, nsrc / 2 + 1024), 1ull << 27);
+  if (const char* ev = std::getenv("GIRG_DEFER_CAPACITY")) {
+    const long long v = std::atoll(ev);
+    if (v >= 1 && v <= (1ll << 30)) dcap0 = (uint64_t)v;
+  }
+  uint32_t dcap[2] = {(uint32_t)dcap0, (uint32_t)dcap0};
   ItemRec* drec[2] = {nullptr, nullptr};
   uint64_t* dkey[2] = {nullptr, nullptr};
   unsigned int dn[2] = {0, 0};
