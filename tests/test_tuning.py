@@ -27,6 +27,11 @@ def test_defaults(lib):
     assert lib.tuning_get(lib.make_params(2**20, 3, 2.5, 0.0, 10.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(2**22 - 1, 2, 2.7, 0.5, 16.0))[0] == 512
     assert lib.tuning_get(lib.make_params(2**22, 2, 2.7, 0.5, 16.0))[0] == 1024
+    assert lib.tuning_get(lib.make_params(2**21, 3, 2.3, 0.8, 20.0))[0] == 768
+    assert lib.tuning_get(lib.make_params(2**19, 4, 2.5, 0.5, 10.0))[0] == 768
+    assert lib.tuning_get(lib.make_params(2**18 - 1, 3, 2.5, 0.5, 16.0))[0] == 512
+    assert lib.tuning_get(lib.make_params(2**18, 3, 2.5, 0.5, 16.0))[0] == 768
+    assert lib.tuning_get(lib.make_params(2**22, 3, 2.3, 0.8, 20.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(10**7, 3, 2.3, 0.8, 20.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(10**4, 1, 2.5, 0.0, 10.0), batch=True) == (256, 16)
 
@@ -39,7 +44,7 @@ def test_set_get_by_class(lib):
     assert lib.tuning_get(lib.make_params(2**21 - 1, 2, 2.1, 0.9, 8.0))[0] == 2048
     assert lib.tuning_get(lib.make_params(2**21, 2, 2.7, 0.5, 16.0))[0] == 512
     assert lib.tuning_get(lib.make_params(2**20, 2, 2.7, 0.0, 16.0))[0] == 1024
-    assert lib.tuning_get(lib.make_params(2**20, 3, 2.7, 0.5, 16.0))[0] == 512
+    assert lib.tuning_get(lib.make_params(2**20, 3, 2.7, 0.5, 16.0))[0] == 768
     h = lib.make_params(2**20, 1, 0.0, 0.5, 10.0, model=1, alpha=0.75)
     assert lib.tuning_get(h)[0] == 512
     lib.tuning_set(h, 768)
