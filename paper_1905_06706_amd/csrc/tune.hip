@@ -1,8 +1,9 @@
 // tune.hip -- the tuning table of the persistent sampling grids (host code).
 // Defaults come from timed runs on MI355X: binomial graphs up to n = 2^22
 // finish sooner with 512 workgroups per pass at d <= 2 (type I and type II
-// share the GPU) and with 768 at d >= 3 from n = 2^18 on (more work per
-// source; at n = 2^17 512 was still 2 % faster), larger ones
+// share the GPU; 256 below n = 2^17, which drains sooner) and with 768 at
+// d >= 3 from n = 2^18 on (more work per source; at n = 2^17 512 was still
+// 2 % faster), larger ones
 // with 1024; threshold graphs (one pass) with 1024 from n = 2^17 on and 512
 // below (less dispatch and drain); the graphs of a batch with 256, since 16
 // instances share the GPU.  The
@@ -40,7 +41,11 @@ constexpr int kDefaultBatchWorkers = 16;
 // binomial graphs run two passes at once, so each takes fewer workgroups;
 // threshold graphs have no type-II pass and fill the GPU with one
 uint32_t default_single(const TuneKey& k) {
-  if (k.binomial) return k.log2n < 22 ? (k.d >= 3 && k.log2n >= 18 ? 768u : 512u) : 1024u;
+  if (k.binomial) {
+    if (k.log2n >= 22) return 1024u;
+    if (k.d >= 3) return k.log2n >= 18 ? 768u : 512u;
+    return k.log2n < 17 ? 256u : 512u;
+  }
   return k.log2n < 17 ? 512u : 1024u;
 }
 

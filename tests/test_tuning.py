@@ -31,6 +31,9 @@ def test_defaults(lib):
     assert lib.tuning_get(lib.make_params(2**19, 4, 2.5, 0.5, 10.0))[0] == 768
     assert lib.tuning_get(lib.make_params(2**18 - 1, 3, 2.5, 0.5, 16.0))[0] == 512
     assert lib.tuning_get(lib.make_params(2**18, 3, 2.5, 0.5, 16.0))[0] == 768
+    assert lib.tuning_get(lib.make_params(2**17 - 1, 2, 2.7, 0.5, 16.0))[0] == 256
+    assert lib.tuning_get(lib.make_params(2**17, 2, 2.7, 0.5, 16.0))[0] == 512
+    assert lib.tuning_get(lib.make_params(2**16, 3, 2.5, 0.5, 16.0))[0] == 512
     assert lib.tuning_get(lib.make_params(2**22, 3, 2.3, 0.8, 20.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(10**7, 3, 2.3, 0.8, 20.0))[0] == 1024
     assert lib.tuning_get(lib.make_params(10**4, 1, 2.5, 0.0, 10.0), batch=True) == (256, 16)
