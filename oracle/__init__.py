@@ -30,7 +30,7 @@ STAT_NAMES = {
     0: "W", 1: "w0", 2: "L", 3: "D", 4: "Dmax", 5: "nb_pairs", 6: "dist_pairs",
     7: "type1_items", 8: "type2_items", 9: "tests", 10: "draws", 11: "candidates",
     12: "edges", 13: "near", 14: "ties", 15: "segments", 16: "kappa_or_coshR",
-    17: "type1_edges", 18: "type2_edges",
+    17: "type1_edges", 18: "type2_edges", 19: "near_expect", 20: "tie_expect",
 }
 
 
@@ -61,56 +61,94 @@ class _Params(ctypes.Structure):
 _lib = None
 
 
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile an edited copy of the oracle's source (the mutation tests plant
+    mistakes in such copies to show that the pins catch them) with the same
+    flags into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call([
+        "gcc", "-O2", "-std=c11", "-w", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+        "-shared", "-I", _HERE, "-o", out_path, src, "-lm",
+    ])
+    return out_path
+
+
+class use_library:
+    """Context manager: every function of this module calls the library at
+    `path` (a variant from build_variant) until the block ends."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = None
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        path = _LIB if os.path.exists(_LIB) else build()
-        L = ctypes.CDLL(path)
-        P = ctypes.POINTER
-        u32p, u64p, dblp = P(ctypes.c_uint32), P(ctypes.c_uint64), P(ctypes.c_double)
-        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_u53.restype = ctypes.c_double
-        L.orc_u53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
-        L.orc_u53_open.restype = ctypes.c_double
-        L.orc_u53_open.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
-        L.orc_morton_encode.restype = ctypes.c_uint64
-        L.orc_morton_encode.argtypes = [u32p, ctypes.c_int, ctypes.c_int]
-        L.orc_morton_decode.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, u32p]
-        L.orc_points_girg.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
-                                      ctypes.c_uint64, dblp, dblp]
-        L.orc_points_hrg.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_uint64, dblp, dblp]
-        L.orc_expected_avg_degree.restype = ctypes.c_double
-        L.orc_expected_avg_degree.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
-                                              ctypes.c_double, dblp]
-        L.orc_solve_c.restype = ctypes.c_int
-        L.orc_solve_c.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_double, dblp, dblp]
-        L.orc_hrg_expected_avg_degree.restype = ctypes.c_double
-        L.orc_hrg_expected_avg_degree.argtypes = [ctypes.c_uint64, ctypes.c_double,
-                                                  ctypes.c_double, ctypes.c_double]
-        L.orc_hrg_solve_R.restype = ctypes.c_int
-        L.orc_hrg_solve_R.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, dblp]
-        L.orc_run_graph.restype = ctypes.c_void_p
-        L.orc_run_graph.argtypes = [P(_Params), dblp, dblp]
-        L.orc_last_error.restype = ctypes.c_char_p
-        L.orc_free.argtypes = [ctypes.c_void_p]
-        for name in ("orc_num_edges", "orc_num_near", "orc_num_ties"):
-            getattr(L, name).restype = ctypes.c_uint64
-            getattr(L, name).argtypes = [ctypes.c_void_p]
-        L.orc_copy_edges.argtypes = [ctypes.c_void_p, u32p]
-        L.orc_copy_near.argtypes = [ctypes.c_void_p, u32p]
-        L.orc_copy_ties.argtypes = [ctypes.c_void_p, u64p]
-        L.orc_copy_sorted_ids.argtypes = [ctypes.c_void_p, u32p]
-        L.orc_stats.argtypes = [ctypes.c_void_p, dblp]
-        L.orc_tables.argtypes = [ctypes.c_void_p, P(ctypes.c_int32), P(ctypes.c_int32),
-                                 P(ctypes.c_int64), dblp]
-        L.orc_pair_item.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
-                                    P(ctypes.c_int64)]
-        L.orc_level_counts.argtypes = [ctypes.c_void_p, u64p, u64p]
-        _lib = L
+        _lib = _load(_LIB if os.path.exists(_LIB) else build())
     return _lib
+
+
+def _load(path: str) -> ctypes.CDLL:
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    u32p, u64p, dblp = P(ctypes.c_uint32), P(ctypes.c_uint64), P(ctypes.c_double)
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_u53.restype = ctypes.c_double
+    L.orc_u53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    L.orc_u53_open.restype = ctypes.c_double
+    L.orc_u53_open.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    L.orc_morton_encode.restype = ctypes.c_uint64
+    L.orc_morton_encode.argtypes = [u32p, ctypes.c_int, ctypes.c_int]
+    L.orc_morton_decode.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, u32p]
+    L.orc_points_girg.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_uint64, dblp, dblp]
+    L.orc_points_hrg.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_uint64, dblp, dblp]
+    L.orc_expected_avg_degree.restype = ctypes.c_double
+    L.orc_expected_avg_degree.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, dblp]
+    L.orc_solve_c.restype = ctypes.c_int
+    L.orc_solve_c.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, dblp, dblp]
+    L.orc_hrg_expected_avg_degree.restype = ctypes.c_double
+    L.orc_hrg_expected_avg_degree.argtypes = [ctypes.c_uint64, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double]
+    L.orc_hrg_solve_R.restype = ctypes.c_int
+    L.orc_hrg_solve_R.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, dblp]
+    L.orc_run_graph.restype = ctypes.c_void_p
+    L.orc_run_graph.argtypes = [P(_Params), dblp, dblp]
+    L.orc_last_error.restype = ctypes.c_char_p
+    L.orc_free.argtypes = [ctypes.c_void_p]
+    for name in ("orc_num_edges", "orc_num_near", "orc_num_ties"):
+        getattr(L, name).restype = ctypes.c_uint64
+        getattr(L, name).argtypes = [ctypes.c_void_p]
+    L.orc_copy_edges.argtypes = [ctypes.c_void_p, u32p]
+    L.orc_copy_near.argtypes = [ctypes.c_void_p, u32p]
+    L.orc_copy_ties.argtypes = [ctypes.c_void_p, u64p]
+    L.orc_copy_sorted_ids.argtypes = [ctypes.c_void_p, u32p]
+    L.orc_stats.argtypes = [ctypes.c_void_p, dblp]
+    L.orc_tables.argtypes = [ctypes.c_void_p, P(ctypes.c_int32), P(ctypes.c_int32),
+                             P(ctypes.c_int64), dblp]
+    L.orc_pair_item.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                P(ctypes.c_int64)]
+    L.orc_level_counts.argtypes = [ctypes.c_void_p, u64p, u64p]
+    L.orc_edge_keys.argtypes = [ctypes.c_void_p, u32p, ctypes.c_uint64, P(ctypes.c_int64)]
+    return L
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -222,6 +260,18 @@ class Run:
         for k, (u, v) in enumerate(pairs):
             L.orc_pair_item(self._handle, int(u), int(v), buf)
             out[k] = np.frombuffer(buf, dtype=np.int64)
+        return out
+
+    def edge_keys(self, edges: np.ndarray) -> np.ndarray:
+        """(m, 8) int64 per edge (u, v): level, A, B, i, j, k, type and a
+        flag set when the edge is not written with u from the A side."""
+        e = np.ascontiguousarray(np.asarray(edges).reshape(-1, 2).view(np.uint32)
+                                 if np.asarray(edges).dtype != np.uint32
+                                 else np.asarray(edges).reshape(-1, 2))
+        out = np.zeros((len(e), 8), dtype=np.int64)
+        if len(e):
+            assert self._handle, "run(..., keep=True) is needed for edge keys"
+            lib().orc_edge_keys(self._handle, _ptr(e, ctypes.c_uint32), len(e), _ptr(out, ctypes.c_int64))
         return out
 
     def close(self):

@@ -496,6 +496,10 @@ struct orc_run {
   vec32 edges, near;
   vec64 ties;
   uint64_t ctr[ORC_NSTATS];
+  /* expected numbers of logged near decisions and skip ties over the random
+   * draws of this run, given the points: the bounds the parity tests put on
+   * the logged counts */
+  double near_expect, tie_expect;
   uint64_t lvl_nb[40], lvl_dist[40]; /* visited cell pairs per level */
   int failed;
 };
@@ -597,6 +601,15 @@ static void near_pair(orc_run* R, uint32_t u, uint32_t v) {
   R->ctr[S_NEAR]++;
 }
 
+/* Probability that a uniform on [0,1) lies within 1e-12 of q in [0,1]: the
+ * chance that a coin compared with q is logged as near. */
+static double near_mass(double q) {
+  double lo = q - 1e-12, hi = q + 1e-12;
+  if (lo < 0.0) lo = 0.0;
+  if (hi > 1.0) hi = 1.0;
+  return hi > lo ? hi - lo : 0.0;
+}
+
 static void type1_pair(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j, uint64_t su,
                        uint64_t sv, uint64_t k) {
   const orc_params* p = &R->p;
@@ -610,6 +623,8 @@ static void type1_pair(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j, 
     /* threshold variant: edge iff ||x_u - x_v|| <= c (w_u w_v / W)^{1/d} */
     double t = p->c * pow(R->sw[su] * R->sw[sv] / R->W, 1.0 / p->d);
     if (fabs(r - t) <= 1e-12 * t) near_pair(R, u, v);
+    /* r / t has a density of order one near 1 over the tested pairs */
+    R->near_expect += 2e-12;
     if (r <= t) emit(R, u, v, 0);
     return;
   }
@@ -617,6 +632,7 @@ static void type1_pair(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j, 
     /* threshold HRG: edge iff d < R, i.e. cosh d < cosh R (Sec. 4.3) */
     double ch = hrg_coshd(R->sw[su], R->sw[sv], r);
     if (fabs(ch - R->coshR) <= 1e-12 * R->coshR) near_pair(R, u, v);
+    R->near_expect += 2e-12;
     if (ch < R->coshR) emit(R, u, v, 0);
     return;
   }
@@ -629,6 +645,7 @@ static void type1_pair(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j, 
   int h = (int)(k & 1);
   double U = orc_u53(o[2 * h], o[2 * h + 1]);
   if (fabs(U - prob) < 1e-12) near_pair(R, u, v);
+  R->near_expect += near_mass(prob);
   if (U < prob) emit(R, u, v, 0);
 }
 
@@ -658,19 +675,37 @@ static void type1(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
  * weights of the layers and the minimum distance g 2^-l between points of the
  * two cells (GIRG); for the HRG the smallest radii of the layers and the same
  * minimum angular distance. */
-static double type2_pbar(const orc_run* R, int l, int i, int j, int g) {
+static double type2_pbar(const orc_run* R, int l, int i, int j, int g, double* raw) {
   const orc_params* p = &R->p;
-  if (p->accept_all) return 1.0;
+  if (p->accept_all) { *raw = 2.0; return 1.0; }
   double dist = ldexp((double)g, -l);
   if (p->model == 0) {
     double dd = dist;
     for (int k = 1; k < p->d; k++) dd *= dist;
     double pb = p->c * pow((R->ext[i] * R->ext[j] / R->W) / dd, 1.0 / p->T);
+    *raw = pb; /* before the clamp to 1 */
     return pb < 1.0 ? pb : 1.0;
   }
   double s = sin(M_PI * dist);
   double ch = 1.0 + 2.0 * sinh(R->ext[i]) * sinh(R->ext[j]) * s * s;
-  return hrg_pT(R, ch);
+  *raw = hrg_pT(R, ch);
+  return *raw;
+}
+
+/* Chance that the skip quotient q of one draw, q ~ Exp(lambda) with
+ * lambda = -ln(1 - pbar), falls within 1e-12 q of an integer j in 1..K, the
+ * candidates still in range: about sum_j 2e-12 j lambda e^{-lambda j}
+ * = 2e-12 lambda sum_j j r^j with r = 1 - pbar (closed form of the sum). */
+static double tie_mass(double pbar, double lambda, double K) {
+  if (!(K >= 1.0) || !(pbar > 0.0) || pbar >= 1.0) return 0.0;
+  double u = K * lambda, S;
+  if (u < 1e-6) {
+    S = 0.5 * K * (K + 1.0);
+  } else {
+    double r = 1.0 - pbar, rK = exp(-u);
+    S = r * (1.0 - rK * (1.0 + K * pbar)) / (pbar * pbar);
+  }
+  return 2e-12 * lambda * S;
 }
 
 static int near_pow2(double x) {
@@ -691,7 +726,8 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
   int g = 0;
   for (int k = 0; k < p->d; k++)
     if ((int)delta[k] - 1 > g) g = (int)delta[k] - 1;
-  double pbar = type2_pbar(R, l, i, j, g);
+  double pbar_raw;
+  double pbar = type2_pbar(R, l, i, j, g, &pbar_raw);
   if (!(pbar > 0.0)) return;
   double Lg = log1p(-pbar);
   uint64_t N = na * nb;
@@ -703,7 +739,10 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
   if (e < emin) e = emin;
   uint64_t G = (e >= 63 || ((uint64_t)1 << e) >= N) ? N : ((uint64_t)1 << e);
   uint64_t nseg = (N + G - 1) / G;
-  int tie = near_pow2(pbar) && e > emin;
+  /* a bound within a few ulps of a power of two (before the clamp to 1, which
+   * makes 1 exact) may fall on either side of it under another pow, and
+   * change the segment size: log the item */
+  int tie = near_pow2(pbar_raw) && e > emin;
   for (uint64_t s = 0; s < nseg; s++) {
     uint64_t k = s * G, kend = (s + 1) * G < N ? (s + 1) * G : N;
     R->ctr[S_SEGS]++;
@@ -721,6 +760,7 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
        * when it decides a candidate or the end of the segment: log the item */
       double fl = floor(q + 0.5);
       if (pbar < 1.0 && fl >= 1.0 && fabs(q - fl) < 1e-12 * q && q < (double)(kend - k) + 1.0) tie = 1;
+      R->tie_expect += tie_mass(pbar, -Lg, (double)(kend - k));
       if (q >= (double)(kend - k)) break;
       k += (uint64_t)q;
       uint64_t a = k / nb, b = k % nb;
@@ -733,9 +773,12 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
         double r = torus_dist(R->sx + su * (uint64_t)p->d, R->sx + sv * (uint64_t)p->d, p->d);
         double prob = p->model == 0 ? girg_p(R, R->sw[su], R->sw[sv], r)
                                     : hrg_pT(R, hrg_coshd(R->sw[su], R->sw[sv], r));
-        double lhs = Acc * pbar;
-        if (fabs(lhs - prob) < 1e-12) near_pair(R, u, v);
-        if (lhs < prob) emit(R, u, v, 1);
+        /* the candidate is accepted with probability p_uv / pbar: the
+         * coin Acc is near when it lies within 1e-12 of that ratio */
+        double ratio = prob / pbar;
+        if (fabs(Acc - ratio) < 1e-12) near_pair(R, u, v);
+        R->near_expect += near_mass(ratio);
+        if (Acc * pbar < prob) emit(R, u, v, 1);
       }
       k += 1;
       if (k >= kend) break;
@@ -965,6 +1008,8 @@ void orc_stats(const orc_run* r, double* out) {
   for (int k = 0; k < ORC_NSTATS; k++) out[k] = (double)r->ctr[k];
   out[0] = r->W; out[1] = r->w0; out[2] = r->L; out[3] = r->D; out[4] = r->Dmax;
   out[16] = r->p.model == 0 ? r->kappa : r->coshR;
+  out[19] = r->near_expect;
+  out[20] = r->tie_expect;
 }
 
 void orc_level_counts(const orc_run* r, uint64_t* nb, uint64_t* dist) {
@@ -1004,4 +1049,31 @@ void orc_pair_item(const orc_run* r, uint32_t u, uint32_t v, int64_t* out) {
   out[4] = swapped ? i : j;
   out[5] = type;
   out[6] = swapped;
+}
+
+/* The key of an edge in the canonical order of the cell-pair iteration: the
+ * item (level, A, B, i, j) that holds the pair, with A <= B and the ordered
+ * layer pair of App. B.1, and the pair index k inside it (a |V_j^B| + b, or
+ * b (b - 1) / 2 + a with a < b when A = B and i = j, a and b counted from
+ * the first sorted positions of V_i^A and V_j^B).  out8[7] = 1 when the edge
+ * is written (B side, A side), i.e. not with u from the A side. */
+void orc_edge_keys(const orc_run* r, const uint32_t* edges, uint64_t m, int64_t* out8) {
+  for (uint64_t e = 0; e < m; e++) {
+    uint32_t u = edges[2 * e], v = edges[2 * e + 1];
+    int64_t it[7];
+    orc_pair_item(r, u, v, it);
+    int level = (int)it[0], i = (int)it[3], j = (int)it[4];
+    uint64_t A = (uint64_t)it[1], B = (uint64_t)it[2];
+    int swapped = (int)it[6];
+    uint64_t su = r->spos[swapped ? v : u], sv = r->spos[swapped ? u : v];
+    uint64_t a0, na, b0, nb;
+    vertex_range(r, i, level, A, &a0, &na);
+    vertex_range(r, j, level, B, &b0, &nb);
+    uint64_t a = su - a0, b = sv - b0, k;
+    if (A == B && i == j) k = b * (b - 1) / 2 + a; /* here a < b */
+    else k = a * nb + b;
+    int64_t* o = out8 + 8 * e;
+    o[0] = level; o[1] = (int64_t)A; o[2] = (int64_t)B; o[3] = i; o[4] = j;
+    o[5] = (int64_t)k; o[6] = it[5]; o[7] = swapped;
+  }
 }

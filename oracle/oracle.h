@@ -90,7 +90,9 @@ void orc_copy_sorted_ids(const orc_run* run, uint32_t* out); /* n */
 /* stats: 0 W, 1 w0 (GIRG) / unused, 2 L, 3 D, 4 Dmax, 5 neighbour cell pairs,
  * 6 distant cell pairs, 7 type-I items, 8 type-II items, 9 tests, 10 draws,
  * 11 candidates, 12 edges, 13 near, 14 ties, 15 segments, 16 kappa / coshR,
- * 17 type-I edges, 18 type-II edges */
+ * 17 type-I edges, 18 type-II edges, 19 expected near count, 20 expected
+ * skip-tie count (sums over the decisions and draws of the run of the chance
+ * that each is logged, given the points) */
 void orc_stats(const orc_run* run, double* out);
 /* CL (64*64, -1 where a layer is empty), I (64), layer sizes (64),
  * per-layer max weight (GIRG) or min radius (HRG) (64). */
@@ -99,6 +101,10 @@ void orc_tables(const orc_run* run, int32_t* CL, int32_t* I, int64_t* count, dou
  * at that level), i, j, type (0 = type-I, 1 = type-II) and swapped (1 if the
  * item holds the pair as (v,u)). */
 void orc_pair_item(const orc_run* run, uint32_t u, uint32_t v, int64_t* out7);
+/* For m edges (u, v): level, A, B, i, j, k (the pair index inside the item),
+ * type and a flag that is 1 when the edge is not written with u from the A
+ * side (App. B.1); out has 8 entries per edge. */
+void orc_edge_keys(const orc_run* run, const uint32_t* edges, uint64_t m, int64_t* out8);
 /* visited cell pairs (neighbouring, distant) per level 0..39 */
 void orc_level_counts(const orc_run* run, uint64_t* nb, uint64_t* dist);
 

@@ -1,8 +1,21 @@
-"""Comparison helpers for GPU-vs-oracle parity: edge sets must be equal except
-for pairs the oracle logged as near the decision boundary (|U - p| < 1e-12,
-or a relative threshold margin below 1e-12) and pairs of type-II items whose
-skip length had a tie; both counts are reported."""
+"""Comparison helpers for GPU-vs-oracle parity.
+
+The edge arrays must agree except for pairs the oracle logged as near the
+decision boundary (|U - p| < 1e-12 for a coin U against a probability p; the
+acceptance coin of a type-II candidate against p_uv / pbar; a relative
+threshold margin below 1e-12 for the threshold variants) and the pairs of
+type-II items whose skip quotient fell within 1e-12 (relative) of an integer.
+Both counts are bounded by what the random draws of the run make likely (the
+oracle sums, over its decisions and draws, the chance of each being logged).
+
+Orientation and order: every edge must be written (A side, B side) as the
+item (level, A, B, i, j) that holds it orders its cells (App. B.1: A <= B, the
+layer pair ordered accordingly, a < b inside a cell of one layer), and after
+sorting both arrays by the canonical key (level, A, B, i, j, k) the two must be
+equal element by element."""
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -34,19 +47,52 @@ def in_tie_items(keys: np.ndarray, run) -> np.ndarray:
     return inside
 
 
-def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0) -> dict:
-    g = pair_keys(gpu_edges)
+def count_bound(expect: float) -> int:
+    """Largest count of a Poisson(expect) variable that is not suspicious:
+    expect + 6 sqrt(expect) + 3 (for expect << 1, a count above 3 has
+    probability below expect^4 / 24)."""
+    return int(math.floor(expect + 6.0 * math.sqrt(max(expect, 0.0)) + 3.0))
+
+
+def canonical_order(edges: np.ndarray, run) -> tuple:
+    """(edges sorted by the canonical key (level, A, B, i, j, k), their keys)."""
+    e = np.ascontiguousarray(np.asarray(edges).reshape(-1, 2)).view(np.uint32)
+    keys = run.edge_keys(e)
+    order = np.lexsort((keys[:, 5], keys[:, 4], keys[:, 3], keys[:, 2], keys[:, 1], keys[:, 0]))
+    return e[order], keys[order]
+
+
+def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0, oriented: bool = True) -> dict:
+    ge = np.ascontiguousarray(np.asarray(gpu_edges).reshape(-1, 2)).view(np.uint32)
+    g = pair_keys(ge)
     o = pair_keys(run.edges)
     assert len(np.unique(g)) == len(g), "GPU output holds a pair twice"
-    e = np.asarray(gpu_edges).reshape(-1, 2)
-    assert np.all(e[:, 0] != e[:, 1]), "GPU output holds a self-loop"
+    assert np.all(ge[:, 0] != ge[:, 1]), "GPU output holds a self-loop"
     only_g = np.setdiff1d(g, o)
     only_o = np.setdiff1d(o, g)
     diff = np.union1d(only_g, only_o)
-    if len(run.near):
-        diff = np.setdiff1d(diff, pair_keys(run.near))
+    near_keys = pair_keys(run.near) if len(run.near) else np.zeros(0, dtype=np.uint64)
+    if len(near_keys):
+        diff = np.setdiff1d(diff, near_keys)
     bad = diff[~in_tie_items(diff, run)]
     rep = {"gpu": len(g), "oracle": len(o), "only_gpu": len(only_g), "only_oracle": len(only_o),
-           "near": len(run.near), "ties": len(run.ties), "unexplained": len(bad)}
+           "near": len(run.near), "ties": len(run.ties),
+           "near_expect": float(run.stats.get("near_expect", 0.0)),
+           "tie_expect": float(run.stats.get("tie_expect", 0.0)), "unexplained": len(bad)}
     assert len(bad) <= allow_extra, f"edge sets differ outside the near-boundary pairs: {rep}"
+    assert rep["near"] <= count_bound(rep["near_expect"]), f"too many near-boundary decisions: {rep}"
+    assert rep["ties"] <= count_bound(rep["tie_expect"]), f"too many skip ties: {rep}"
+    if oriented and allow_extra == 0:
+        # drop the excluded pairs from both sides, then compare (u, v) element
+        # by element in the canonical order
+        excl = np.union1d(near_keys, np.union1d(g[in_tie_items(g, run)], o[in_tie_items(o, run)]))
+        gk = ge[~np.isin(g, excl)]
+        ok = np.ascontiguousarray(run.edges)[~np.isin(o, excl)]
+        gs, gkey = canonical_order(gk, run)
+        os_, okey = canonical_order(ok, run)
+        assert not gkey[:, 7].any(), "a GPU edge is not written with u from the A side of its item"
+        assert not okey[:, 7].any(), "an oracle edge is not written with u from the A side"
+        assert np.array_equal(gkey[:, :6], okey[:, :6]), "canonical keys differ"
+        assert np.array_equal(gs, os_), "oriented edges differ in the canonical order"
+        rep["oriented"] = len(gs)
     return rep

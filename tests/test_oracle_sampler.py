@@ -330,3 +330,26 @@ def test_coincident_points_give_the_complete_graph(orc, T, d):
     assert len(e) == n * (n - 1) // 2
     assert len(np.unique(e[:, 0] * n + e[:, 1])) == n * (n - 1) // 2
     assert run.stats["type1_items"] == 1 and run.stats["type2_items"] == 0
+
+
+@pytest.mark.parametrize("bias", [-2, 1])
+def test_binomial_edge_count_variance(orc, bias):
+    """Edges are independent given the points (Sec. 2.1): over seeds, the
+    number of edges has variance sum p_uv (1 - p_uv).  Coins shared between
+    pairs (a Philox word used twice, a jump sequence reused) correlate pairs
+    and inflate it; the mean stays sum p_uv.  cl_bias = -2 leaves nearly
+    every pair to type-I tests, cl_bias = 1 most of them to type-II items."""
+    n, d, T = 300, 2, 0.6
+    w = synth.pareto_weights(n, 2.4, 19)
+    x = synth.positions(n, d, 19)
+    c = orc.solve_c(w, d, T, 12.0)
+    p = girg_p_numpy(w, x, c, T)
+    iu = np.triu_indices(n, 1)
+    mu, var = p[iu].sum(), (p[iu] * (1 - p[iu])).sum()
+    S = 1500
+    ms = np.array([len(orc.run(w, x, T=T, c=c, seed=20000 + s, cl_bias=bias).edges) for s in range(S)],
+                  dtype=float)
+    assert abs(ms.mean() - mu) < 4.5 * np.sqrt(var / S)
+    ratio = ms.var(ddof=1) / var
+    lo, hi = stats.chi2.ppf([1e-5, 1 - 1e-5], S - 1) / (S - 1)
+    assert lo < ratio < hi, ratio
