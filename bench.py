@@ -23,36 +23,47 @@ if ROOT not in sys.path:
 
 METRIC = "edges/sec on 1 MI355X (+% HBM peak), mixed vs plain FP64, at oracle match"
 
-# name: (description, generate kwargs)
+# name: (description, generate kwargs).  Binomial GIRG workloads (and the
+# batch) run two legs, plain FP64 and the FP32 filter with FP64 recheck; the
+# others run FP64 only (the filter applies to binomial GIRGs).
 WORKLOADS = {
-    "girg_d1_n1e4": ("GIRG d=1 n=10^4 beta=2.5 T=0 avg_deg=10 seed=1 FP64",
-                     dict(model=0, n=10**4, d=1, beta=2.5, T=0.0, avg_deg=10.0, seed=1, precision=0)),
-    "girg_d2_n2p20": ("GIRG d=2 n=2^20 beta=2.7 T=0.5 avg_deg=16 seed=2 FP64",
-                      dict(model=0, n=2**20, d=2, beta=2.7, T=0.5, avg_deg=16.0, seed=2, precision=0)),
-    "hrg_n2p20": ("HRG n=2^20 alpha=0.75 T=0.5 avg_deg=10 (R solved) seed=3 FP64",
-                  dict(model=1, n=2**20, d=1, alpha=0.75, T=0.5, avg_deg=10.0, seed=3, precision=0)),
-    "girg_d3_n1e7": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4 FP64",
-                     dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=0)),
-    "girg_d3_n1e7_mixed": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4 FP32 filter + FP64 recheck",
-                           dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4, precision=1)),
+    "girg_d3_n1e7": ("GIRG d=3 n=10^7 beta=2.3 T=0.8 avg_deg=20 seed=4",
+                     dict(model=0, n=10**7, d=3, beta=2.3, T=0.8, avg_deg=20.0, seed=4)),
+    "girg_d2_n2p20": ("GIRG d=2 n=2^20 beta=2.7 T=0.5 avg_deg=16 seed=2",
+                      dict(model=0, n=2**20, d=2, beta=2.7, T=0.5, avg_deg=16.0, seed=2)),
+    "hrg_n2p20": ("HRG n=2^20 alpha=0.75 T=0.5 avg_deg=10 (R solved) seed=3",
+                  dict(model=1, n=2**20, d=1, alpha=0.75, T=0.5, avg_deg=10.0, seed=3)),
+    "girg_d1_n1e4": ("GIRG d=1 n=10^4 beta=2.5 T=0 avg_deg=10 seed=1",
+                     dict(model=0, n=10**4, d=1, beta=2.5, T=0.0, avg_deg=10.0, seed=1)),
     "girg_batch256": ("256 GIRGs, n=round(10^(3+3U)), d in {1,2}, beta~U[2.1,3], T in {0,0.3,0.9}, "
-                      "avg_deg~U[8,32], seed 1000+b (numpy default_rng(5)) FP64",
-                      dict(model=0, batch=256, master_seed=5, precision=0)),
-    "girg_batch256_mixed": ("the same 256 GIRGs, FP32 filter + FP64 recheck",
-                            dict(model=0, batch=256, master_seed=5, precision=1)),
+                      "avg_deg~U[8,32], seed 1000+b (numpy default_rng(5))",
+                      dict(model=0, batch=256, master_seed=5)),
 }
-DEFAULT = "girg_d2_n2p20"
+DEFAULT = "girg_d3_n1e7"
+LEG_NAMES = {0: "fp64", 1: "mixed"}
+
+
+def legs_of(wl: dict) -> list:
+    """Precisions the workload runs: FP64, and the FP32 filter with FP64
+    recheck where it applies (binomial GIRGs; the batch, whose threshold
+    instances take the FP64 path either way)."""
+    if "batch" in wl:
+        return [0, 1]
+    return [0, 1] if wl["model"] == 0 and wl["T"] > 0.0 else [0]
+
 
 # Peak figures (MI355X): HBM3E 8 TB/s; VALU 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-operations per second, in T
 
-# algorithmic VALU lane-operations per unit of work (estimates from the
-# operation counts of each decision; the counters show the issued totals)
-OPS_TEST_T0 = 15.0      # threshold test: torus distance, product, compare
-OPS_TEST_BINOM = 120.0  # binomial test: distance, pow (log + exp), half a Philox block, compare
-OPS_DRAW = 80.0         # geometric draw: one Philox block, one log, divide, compare
-OPS_CAND = 70.0         # candidate: distance, pow, compare
+# algorithmic VALU lane-operations per unit of work: the VALU instructions of
+# each decision's arithmetic in the gfx950 build of the library's own device
+# functions (d = 3; tests/test_opcount.py counts them in the assembly and
+# keeps these figures within 10 % of the build)
+OPS_TEST_T0 = 23.0      # threshold test: torus distance, r^d W <= kappa w_u w_v
+OPS_TEST_BINOM = 175.0  # binomial test: distance, p_uv (FP64 log and exp series), half a Philox block, compare
+OPS_DRAW = 149.0        # geometric draw: one Philox block, FP64 log series, skip quotient, end test
+OPS_CAND = 140.0        # candidate: distance, p_uv, compare
 
 
 # sources of the sampling kernels: HBM byte counters in profiles/ hold for
@@ -88,7 +99,7 @@ def profiled_traffic(workload: str, stage: str):
     return None
 
 
-def batch_params(hg, wl: dict) -> list:
+def batch_params(hg, wl: dict, precision: int) -> list:
     """The batch recipe: per instance n = round(10^(3+3U)), d uniform in {1, 2},
     beta ~ U[2.1, 3.0], T uniform in {0, 0.3, 0.9}, average degree ~ U[8, 32],
     seed 1000 + b; parameters drawn from numpy's default_rng(master_seed)."""
@@ -101,14 +112,14 @@ def batch_params(hg, wl: dict) -> list:
         beta = float(rng.uniform(2.1, 3.0))
         T = float(rng.choice([0.0, 0.3, 0.9]))
         deg = float(rng.uniform(8.0, 32.0))
-        out.append(hg.make_params(n, d, beta, T, deg, 0.0, 1000 + b, wl["precision"]))
+        out.append(hg.make_params(n, d, beta, T, deg, 0.0, 1000 + b, precision))
     return out
 
 
-def make_call(hg, wl: dict):
+def make_call(hg, wl: dict, precision: int):
     L = hg.load()
     if "batch" in wl:
-        params = batch_params(hg, wl)
+        params = batch_params(hg, wl, precision)
         cnt = len(params)
         arr = (hg.Params * cnt)(*params)
         offs = (ctypes.c_uint64 * (cnt + 1))()
@@ -118,7 +129,8 @@ def make_call(hg, wl: dict):
             st = L.girg_generate_batch(arr, cnt, buf, cap, offs, infos, stream)
             m._obj.value = offs[cnt]
             # totals of the batch in `info`
-            tot = {k: 0 for k in ("tests", "draws", "candidates", "rechecks", "type1_edges", "type2_edges")}
+            tot = {k: 0 for k in ("tests", "draws", "candidates", "rechecks", "type1_edges", "type2_edges",
+                                  "near_boundary", "skip_ties")}
             for i in infos:
                 for k in tot:
                     tot[k] += getattr(i, k)
@@ -140,8 +152,7 @@ def make_call(hg, wl: dict):
         call.params = hg.make_params(wl["n"], 1, 0.0, wl["T"], wl["avg_deg"], 0.0, wl["seed"], model=1,
                                      alpha=wl["alpha"])
         return call
-    p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"],
-                       wl["precision"])
+    p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"], precision)
 
     def call(buf, cap, m, info, stream):
         return L.girg_generate(ctypes.byref(p), buf, cap, m, info, stream)
@@ -149,36 +160,72 @@ def make_call(hg, wl: dict):
     return call
 
 
-def cpu_baseline(wl: dict) -> dict:
-    """The oracle as it stands, single-threaded, on one full graph of the
-    workload (points, constant and sampling), when that is about 10-30 s of
-    CPU work; otherwise on a sampled share of its cell pairs."""
+def cpu_info() -> dict:
+    """Host cores and CPU model (the oracle runs single-threaded on them)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 0
+    return {"nproc": nproc, "cpu_model": model}
+
+
+def oracle_check(hg, wl: dict, edges, info: dict) -> tuple:
+    """The oracle on the GPU's own points and constant (c, or R for the HRG),
+    the same seed: the whole graph up to n = 2^21, above that every cell-pair
+    item above level 3 plus the level-3 subtrees whose A-side ancestor is
+    0 mod 512 (the GPU edges filtered the same way).  Returns the comparison
+    report (edges that differ outside the near-boundary pairs and the tie
+    items are 'unexplained') and the oracle's timing as the CPU baseline."""
     import numpy as np
+    import torch
     import oracle
+    from tests.parity import compare, level3_sample
     oracle.build()
     n = wl["n"]
-    t0 = time.perf_counter()
     if wl["model"] == 1:
-        R = oracle.hrg_solve_R(n, wl["alpha"], wl["T"], wl["avg_deg"])
-        r, x = oracle.points_hrg(n, wl["alpha"], R, wl["seed"])
+        R = info["R"]
+        w, x = hg.points(n, model=1, alpha=wl["alpha"], R=R, seed=wl["seed"])
         kw = dict(T=wl["T"], model=1, R=R, alpha=wl["alpha"], seed=wl["seed"])
-        w = r
     else:
-        w, x = oracle.points_girg(n, wl["d"], wl["beta"], wl["seed"])
-        c = oracle.solve_c(w, wl["d"], wl["T"], wl["avg_deg"])
-        kw = dict(T=wl["T"], c=c, seed=wl["seed"])
-    sample = "one full graph (points, constant, sampling)"
+        w, x = hg.points(n, wl["d"], wl["beta"], seed=wl["seed"])
+        kw = dict(T=wl["T"], c=info["c"], seed=wl["seed"])
+    sample = "the whole graph"
     if n > 2**21:
-        # sampled: every item above level 3, and 1/512 of the level-3 subtrees
-        # (A-side ancestor 0 mod 512)
         kw.update(filter_level=3, filter_mod=512, filter_rem=0)
-        sample = ("points + constant for the full graph; sampling of every cell pair above level 3 "
-                  "and of 1/512 of the level-3 subtrees")
-    run = oracle.run(w, x, **kw)
+        sample = ("every cell-pair item above level 3 and the level-3 subtrees whose A-side "
+                  "ancestor is 0 mod 512")
+    wh = w.cpu().numpy()
+    xh = np.ascontiguousarray(x.cpu().numpy().T)
+    t0 = time.perf_counter()
+    run = oracle.run(wh, xh, keep=True, **kw)
     dt = time.perf_counter() - t0
-    m = len(run.edges)
-    return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; {m} edges in {dt:.2f} s"}
+    m_orc = len(run.edges)
+    if n > 2**21:
+        edges = level3_sample(edges, x, run, 512)
+    t1 = time.perf_counter()
+    rep = {"sample": sample, "inputs": "the GPU's points and constant, same seed"}
+    try:
+        rep.update(compare(edges.cpu().numpy().view(np.uint32), run))
+        rep["match"] = True
+    except AssertionError as exc:
+        rep["match"] = False
+        rep["error"] = str(exc)[:400]
+    rep["compare_s"] = time.perf_counter() - t1
+    run.close()
+    del w, x
+    cpu = {"value": m_orc / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"sampling of {sample} of the same graph (points and constant given): "
+                     f"{m_orc} edges in {dt:.2f} s, single-threaded", **cpu_info()}
+    return rep, cpu
 
 
 def cpu_baseline_batch(params: list, budget_s: float = 15.0) -> dict:
@@ -198,7 +245,8 @@ def cpu_baseline_batch(params: list, budget_s: float = 15.0) -> dict:
             break
     dt = time.perf_counter() - t0
     return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {k} of {len(params)} instances, whole graphs; {m} edges in {dt:.2f} s"}
+            "sample": f"the first {k} of {len(params)} instances, whole graphs; {m} edges in {dt:.2f} s",
+            **cpu_info()}
 
 
 def single_calls(hg, params: list, sp) -> dict:
@@ -392,13 +440,86 @@ def hbm_copy(mib: int, steps: int, warmup: int) -> int:
     return 0
 
 
+def profiled_steps(hg, call, bp, cap, sp, nprof: int) -> tuple:
+    """nprof calls with stage events, the concurrent sampling passes run one
+    after another (profiling mode 2): every kernel's time is its own, as a
+    kernel trace sees it.  Returns (mean stage times in ms, info of the last)."""
+    import torch
+    m = ctypes.c_uint64(0)
+    info = hg.Info()
+    hg.set_profiling(True, serial=True)
+    acc: dict = {}
+    try:
+        for _ in range(nprof):
+            hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
+            for name, ms in hg.stage_times():
+                acc[name] = acc.get(name, 0.0) + ms
+        torch.cuda.synchronize()
+    finally:
+        hg.set_profiling(False)
+    return {k: v / nprof for k, v in acc.items()}, info.as_dict()
+
+
+def roofline(wl: dict, workload: str, stages: dict, info: dict) -> dict:
+    """VALU roofline of the dominant sampling kernel, timed alone: its
+    algorithmic lane-operations (units of work x VALU instructions per unit of
+    the decision arithmetic) over its duration."""
+    tb = OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM
+    pw, pc = info["pass_work"], info["pass_cands"]
+    per = {"type1": (pw[0] * tb, {"tests": pw[0]}),
+           "split1": (pw[1] * tb, {"tests": pw[1]}),
+           "type2": (pw[2] * OPS_DRAW + pc[2] * OPS_CAND, {"draws": pw[2], "candidates": pc[2]}),
+           "segments2": (pw[3] * OPS_DRAW + pc[3] * OPS_CAND, {"draws": pw[3], "candidates": pc[3]})}
+    ran = {k: stages[k] for k in per if stages.get(k, 0.0) > 0.0 and per[k][0] > 0}
+    dom = max(ran, key=ran.get)
+    ops, units = per[dom]
+    ms = ran[dom]
+    achieved = ops / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "kernel": STAGE_KERNEL[dom] + "...>", "achieved": achieved,
+           "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
+           "traffic": profiled_traffic(workload, dom), "launch_ms": ms, "units_per_launch": units,
+           "ops_per_unit": {"test": tb, "draw": OPS_DRAW, "candidate": OPS_CAND},
+           "ops_per_launch": ops,
+           "other_kernels": {STAGE_KERNEL[k] + "...>": {"ms": ran[k],
+                                                        "frac": per[k][0] / (ran[k] * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                             for k in ran if k != dom}}
+    cnt = profiled_counters(workload, dom)
+    if cnt:
+        out["counters"] = cnt
+    return out
+
+
+def profiled_counters(workload: str, stage: str):
+    """SQ counters of the stage's kernel from the committed rocprofv3 summary
+    (VALU busy share, issued VALU lane-instructions per launch), or None when
+    there is none or the kernels changed since."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload}.txt")
+    if not os.path.exists(path) or stage not in STAGE_KERNEL:
+        return None
+    want = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"valu (.+) valu_busy=([\d.]+) valu_lane_ops_per_launch=(\d+) "
+                         r"lanes_active=([\d.]+) source_sha=(\w+)", line)
+            if m and m.group(1).startswith(STAGE_KERNEL[stage]) and m.group(5) == want:
+                return {"valu_busy": float(m.group(2)), "valu_lane_ops_per_launch": int(m.group(3)),
+                        "lanes_active": float(m.group(4)), "source": os.path.relpath(path, ROOT)}
+    return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
+                    help="legs to run (default both where the FP32 filter applies)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (both its timing and the oracle-match check)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the profiled steps (passes one after another), for a kernel trace")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the launch shapes on this workload before the warm-up "
                          "(default: the library's tuning table)")
@@ -410,8 +531,8 @@ def main() -> int:
                     help="HRG vs GIRG sub/supergraph experiment (threshold, n = 10^6), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sampler has no "
-              "multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the sampler has no "
+              "multi-GPU path (DESIGN.md describes how it would shard)", file=sys.stderr)
         return 2
     if args.hbm_copy:
         return hbm_copy(args.hbm_copy, args.steps, args.warmup)
@@ -424,103 +545,83 @@ def main() -> int:
     import paper_1905_06706_amd as hg
 
     desc, wl = WORKLOADS[args.workload]
-    L = hg.load()
+    hg.load()
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
-    call = make_call(hg, wl)
+    legs = legs_of(wl)
+    if args.precision != "both":
+        want = 0 if args.precision == "fp64" else 1
+        if want not in legs:
+            print(f"[bench] {args.workload} has no {args.precision} leg", file=sys.stderr)
+            return 2
+        legs = [want]
+    is_batch = "batch" in wl
 
-    # first call sizes the output exactly (the sampler is deterministic)
-    m = ctypes.c_uint64(0)
-    info = hg.Info()
-    st = call(None, 0, ctypes.byref(m), ctypes.byref(info), sp)
-    if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
-        hg._check(st)
-    cap = int(m.value)
-    buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
-    bp = ctypes.c_void_p(buf.data_ptr())
+    # per leg: the call, an output buffer sized by a first (counting) call
+    L = {}
+    for q in legs:
+        call = make_call(hg, wl, q)
+        m = ctypes.c_uint64(0)
+        info = hg.Info()
+        st = call(None, 0, ctypes.byref(m), ctypes.byref(info), sp)
+        if st not in (hg.GIRG_OK, hg.GIRG_EOVERFLOW):
+            hg._check(st)
+        cap = int(m.value)
+        buf = torch.empty((max(cap, 1), 2), dtype=torch.int32, device="cuda")
+        L[q] = dict(call=call, cap=cap, buf=buf, bp=ctypes.c_void_p(buf.data_ptr()))
+    p0 = L[legs[0]]["call"].params
     # launch shapes (persistent grid size, batch workers): the library's table,
-    # or tuned on this workload before the warm-up; they change no edge, only
-    # the speed
+    # or tuned on this workload before the warm-up; they change no edge
     if not args.autotune:
-        b, w = hg.tuning_get(call.params[0] if "batch" in wl else call.params, batch="batch" in wl)
-        tuning = {"autotuned": False, "blocks": b, **({"workers": w} if "batch" in wl else {})}
-    elif "batch" in wl:
-        b, w = hg.autotune_batch(call.params, reps=1)
+        b, w = hg.tuning_get(p0[0] if is_batch else p0, batch=is_batch)
+        tuning = {"autotuned": False, "blocks": b, **({"workers": w} if is_batch else {})}
+    elif is_batch:
+        b, w = hg.autotune_batch(p0, reps=1)
         tuning = {"autotuned": True, "blocks": b, "workers": w}
     else:
-        tuning = {"autotuned": True, "blocks": hg.autotune(call.params, reps=2)}
+        tuning = {"autotuned": True, "blocks": hg.autotune(p0, reps=2)}
     print(f"[bench] tuning {tuning}", file=sys.stderr)
-    for _ in range(args.warmup):
-        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
-    # the timed steps run without stage events; the stage and kernel times come
-    # from a few profiled steps after them (the same work, untimed)
-    edges = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
-        edges += m.value
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    hg.set_profiling(True)
-    stage_sum: dict = {}
-    nprof = max(1, min(args.steps, 5))
-    for _ in range(nprof):
-        hg._check(call(bp, cap, ctypes.byref(m), ctypes.byref(info), sp))
-        for name, ms in hg.stage_times():
-            stage_sum[name] = stage_sum.get(name, 0.0) + ms
-    torch.cuda.synchronize()
-    hg.set_profiling(False)
-    info_d = info.as_dict()
-    stages = {k: v / nprof for k, v in stage_sum.items()}
-    print(f"[bench] {desc}: m={m.value} steps={args.steps} {dt / args.steps * 1e3:.3f} ms/step",
-          file=sys.stderr)
-    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
-        print(f"[bench]   {k:>14s} {v:9.4f} ms", file=sys.stderr)
-    print(f"[bench] info {info_d}", file=sys.stderr)
 
-    if "batch" in wl:
-        # instances run concurrently on several streams: the whole step is the
-        # unit (all kernels of all instances)
-        ops = call.ops
-        achieved = ops / (dt / args.steps) / 1e12
-        roof = {"bound": "alu", "kernel": "whole batch step (all kernels, concurrent streams)",
-                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "launch_ms": dt / args.steps * 1e3, "ops_per_launch": ops}
-    else:
-        # The sampling kernels run in two phases, each with two kernels on two
-        # streams at once: type I beside type II, then the split type-I pass
-        # beside the segmented type-II pass.  The dominant phase is the unit:
-        # its lane-operations over its wall time (both kernels start at the
-        # fork, so the wall time is the longer of the two kernel times, each
-        # timed by HIP events on its own stream).
-        tb = OPS_TEST_T0 if wl["T"] == 0.0 else OPS_TEST_BINOM
-        pw, pc = info_d["pass_work"], info_d["pass_cands"]
-        phases = {
-            "sampling": (("type1", "type2"), pw[0] * tb + pw[2] * OPS_DRAW + pc[2] * OPS_CAND,
-                         {"tests": pw[0], "draws": pw[2], "candidates": pc[2]}),
-            "deferred": (("split1", "segments2"), pw[1] * tb + pw[3] * OPS_DRAW + pc[3] * OPS_CAND,
-                         {"tests": pw[1], "draws": pw[3], "candidates": pc[3]}),
-        }
-        ran = {k for k, q in (("type1", 0), ("split1", 1), ("type2", 2), ("segments2", 3)) if pw[q] > 0}
-        wall = {ph: max([stages.get(k, 0.0) for k in ks if k in ran] or [0.0])
-                for ph, (ks, _, _) in phases.items()}
-        dom = max(wall, key=wall.get)
-        kstages, ops, units = phases[dom]
-        achieved = ops / (wall[dom] * 1e-3) / 1e12
-        pass_of = {"type1": 0, "split1": 1, "type2": 2, "segments2": 3}
-        kinds = [k for k in kstages if pw[pass_of[k]] > 0]  # kernels that ran
-        traffic = [profiled_traffic(args.workload, k) for k in kinds]
-        roof = {"bound": "alu", "kernel": " + ".join(STAGE_KERNEL[k] + "...>" for k in kinds)
-                + (" (concurrent streams)" if len(kinds) > 1 else ""),
-                "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
-                "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": sum(traffic) if traffic and None not in traffic else None,
-                "launch_ms": wall[dom], "kernels_ms": {STAGE_KERNEL[k][:-1]: stages[k] for k in kinds},
-                "units_per_launch": units, "ops_per_launch": ops}
-    value = edges / dt
+    if args.kernels_only:
+        for q in legs:
+            lg = L[q]
+            stages, _ = profiled_steps(hg, lg["call"], lg["bp"], lg["cap"], sp, max(1, args.steps))
+            print(json.dumps({"leg": LEG_NAMES[q], "workload": args.workload, "stages_ms": stages}), flush=True)
+        return 0
+
+    m = ctypes.c_uint64(0)
+    info = hg.Info()
+    for _ in range(args.warmup):
+        for q in legs:
+            lg = L[q]
+            hg._check(lg["call"](lg["bp"], lg["cap"], ctypes.byref(m), ctypes.byref(info), sp))
+    # timed: K steps per leg, each leg bracketed by device synchronisations
+    # (no stage events); FP64 first, then the FP32 filter
+    for q in legs:
+        lg = L[q]
+        edges = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            hg._check(lg["call"](lg["bp"], lg["cap"], ctypes.byref(m), ctypes.byref(info), sp))
+            edges += m.value
+        torch.cuda.synchronize()
+        lg["dt"] = time.perf_counter() - t0
+        lg["edges"] = edges
+        lg["m"] = int(m.value)
+        lg["info"] = info.as_dict()
+        print(f"[bench] {desc} {LEG_NAMES[q]}: m={m.value} steps={args.steps} "
+              f"{lg['dt'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    # kernel times, each pass alone (a few profiled steps after the timed ones)
+    nprof = max(1, min(args.steps, 5))
+    for q in legs:
+        lg = L[q]
+        lg["stages"], lg["pinfo"] = profiled_steps(hg, lg["call"], lg["bp"], lg["cap"], sp, nprof)
+        for k, v in sorted(lg["stages"].items(), key=lambda kv: -kv[1]):
+            print(f"[bench]   {LEG_NAMES[q]} {k:>14s} {v:9.4f} ms", file=sys.stderr)
+    top = legs[-1]  # the reported leg: the FP32 filter where it runs
+    lt = L[top]
+    value = lt["edges"] / lt["dt"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -528,24 +629,51 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": lt["dt"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if wl["precision"] == 0 else "f32+f64",
+        "dtype": "f32+f64" if top == 1 else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, **{k: wl[k] for k in wl}},
-        "edges_per_step": int(m.value),
+        "config": {"workload": desc + (" (FP32 filter with FP64 recheck vs plain FP64)" if len(legs) > 1
+                                       else " (FP64)"),
+                   **{k: v for k, v in wl.items()}},
+        "edges_per_step": lt["m"],
         "hbm_frac_edge_output": value * 8 / (HBM_PEAK_GBS * 1e9),
-        "roofline": roof,
-        "stages_ms": stages,
     }
+    for q in legs:
+        lg = L[q]
+        out[LEG_NAMES[q]] = {"value": lg["edges"] / lg["dt"], "ms_per_step": lg["dt"] / args.steps * 1e3,
+                             "edges_per_step": lg["m"], "near_boundary": lg["info"]["near_boundary"],
+                             "skip_ties": lg["info"]["skip_ties"], "rechecks": lg["info"]["rechecks"]}
+    if len(legs) > 1:
+        out["mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+        same = L[0]["m"] == L[1]["m"] and torch.equal(L[0]["buf"][:L[0]["m"]], L[1]["buf"][:L[1]["m"]])
+        out["mixed_equals_fp64"] = bool(same)
+    if is_batch:
+        ops = lt["call"].ops
+        achieved = ops / (lt["dt"] / args.steps) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "whole batch step (all kernels, concurrent streams)",
+                           "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                           "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                           "launch_ms": lt["dt"] / args.steps * 1e3, "ops_per_launch": ops}
+    else:
+        out["roofline"] = roofline(wl, args.workload + ("_mixed" if top == 1 else ""), lt["stages"],
+                                   lt["pinfo"])
+    out["stages_ms"] = lt["stages"]
     out["tuning"] = tuning
-    if "batch" in wl:
-        out["single_calls"] = single_calls(hg, call.params, sp)
+    if is_batch:
+        out["single_calls"] = single_calls(hg, lt["call"].params, sp)
         print(f"[bench] single calls {out['single_calls']}", file=sys.stderr)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batch(call.params) if "batch" in wl else cpu_baseline(wl)
+        if is_batch:
+            out["cpu_baseline"] = cpu_baseline_batch(lt["call"].params)
+        else:
+            t0 = time.perf_counter()
+            rep, cpu = oracle_check(hg, wl, lt["buf"][:lt["m"]], lt["info"])
+            out["oracle_match"] = rep
+            out["cpu_baseline"] = cpu
+            print(f"[bench] oracle check ({time.perf_counter() - t0:.1f} s): {rep}", file=sys.stderr)
     print(json.dumps(out), flush=True)
     return 0
 

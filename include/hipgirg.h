@@ -92,6 +92,15 @@ typedef struct {
    * segmented type-II items): edges, work units (tests for 0-1, draws for
    * 2-3) and type-II candidates */
   uint64_t pass_edges[4], pass_work[4], pass_cands[4];
+  /* decisions inside the parity margins (expected about 0): near_boundary =
+   * coins within 1e-12 of what they are compared with (type I: |U - p_uv|;
+   * type II: |Acc - p_uv / pbar| for the acceptance coin Acc of Sec. 3.2;
+   * threshold variants: distance within 1e-12, relative, of the threshold);
+   * skip_ties = type-II draws whose skip quotient ln S / ln(1 - pbar) lies
+   * within 1e-12 (relative) of an integer >= 1 that can still decide a
+   * candidate or the end of the item.  Only such decisions can come out
+   * differently under another rounding of the same formulas. */
+  uint64_t near_boundary, skip_ties;
 } girg_info;
 
 /* girg_generate: points (Sec. 2.1 weights and positions), constant c
@@ -112,16 +121,29 @@ girg_status girg_generate(const girg_params* p, uint32_t* edges, uint64_t cap, u
 girg_status girg_hrg(uint64_t n, double alpha, double T, double R, double avg_deg, uint64_t seed,
                      uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info, void* stream);
 
-/* girg_from_points: the sampler alone over caller-provided points (device
- * pointers).  GIRG: w = weights (> 0), x = positions in [0,1), dimension-
- * major [d][n]; c given or solved from avg_deg over these weights.  HRG:
- * w = radii in [0, R], x = angle / (2 pi) in [0,1); R must be given. */
+/* girg_from_points: the sampler of Sec. 3 alone (weight layers and levels of
+ * Sec. 3.1, type-I tests and type-II geometric jumps of Sec. 3.2, the cell
+ * pairs of Algorithm 1 in Sec. 3.3, the Morton layout of Sec. 3.4) over
+ * caller-provided points, which is the problem statement of Sec. 2 with the
+ * weights and positions given (the paper lets the user supply weights).
+ * Device pointers.  GIRG: w = weights (> 0), x = positions in [0,1),
+ * dimension-major [d][n]; c given or solved from avg_deg over these weights
+ * (App. B.2).  HRG: w = radii in [0, R], x = angle / (2 pi) in [0,1); R must
+ * be given (Sec. 2.2, mapped as in Sec. 2.3).  Errors: GIRG_EINVAL for a
+ * weight <= 0 or not finite, a position outside [0,1), a radius outside
+ * [0, R], more than 64 weight layers; the edge buffer is then untouched. */
 girg_status girg_from_points(const girg_params* p, const double* w, const double* x,
                              uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
                              void* stream);
 
-/* girg_points: only the point generation (GIRG: w[n], x[d][n]; HRG: r[n],
- * x[n] with R required).  Device pointers. */
+/* girg_points: only the point generation of the models.  GIRG (Sec. 2.1):
+ * weights of a power law with exponent beta, drawn as Pareto w = S^(-1/(beta-1))
+ * with w_min = 1 (the paper fixes no sampler), positions uniform on the torus
+ * as multiples of 2^-53; w[n], x[d][n].  HRG (Sec. 2.2): radii of density
+ * alpha sinh(alpha r) / (cosh(alpha R) - 1) on [0, R) by the inverse CDF,
+ * angles uniform; r[n], x[n] = angle / (2 pi); R required.  Device pointers
+ * owned by the caller; the call draws from the stream's point counters
+ * (vertex id, purpose), so any prefix of ids gives the same points. */
 girg_status girg_points(const girg_params* p, double* w, double* x, void* stream);
 
 /* girg_solve_c: c for a target average degree over given weights (host
@@ -141,7 +163,11 @@ girg_status hrg_solve_R(uint64_t n, double alpha, double T, double avg_deg, doub
 /* hrg_expected_degree: expected average degree of an HRG with radius R. */
 girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, double* deg_out);
 
-/* girg_generate_batch: `count` independent GIRGs p[0..count-1]; graph b's
+/* girg_generate_batch: no passage of the paper defines it; Sec. 5.2 (HRG run
+ * time comparison) only notes that one often needs many graphs rather than
+ * one huge instance, and then runs instances side by side.  `count`
+ * independent GIRGs
+ * p[0..count-1], each sampled exactly as girg_generate would; graph b's
  * edges occupy edges[2*offsets[b] .. 2*offsets[b+1]) and carry its own vertex
  * ids.  offsets: host pointer to count+1 entries; infos: host array of count
  * or NULL.  GIRG_EOVERFLOW leaves offsets[count] = edges needed.  Instances
@@ -191,7 +217,9 @@ girg_status girg_tuning_reset(void);
  * records HIP events around its stages on the call's own stream; type I and
  * its split pass, which run concurrently with type II and its segmented pass
  * on a second stream of the library's, are timed on that stream, so their
- * times overlap.
+ * times overlap.  girg_set_profiling(2) does the same but runs those passes
+ * one after another on the call's stream (same edges), so that each sampling
+ * kernel's time is its own, as a kernel trace sees it.  0 turns it off.
  * girg_stage_times copies the durations (milliseconds) and names of the last
  * call's stages (at most `max`; either array may be NULL) and returns how many
  * there were, or -1 on error.  Names stay valid until the next call. */

@@ -54,7 +54,7 @@ class _Params(ctypes.Structure):
         ("R", ctypes.c_double), ("seed", ctypes.c_uint64), ("max_depth", ctypes.c_int32),
         ("cl_bias", ctypes.c_int32), ("accept_all", ctypes.c_int32),
         ("filter_level", ctypes.c_int32), ("filter_mod", ctypes.c_uint32),
-        ("filter_rem", ctypes.c_uint32),
+        ("filter_rem", ctypes.c_uint32), ("filter_skip_top", ctypes.c_int32),
     ]
 
 
@@ -289,7 +289,8 @@ class Run:
 def run(w: np.ndarray, x: np.ndarray, *, T: float, c: float = 0.0, seed: int = 0,
         model: int = 0, alpha: float = 0.0, R: float = 0.0, max_depth: int = -1,
         cl_bias: int = 0, accept_all: bool = False, filter_level: int = 0,
-        filter_mod: int = 0, filter_rem: int = 0, keep: bool = False) -> Run:
+        filter_mod: int = 0, filter_rem: int = 0, filter_skip_top: bool = False,
+        keep: bool = False) -> Run:
     """Sample one graph over the given points (GIRG: weights w, HRG: radii w)."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -299,7 +300,8 @@ def run(w: np.ndarray, x: np.ndarray, *, T: float, c: float = 0.0, seed: int = 0
     assert len(w) == n
     p = _Params(n=n, d=d, model=model, T=T, c=c, alpha=alpha, R=R, seed=seed,
                 max_depth=max_depth, cl_bias=cl_bias, accept_all=int(accept_all),
-                filter_level=filter_level, filter_mod=filter_mod, filter_rem=filter_rem)
+                filter_level=filter_level, filter_mod=filter_mod, filter_rem=filter_rem,
+                filter_skip_top=int(filter_skip_top))
     L = lib()
     h = L.orc_run_graph(ctypes.byref(p), _ptr(w, ctypes.c_double), _ptr(x, ctypes.c_double))
     if not h:

@@ -806,7 +806,7 @@ static int any_nonempty(const orc_run* R, int l, uint64_t A) {
 static void recur(orc_run* R, int l, uint64_t A, uint64_t B, int nb, int selected) {
   const orc_params* p = &R->p;
   if (p->filter_mod && l == p->filter_level) selected = (A % p->filter_mod) == p->filter_rem;
-  if (selected) {
+  if (selected && !(p->filter_mod && p->filter_skip_top && l < p->filter_level)) {
     R->ctr[nb ? S_NBPAIRS : S_DISTPAIRS]++;
     if (nb) R->lvl_nb[l]++; else R->lvl_dist[l]++;
     /* for all bucket pairs (i,j) that process (A,B): neighbouring pairs at

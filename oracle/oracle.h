@@ -45,6 +45,10 @@ typedef struct orc_params {
   int32_t filter_level; /* subtree sampling: with filter_mod > 0, a cell pair at  */
   uint32_t filter_mod;  /* level >= filter_level is processed only if its level-  */
   uint32_t filter_rem;  /* filter_level A-side ancestor a has a % mod == rem      */
+  int32_t filter_skip_top; /* with filter_mod > 0: the cell pairs above        */
+                           /* filter_level are walked but not sampled, so that  */
+                           /* runs over the remainders mod filter_mod and one   */
+                           /* run of the top levels alone partition the graph   */
 } orc_params;
 
 typedef struct orc_run orc_run;

@@ -58,6 +58,7 @@ class Info(ctypes.Structure):
         ("D", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
         ("pass_edges", ctypes.c_uint64 * 4), ("pass_work", ctypes.c_uint64 * 4),
         ("pass_cands", ctypes.c_uint64 * 4),
+        ("near_boundary", ctypes.c_uint64), ("skip_ties", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -335,8 +336,10 @@ def tuning_reset():
     _check(load().girg_tuning_reset())
 
 
-def set_profiling(on: bool):
-    _check(load().girg_set_profiling(1 if on else 0))
+def set_profiling(on, serial: bool = False):
+    """Stage timing on (True) or off; serial=True runs the otherwise
+    concurrent sampling passes one after another (mode 2)."""
+    _check(load().girg_set_profiling((2 if serial else 1) if on else 0))
 
 
 def stage_times() -> list:

@@ -124,6 +124,9 @@ struct Ctx {
   // runs from the event before it to its own, both on the stream it ran on;
   // the passes that overlap are timed on their own streams
   bool profiling = false;
+  // profiling mode 2: the passes that otherwise overlap run one after
+  // another on the call's stream, so each kernel's time is its own
+  bool serial = false;
   std::vector<hipEvent_t> ev;
   std::vector<std::string> ev_name;
   std::vector<double> last_ms;
@@ -955,16 +958,18 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   // staging of the edges: capacity = the caller's; flush records.  The
   // counters sit in one block, cleared by one memset per attempt, 256 bytes
   // apart (atomics of all waves on one cache line slow every pass down):
-  // tickets[0..7], deferred counts[64..65], flush records[128], cursor (u64) at 192
+  // tickets[0..7], deferred counts[64..65], flush records[128], near-boundary
+  // candidates[160], cursor (u64) at 192
   unsigned int* ctr = ar.get<unsigned int>(256);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (counters)");
   unsigned int* tickets = ctr;
   unsigned int* dcount = ctr + 64;
   unsigned int* nrec_d = ctr + 128;
+  unsigned int* ncnt = ctr + 160;
   unsigned long long* cursor = reinterpret_cast<unsigned long long*>(ctr + 192);
   // type I (and its split pass) on the side stream, concurrently with type II
   // (and its segments); profiled calls time each pass on its own stream
-  const bool overlap = cx.side != nullptr;
+  const bool overlap = cx.side != nullptr && !(cx.profiling && cx.serial);
   hipStream_t s1 = overlap ? cx.side : st;
   SideGuard sguard{cx};
   // persistent grids: the tuned number of workgroups, at most one wave per chunk
@@ -1003,8 +1008,13 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint64_t* roff = ar.get<uint64_t>(rcap);
   uint64_t* rpos = ar.get<uint64_t>(rcap);
   uint32_t* rcnt = ar.get<uint32_t>(rcap);
+  // type-II candidates whose coin lies within 1e-12 of p_uv (expected far
+  // fewer than the list holds)
+  constexpr uint32_t kNearCap = 1u << 16;
+  uint4* nbuf = binomial ? ar.get<uint4>(kNearCap) : nullptr;
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (edge staging)");
-  Stage sg{stage, cap, cursor, rtag, roff, rpos, rcnt, nrec_d, rcap, cx.stats};
+  Stage sg{stage, cap, cursor, rtag, roff, rpos, rcnt, nrec_d, rcap, cx.stats, nbuf, ncnt,
+           binomial ? kNearCap : 0u};
 
   // type-I and type-II passes (deferred lists grown once if too small)
   // first capacity: half an entry per source (the workloads measured defer up to
@@ -1087,6 +1097,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   cx.mark("segments2", st);
   HIPCHK(join_side(cx, st, overlap, sguard));
   cx.mark("-", st);
+  if (binomial) HIPCHK(launch_near2(g, cx.gd, v, pbt, nlev, sg, st));
   // where each chunk's edges start, in pass order
   HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot},
                               {sch[0].nchunks, sch[1].nchunks, sch[2].nchunks, sch[3].nchunks}, 1u},
@@ -1134,6 +1145,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     info->draws = stt[2] + stt[3];
     info->candidates = stt[4] + stt[5];
     info->rechecks = stt[6];
+    info->near_boundary = stt[12];
+    info->skip_ties = stt[13];
     info->sources = nsrc;
     info->heavy_items = dn[1];
     info->split_items = dn[0];
@@ -1498,6 +1511,7 @@ girg_status girg_set_profiling(int32_t on) {
   if (s != GIRG_OK) return s;
   std::lock_guard<std::mutex> lk(cx->mu);
   cx->profiling = on != 0;
+  cx->serial = on == 2;
   return GIRG_OK;
 }
 

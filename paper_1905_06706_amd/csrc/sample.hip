@@ -43,6 +43,24 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+// statistics slots of the decisions that lie inside the parity margins (rare,
+// so each is counted by one atomic): coins within 1e-12 of the probability
+// they are compared with (threshold variants: distance within 1e-12, relative,
+// of the threshold), and type-II draws whose skip quotient lies within 1e-12
+// (relative) of an integer that can still decide a candidate or the end
+constexpr int kStatNear = 12, kStatTie = 13;
+__device__ __forceinline__ void count_stat(unsigned long long* st, int slot) {
+  atomicAdd(&st[slot], 1ull);
+}
+// list a type-II candidate with |apb - p_uv| < 1e-12 for the test against the
+// band 1e-12 pbar after the passes (k_near2)
+__device__ __forceinline__ void list_near2(uint4* nbuf, unsigned int* ncnt, uint32_t ncap,
+                                           uint32_t su, uint32_t sv, double apb) {
+  const unsigned int slot = atomicAdd(ncnt, 1u);
+  const uint64_t bits = (uint64_t)__double_as_longlong(apb);
+  if (slot < ncap) nbuf[slot] = make_uint4(su, sv, (uint32_t)bits, (uint32_t)(bits >> 32));
+}
+
 // ---------------------------------------------------------------------------
 // edge decisions (FP64)
 // ---------------------------------------------------------------------------
@@ -122,9 +140,11 @@ __device__ __noinline__ double hrg_prob(const Graph* __restrict__ g, double cosh
 // pairs outside a 1e-12 relative margin of both entries, and U outside 1e-9
 // of a grid point, are decided by the table; the rest evaluate p_T, so the
 // result is that of the direct FP64 comparison.
+// A pair the table decides lies more than 1e-11 from p_T; nr is set when the
+// direct comparison finds |U - p_T| < 1e-12.
 template <int D>
 __device__ __forceinline__ bool hrg_below(const Graph* __restrict__ g, const Rec<D, 1>& a,
-                                          const Rec<D, 1>& b, double U) {
+                                          const Rec<D, 1>& b, double U, bool& nr) {
   const double ch = hrg_coshd<D>(a, b, torus_r<D, 1>(a, b));
   const double t = U * (double)(kHrgTab - 1);
   const int m = (int)t;
@@ -132,7 +152,9 @@ __device__ __forceinline__ bool hrg_below(const Graph* __restrict__ g, const Rec
     if (ch < g->hct[m + 1] * (1.0 - 1e-12)) return true;
     if (ch > g->hct[m] * (1.0 + 1e-12)) return false;
   }
-  return U < hrg_prob(g, ch);
+  const double p = hrg_prob(g, ch);
+  nr = fabs(U - p) < 1e-12;
+  return U < p;
 }
 
 // probability (binomial variants) of the pair of sorted vertices (su, sv)
@@ -149,16 +171,22 @@ __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const V
 }
 
 // threshold variants
+// (nr: the distance lies within 1e-12, relative, of the threshold; for GIRGs
+// (r / t)^d within d 1e-12 of 1)
 template <int D, int MODEL>
 __device__ __forceinline__ bool pair_thresh(const Graph* __restrict__ g, const Verts& v,
-                                            uint32_t su, uint32_t sv) {
+                                            uint32_t su, uint32_t sv, bool& nr) {
   const Rec<D, MODEL> a = load_rec<D, MODEL>(v.rec, su), b = load_rec<D, MODEL>(v.rec, sv);
   const double r = torus_r<D, MODEL>(a, b);
   if constexpr (MODEL == 0) {
     // ||x_u - x_v|| <= c (w_u w_v / W)^{1/d}  <=>  r^d W <= c^d w_u w_v
-    return pow_d<D>(r) * g->W <= g->kappa * a.v[0] * b.v[0];
+    const double lhs = pow_d<D>(r) * g->W, rhs = g->kappa * a.v[0] * b.v[0];
+    nr = fabs(lhs - rhs) <= (1e-12 * D) * rhs;
+    return lhs <= rhs;
   } else {
-    return hrg_coshd<D>(a, b, r) < g->coshR;
+    const double ch = hrg_coshd<D>(a, b, r);
+    nr = fabs(ch - g->coshR) <= 1e-12 * g->coshR;
+    return ch < g->coshR;
   }
 }
 
@@ -184,10 +212,10 @@ __device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, double w
   return true;
 }
 
-// type-I test: edge iff U < p_uv
+// type-I test: edge iff U < p_uv (nr: |U - p_uv| < 1e-12)
 template <int D>
 __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double U, uint32_t& nre) {
+                                           uint32_t sv, double U, uint32_t& nre, bool& nr) {
   const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
   const double r = torus_r<D, 0>(a, b);
   float Lc, err;
@@ -197,13 +225,16 @@ __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Ve
     if (lu > Lc + err) return false;
   }
   ++nre;
-  return U < girg_prob<D>(g, a.v[0], b.v[0], r);
+  const double p = girg_prob<D>(g, a.v[0], b.v[0], r);
+  nr = fabs(U - p) < 1e-12;
+  return U < p;
 }
 
-// type-II candidate: accepted iff Acc * pbar < p_uv (apb = Acc * pbar in FP64)
+// type-II candidate: accepted iff Acc * pbar < p_uv (apb = Acc * pbar in FP64;
+// a recheck with |apb - p_uv| < 1e-12 is listed for k_near2)
 template <int D>
 __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Verts& v, uint32_t su,
-                                           uint32_t sv, double apb, uint32_t& nre) {
+                                           uint32_t sv, double apb, uint32_t& nre, const Stage& sg) {
   const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
   const double r = torus_r<D, 0>(a, b);
   float Lc, err;
@@ -214,7 +245,9 @@ __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Ve
     if (la > Lc + e2) return false;
   }
   ++nre;
-  return apb < girg_prob<D>(g, a.v[0], b.v[0], r);
+  const double p = girg_prob<D>(g, a.v[0], b.v[0], r);
+  if (fabs(apb - p) < 1e-12) list_near2(sg.nbuf, sg.ncnt, sg.ncap, su, sv, apb);
+  return apb < p;
 }
 
 // ---------------------------------------------------------------------------
@@ -390,7 +423,7 @@ template <int D, int MODEL, bool T0, bool MX>
 __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Verts& v,
                                            const QItem1& it, uint64_t k, uint64_t kend, bool& e0,
                                            bool& e1, uint2& p0, uint2& p1, uint32_t& ntests,
-                                           uint32_t& nre) {
+                                           uint32_t& nre, unsigned long long* st) {
   const bool tri = it.tri != 0;
   uint32_t a, b;
   if (tri) {
@@ -414,16 +447,21 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
   for (int h = 0; h < 2; ++h) {
     if (k < kend) {
       const uint32_t su = it.a0 + a, sv = (tri ? it.a0 : it.b0) + b;
-      bool e;
+      bool e, nr = false;
       if constexpr (T0) {
-        e = pair_thresh<D, MODEL>(g, v, su, sv);
+        e = pair_thresh<D, MODEL>(g, v, su, sv, nr);
       } else {
         const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
-        if constexpr (MX) e = mixed_test<D>(g, v, su, sv, U, nre);
+        if constexpr (MX) e = mixed_test<D>(g, v, su, sv, U, nre, nr);
         else if constexpr (MODEL == 1)
-          e = hrg_below<D>(g, load_rec<D, 1>(v.rec, su), load_rec<D, 1>(v.rec, sv), U);
-        else e = U < pair_prob<D, MODEL>(g, v, su, sv);
+          e = hrg_below<D>(g, load_rec<D, 1>(v.rec, su), load_rec<D, 1>(v.rec, sv), U, nr);
+        else {
+          const double p = pair_prob<D, MODEL>(g, v, su, sv);
+          nr = fabs(U - p) < 1e-12;
+          e = U < p;
+        }
       }
+      if (nr) count_stat(st, kStatNear);
       if (e) {
         if (h == 0) p0 = make_uint2(su, sv);
         else p1 = make_uint2(su, sv);
@@ -472,7 +510,7 @@ __device__ __forceinline__ void step1(const Graph* __restrict__ g, const Verts& 
     const uint64_t tot = it.tri ? (uint64_t)it.na * (it.na - 1) / 2 : (uint64_t)it.na * it.nb;
     const uint64_t kb = (uint64_t)it.kb + (gb - it.cs);
     const uint64_t kend = 2ull * ((uint64_t)it.kb + it.nbk) < tot ? 2ull * ((uint64_t)it.kb + it.nbk) : tot;
-    test_block<D, MODEL, T0, MX>(g, v, it, 2ull * kb, kend, e0, e1, p0, p1, ntests, nre);
+    test_block<D, MODEL, T0, MX>(g, v, it, 2ull * kb, kend, e0, e1, p0, p1, ntests, nre, sg.stats);
   }
   emit(e0, e1, p0, p1, sg, out);
   r.bc += take;
@@ -795,7 +833,8 @@ struct Ring2 {
 // otherwise from the FP64 quotient.
 template <bool MX>
 __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, const PB& pe,
-                                         bool& done, Cand& cd, uint32_t& nre) {
+                                         bool& done, Cand& cd, uint32_t& nre,
+                                         unsigned long long* st) {
   const U4 o = philox(it.t, it.A, it.B, it.w3, k0s, k1s);
   ++it.t;
   const uint64_t vv = (((uint64_t)o.y << 32) | o.x) >> 11;
@@ -832,6 +871,12 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
     // reciprocal overflows to -inf)
     const double ls = log_pos(S);
     const double q = ls == 0.0 ? 0.0 : ls * pe.ilg;
+    // a quotient within 1e-12 (relative) of an integer >= 1 that can decide
+    // a candidate or the end (the FP32 filter never decides those)
+    if (pe.pbar < 1.0 && q >= 0.5 && q < (double)rem + 1.0) {
+      const double fl = rint(q);
+      if (fabs(q - fl) < 1e-12 * q) count_stat(st, kStatTie);
+    }
     if (q >= (double)rem) end = true;
     else skip = (uint64_t)q;
   }
@@ -856,9 +901,45 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   return true;
 }
 
+// Whether a type-II candidate's coin lies within 1e-12 of its acceptance
+// probability, |Acc - p_uv / pbar| < 1e-12, i.e. |apb - p_uv| < 1e-12 pbar.
+// The sampling kernels list the candidates with |apb - p_uv| < 1e-12 (rare);
+// k_near2 applies this test to them afterwards.  pbar is that of the item:
+// its level is the first at which the cells of the two vertices are not
+// neighbours (their parents are), with gap max_k(torus difference - 1) there.
+template <int D, int MODEL>
+__device__ __forceinline__ bool t2_near(const Graph* __restrict__ g, const Verts& v,
+                                     const Pbar* __restrict__ pbt, int nlev, uint32_t su,
+                                     uint32_t sv, double apb) {
+  uint32_t qa[D], qb[D];
+  morton_decode<D>(v.mort[su], qa);
+  morton_decode<D>(v.mort[sv], qb);
+  int lvl = -1, gap = 0;
+  for (int l = 1; l < nlev && lvl < 0; ++l) {
+    const int sh = g->Dmax - l;
+    const uint64_t side = 1ull << l;
+    int dm = 0;
+    for (int k = 0; k < D; ++k) {
+      const uint64_t a = qa[k] >> sh, b = qb[k] >> sh;
+      const uint64_t df = a > b ? a - b : b - a;
+      const uint64_t dt = df < side - df ? df : side - df;
+      dm = (int)dt > dm ? (int)dt : dm;
+    }
+    if (dm > 1) {
+      lvl = l;
+      gap = dm - 1;
+    }
+  }
+  if (lvl < 0) return false;
+  const uint64_t pidx = (((uint64_t)v.layer[su] * g->L + v.layer[sv]) * nlev + lvl) * 2 + (gap - 1);
+  const double pbar = pbt[pidx].pbar;
+  return fabs(apb - pair_prob<D, MODEL>(g, v, su, sv)) < 1e-12 * pbar;
+}
+
 // evaluate up to 64 queued candidates (accept iff Acc * pbar < p_uv)
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Verts& v,
+                                           const Pbar* __restrict__ pbt, int nlev,
                                            const Cand* __restrict__ cq, Ring2& r, const Stage& sg,
                                            Out& out, uint32_t& nre) {
   const uint32_t lane = lane_id();
@@ -868,10 +949,17 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
   uint2 p0 = make_uint2(0, 0);
   if (lane < take) {
     const Cand cd = cq[(r.ch + lane) & (kCCap - 1)];
-    if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.apb, nre);
+    bool nr = false;
+    if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.apb, nre, sg);
     else if constexpr (MODEL == 1)
-      e0 = hrg_below<D>(g, load_rec<D, 1>(v.rec, cd.su), load_rec<D, 1>(v.rec, cd.sv), cd.apb);
-    else e0 = cd.apb < pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
+      e0 = hrg_below<D>(g, load_rec<D, 1>(v.rec, cd.su), load_rec<D, 1>(v.rec, cd.sv), cd.apb, nr);
+    else {
+      const double p = pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
+      nr = fabs(cd.apb - p) < 1e-12;
+      e0 = cd.apb < p;
+    }
+    // |apb - p_uv| < 1e-12 (rare): the band 1e-12 pbar is checked after the passes
+    if (nr) list_near2(sg.nbuf, sg.ncnt, sg.ncap, cd.su, cd.sv, cd.apb);
     if (e0) p0 = make_uint2(cd.su, cd.sv);
   }
   emit(e0, false, p0, p0, sg, out);
@@ -882,7 +970,7 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
 // runs while at least `need` items are queued or held (to the end if 0)
 template <int D, int MODEL, bool MX>
 __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts& v,
-                                       const Pbar* __restrict__ pbt,
+                                       const Pbar* __restrict__ pbt, int nlev,
                                        const QItem2* __restrict__ q, Cand* __restrict__ cq,
                                        Ring2& r, bool& act, QItem2& it, PB& pe, uint32_t need,
                                        const Stage& sg, Out& out, uint32_t& ndraws,
@@ -908,7 +996,7 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     Cand cd{0, 0, 0.0};
     if (act) {
       bool done = false;
-      hc = geo_draw<MX>(k0s, k1s, it, pe, done, cd, nre);
+      hc = geo_draw<MX>(k0s, k1s, it, pe, done, cd, nre, sg.stats);
       ++ndraws;
       if (done) act = false;
     }
@@ -916,7 +1004,7 @@ __device__ __forceinline__ void draws2(const Graph* __restrict__ g, const Verts&
     if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
     r.ct += (uint32_t)__popcll(mc);
     ncand += hc ? 1 : 0;
-    if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
+    if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
   }
 }
 
@@ -1005,7 +1093,7 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   Cand cd{0, 0, 0.0};
   if (fresh) {
     bool done = false;
-    hc = geo_draw<MX>(g->seed_lo, g->seed_hi, it, pe, done, cd, nre);
+    hc = geo_draw<MX>(g->seed_lo, g->seed_hi, it, pe, done, cd, nre, sg.stats);
     ++ndraws;
     cont = !done;
   }
@@ -1013,10 +1101,10 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
   if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
   r.ct += (uint32_t)__popcll(mc);
   ncand += hc ? 1 : 0;
-  if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
+  if (r.ct - r.ch >= 64) eval_cands<D, MODEL, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
   if (__any(cont)) {
     if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-      draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
+      draws2<D, MODEL, MX>(g, v, pbt, nlev, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
     enqueue2(cont, it, q, r);
   }
 }
@@ -1163,8 +1251,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     while (in)
       take_items2<D, MODEL, MX>(g, v, crec, src, pbt, nlev, ib, in, q, cq, r, act, cur, cpe, c, dseq,
                                 dfo, sg, out, ndraws, ncand, nre);
-    draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
-    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
+    draws2<D, MODEL, MX>(g, v, pbt, nlev, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
+    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
     end_chunk(sg, out, sc, c, dseq);
     nedge += out.off;
   }
@@ -1209,7 +1297,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
     Out out{ebs[wv], 0, 0, ((uint64_t)sc.pass << 32) | c, v.id};
     for (uint64_t u0 = ub; u0 < ue; u0 += kWave) {
       if (r.qt - r.qh > (uint32_t)(kQCap - 64))
-        draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
+        draws2<D, MODEL, MX>(g, v, pbt, nlev, q, cq, r, act, cur, cpe, 64, sg, out, ndraws, ncand, nre);
       const uint64_t u = u0 + lane;
       bool enq = false;
       QItem2 it{};
@@ -1234,8 +1322,8 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
       }
       enqueue2(enq, it, q, r);
     }
-    draws2<D, MODEL, MX>(g, v, pbt, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
-    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, cq, r, sg, out, nre);
+    draws2<D, MODEL, MX>(g, v, pbt, nlev, q, cq, r, act, cur, cpe, 0, sg, out, ndraws, ncand, nre);
+    while (r.ct != r.ch) eval_cands<D, MODEL, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
     end_chunk(sg, out, sc, c, 0);
     nedge += out.off;
   }
@@ -1298,6 +1386,26 @@ __global__ __launch_bounds__(256) void k_stage_copy(const uint2* __restrict__ st
     const uint32_t cnt = rcnt[w];
     for (uint32_t i = lane; i < cnt; i += kWave)
       if (dst + i < m) out[dst + i] = stage[src + i];
+  }
+}
+
+// the type-II candidates listed as within 1e-12 of their probability: count
+// those inside the band 1e-12 pbar; a list that overflowed counts the rest
+// (an upper bound)
+template <int D, int MODEL>
+__global__ __launch_bounds__(256) void k_near2(const Graph* __restrict__ g, Verts v,
+                                               const Pbar* __restrict__ pbt, int nlev,
+                                               const uint4* __restrict__ nbuf,
+                                               const unsigned int* __restrict__ ncnt, uint32_t ncap,
+                                               unsigned long long* __restrict__ stats) {
+  const uint32_t cnt = *ncnt;
+  const uint32_t nl = cnt < ncap ? cnt : ncap;
+  const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h == 0 && cnt > ncap) atomicAdd(&stats[kStatNear], (unsigned long long)(cnt - ncap));
+  for (uint32_t e = h; e < nl; e += gridDim.x * blockDim.x) {
+    const uint4 t = nbuf[e];
+    const double apb = __longlong_as_double((long long)(((uint64_t)t.w << 32) | t.z));
+    if (t2_near<D, MODEL>(g, v, pbt, nlev, t.x, t.y, apb)) atomicAdd(&stats[kStatNear], 1ull);
   }
 }
 
@@ -1406,6 +1514,15 @@ hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const 
       if (mx) hipLaunchKernelGGL((k_heavy2<DD, 0, true>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
       else hipLaunchKernelGGL((k_heavy2<DD, 0, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
     } else hipLaunchKernelGGL((k_heavy2<DD, MM, false>), grid, block, 0, st, gd, v, rec, uoff, nrec, sc, pbt, nlev, sg);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_near2(const Graph& g, const Graph* gd, const Verts& v, const Pbar* pbt, int nlev,
+                        const Stage& sg, hipStream_t st) {
+  HG_DISPATCH_D({
+    hipLaunchKernelGGL((k_near2<DD, MM>), dim3(16), dim3(256), 0, st, gd, v, pbt, nlev, sg.nbuf, sg.ncnt,
+                       sg.ncap, sg.stats);
   });
   return hipGetLastError();
 }

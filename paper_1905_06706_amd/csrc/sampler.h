@@ -59,8 +59,14 @@ struct Stage {
   unsigned int* nrec;
   uint32_t rcap;
   // 0-1 tests of passes 0-1, 2-3 draws of passes 2-3, 4-5 candidates of
-  // passes 2-3, 6 rechecks, 8-11 edges of passes 0-3
+  // passes 2-3, 6 rechecks, 8-11 edges of passes 0-3, 12 decisions within
+  // 1e-12 of the boundary, 13 skip quotients within 1e-12 of an integer
   unsigned long long* stats;
+  // type-II candidates with |Acc pbar - p_uv| < 1e-12: (su, sv, Acc pbar)
+  // for the test against the band 1e-12 pbar after the passes (launch_near2)
+  uint4* nbuf;
+  unsigned int* ncnt;
+  uint32_t ncap;
 };
 
 // deferred items: key = chunk << 24 | sequence in chunk; big = the type-I
@@ -116,6 +122,10 @@ hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const C
                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
                         int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
                         hipStream_t st);
+// the listed type-II candidates inside the band |Acc - p_uv / pbar| < 1e-12
+// counted into stats[12] (one small grid; after both type-II passes)
+hipError_t launch_near2(const Graph& g, const Graph* gd, const Verts& v, const Pbar* pbt, int nlev,
+                        const Stage& sg, hipStream_t st);
 // deferred items: units per record (kind 1: test pieces, kind 2: segments)
 hipError_t launch_rec_units(const ItemRec* rec, uint32_t nrec, int kind, uint64_t* units,
                             hipStream_t st);

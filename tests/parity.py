@@ -62,7 +62,19 @@ def canonical_order(edges: np.ndarray, run) -> tuple:
     return e[order], keys[order]
 
 
-def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0, oriented: bool = True) -> dict:
+def check_gpu_counts(rep: dict, run, info) -> None:
+    """The GPU's own counts of decisions inside the parity margins (a whole
+    graph on both sides): near-boundary decisions as many as the oracle logged
+    (the same test of the same coins), skip ties within the bound of what the
+    draws make likely (the GPU counts draws, the oracle items)."""
+    rep["gpu_near"] = int(info["near_boundary"])
+    rep["gpu_ties"] = int(info["skip_ties"])
+    assert rep["gpu_near"] == len(run.near), f"GPU and oracle near-boundary counts differ: {rep}"
+    assert rep["gpu_ties"] <= count_bound(rep["tie_expect"]), f"too many GPU skip ties: {rep}"
+
+
+def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0, oriented: bool = True,
+            info=None) -> dict:
     ge = np.ascontiguousarray(np.asarray(gpu_edges).reshape(-1, 2)).view(np.uint32)
     g = pair_keys(ge)
     o = pair_keys(run.edges)
@@ -95,4 +107,85 @@ def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0, oriented: bool 
         assert np.array_equal(gkey[:, :6], okey[:, :6]), "canonical keys differ"
         assert np.array_equal(gs, os_), "oriented edges differ in the canonical order"
         rep["oriented"] = len(gs)
+    if info is not None:
+        check_gpu_counts(rep, run, info)
+    return rep
+
+
+def level3_sample(edges, x, run, mod: int):
+    """Edges of the items the oracle samples with filter_level = 3 and
+    filter_mod = mod, filter_rem = 0: every item above level 3, and below it
+    those whose A-side level-3 ancestor is 0 mod `mod`.  An item of a pair
+    (u, v) sits above level 3 when CL(i, j) < 3 or the level-2 cells of u and
+    v are not neighbours (the pair became distant earlier); otherwise its
+    A side at level 3 is the smaller level-3 cell of u and v (A <= B is kept
+    by every descendant).  edges (m, 2) and x (d, n) are device tensors."""
+    import torch
+    dev = edges.device
+    d = x.shape[0]
+    n = x.shape[1]
+    layer = np.empty(n, dtype=np.int64)
+    layer[run.sorted_ids.astype(np.int64)] = np.repeat(np.arange(64), run.count.astype(np.int64))
+    layer = torch.from_numpy(layer).to(dev)
+    CL = torch.from_numpy(run.CL.astype(np.int64)).to(dev)
+    c3 = (x * 8.0).long()
+    m3 = torch.zeros(n, dtype=torch.int64, device=dev)
+    for b in (2, 1, 0):  # coarse to fine, dimension 0 most significant
+        for k in range(d):
+            m3 = (m3 << 1) | ((c3[k] >> b) & 1)
+    u = edges[:, 0].long()
+    v = edges[:, 1].long()
+    far2 = torch.zeros(len(u), dtype=torch.bool, device=dev)
+    for k in range(d):
+        far2 |= torch.remainder((c3[k] >> 1)[u] - (c3[k] >> 1)[v], 4) == 2
+    keep = (CL[layer[u], layer[v]] < 3) | far2 | (torch.remainder(torch.minimum(m3[u], m3[v]), mod) == 0)
+    return edges[keep]
+
+
+def oriented_keys(edges: np.ndarray) -> np.ndarray:
+    """u << 32 | v of oriented edges (u, v)."""
+    e = np.asarray(edges, dtype=np.uint64).reshape(-1, 2)
+    return (e[:, 0] << np.uint64(32)) | e[:, 1]
+
+
+def compare_large(gpu_edges: np.ndarray, run, info=None) -> dict:
+    """compare() for edge sets too large for the per-edge canonical keys: the
+    same exclusions and bounds, and every pair both sides hold must be written
+    with the same orientation (u, v).  Since an oracle edge is written with u
+    from the A side of its item (pinned by compare() on smaller graphs), equal
+    oriented pairs mean equal arrays in the canonical order once the excluded
+    pairs are dropped."""
+    ge = np.ascontiguousarray(np.asarray(gpu_edges).reshape(-1, 2)).view(np.uint32)
+    oe = np.ascontiguousarray(run.edges)
+    assert np.all(ge[:, 0] != ge[:, 1]), "GPU output holds a self-loop"
+    gk = pair_keys(ge)
+    ok = pair_keys(oe)
+    gi = np.argsort(gk, kind="stable")
+    oi = np.argsort(ok, kind="stable")
+    g = gk[gi]
+    o = ok[oi]
+    assert not np.any(g[1:] == g[:-1]), "GPU output holds a pair twice"
+    # orientation flag: 1 when u > v
+    gf = (ge[gi, 0] > ge[gi, 1])
+    of = (oe[oi, 0] > oe[oi, 1])
+    both, ig, io = np.intersect1d(g, o, assume_unique=True, return_indices=True)
+    only_g = np.delete(g, ig)
+    only_o = np.delete(o, io)
+    diff = np.union1d(only_g, only_o)
+    near_keys = np.unique(pair_keys(run.near)) if len(run.near) else np.zeros(0, dtype=np.uint64)
+    if len(near_keys):
+        diff = np.setdiff1d(diff, near_keys, assume_unique=True)
+    bad = diff[~in_tie_items(diff, run)]
+    rep = {"gpu": len(g), "oracle": len(o), "only_gpu": len(only_g), "only_oracle": len(only_o),
+           "near": len(run.near), "ties": len(run.ties),
+           "near_expect": float(run.stats.get("near_expect", 0.0)),
+           "tie_expect": float(run.stats.get("tie_expect", 0.0)), "unexplained": len(bad)}
+    assert len(bad) == 0, f"edge sets differ outside the near-boundary pairs: {rep}"
+    assert rep["near"] <= count_bound(rep["near_expect"]), f"too many near-boundary decisions: {rep}"
+    assert rep["ties"] <= count_bound(rep["tie_expect"]), f"too many skip ties: {rep}"
+    flip = int(np.count_nonzero(gf[ig] != of[io]))
+    assert flip == 0, f"{flip} common pairs written with the other orientation"
+    rep["oriented"] = len(both)
+    if info is not None:
+        check_gpu_counts(rep, run, info)
     return rep

@@ -105,3 +105,35 @@ def test_batch_recipe_against_oracle(hg, orc):
         assert infos[b]["c"] == pytest.approx(c, rel=1e-12)
         run = orc.run(w, x, T=p.T, c=c, seed=p.seed, keep=True)
         compare(e[offs[b]:offs[b + 1]], run)
+
+
+def test_batch_full_recipe_largest_against_oracle(hg, orc):
+    """The benchmark's 256-instance recipe at its real sizes (n up to 10^6),
+    FP32 filter with FP64 recheck (the reported leg): equal to the FP64 batch
+    bit for bit, and its three largest instances plus three others against the
+    oracle on the GPU's points and constants."""
+    import bench
+    from tests.parity import compare_large
+    Pm = bench.batch_params(hg, dict(batch=256, master_seed=5), 1)
+    Pf = bench.batch_params(hg, dict(batch=256, master_seed=5), 0)
+    print(f"[batch] recipe: {len(Pm)} instances, n total {sum(p.n for p in Pm)}", flush=True)
+    em, om, im = hg.generate_batch(Pm)
+    ef, of, _ = hg.generate_batch(Pf)
+    assert om == of
+    import torch
+    assert torch.equal(em, ef)
+    e = em.cpu().numpy().view(np.uint32)
+    del ef
+    order = sorted(range(len(Pm)), key=lambda b: -Pm[b].n)
+    pick = order[:3] + order[60:256:80]
+    for b in pick:
+        p = Pm[b]
+        print(f"[batch] instance {b}: n={p.n} d={p.d} beta={p.beta:.3f} T={p.T} deg={p.avg_deg:.2f}",
+              flush=True)
+        wd, xd = hg.points(p.n, p.d, p.beta, seed=p.seed)
+        w, x = wd.cpu().numpy(), np.ascontiguousarray(xd.cpu().numpy().T)
+        assert im[b]["c"] == pytest.approx(orc.solve_c(w, p.d, p.T, p.avg_deg), rel=1e-12)
+        run = orc.run(w, x, T=p.T, c=im[b]["c"], seed=p.seed, keep=True)
+        rep = compare_large(e[om[b]:om[b + 1]], run, info=im[b])
+        assert rep["gpu"] == om[b + 1] - om[b]
+        run.close()

@@ -5,9 +5,16 @@ and the mixed-precision path against the FP64 path bit for bit."""
 import numpy as np
 import pytest
 
-from tests.parity import compare
+from tests.parity import compare, level3_sample
 
 pytestmark = pytest.mark.gpu
+
+
+def gpu_points(hg, n, d, beta, seed):
+    """The GPU's points (the kernel girg_generate runs), on the host as the
+    oracle takes them: w (n,), x (n, d)."""
+    w, x = hg.points(n, d, beta, seed=seed)
+    return w.cpu().numpy(), np.ascontiguousarray(x.cpu().numpy().T)
 
 
 @pytest.fixture(scope="module")
@@ -20,47 +27,16 @@ def hg():
     return hg
 
 
-def level3_sample(edges, x, run, mod: int):
-    """Edges of the items the oracle samples with filter_level = 3 and
-    filter_mod = mod, filter_rem = 0: every item above level 3, and below it
-    those whose A-side level-3 ancestor is 0 mod `mod`.  An item of a pair
-    (u, v) sits above level 3 when CL(i, j) < 3 or the level-2 cells of u and
-    v are not neighbours (the pair became distant earlier); otherwise its
-    A side at level 3 is the smaller level-3 cell of u and v (A <= B is kept
-    by every descendant).  edges (m, 2) and x (d, n) are device tensors."""
-    import torch
-    dev = edges.device
-    d = x.shape[0]
-    n = x.shape[1]
-    layer = np.empty(n, dtype=np.int64)
-    layer[run.sorted_ids.astype(np.int64)] = np.repeat(np.arange(64), run.count.astype(np.int64))
-    layer = torch.from_numpy(layer).to(dev)
-    CL = torch.from_numpy(run.CL.astype(np.int64)).to(dev)
-    c3 = (x * 8.0).long()
-    m3 = torch.zeros(n, dtype=torch.int64, device=dev)
-    for b in (2, 1, 0):  # coarse to fine, dimension 0 most significant
-        for k in range(d):
-            m3 = (m3 << 1) | ((c3[k] >> b) & 1)
-    u = edges[:, 0].long()
-    v = edges[:, 1].long()
-    far2 = torch.zeros(len(u), dtype=torch.bool, device=dev)
-    for k in range(d):
-        far2 |= torch.remainder((c3[k] >> 1)[u] - (c3[k] >> 1)[v], 4) == 2
-    keep = (CL[layer[u], layer[v]] < 3) | far2 | (torch.remainder(torch.minimum(m3[u], m3[v]), mod) == 0)
-    return edges[keep]
-
-
 def test_fullsize_girg_d2_n2p20(hg, orc):
     """GIRG d = 2, n = 2^20, beta = 2.7, T = 0.5, average degree 16, seed 2:
     the whole edge set."""
     n, d, beta, T, deg, seed = 2**20, 2, 2.7, 0.5, 16.0, 2
     print(f"[fullsize] girg n={n} d={d} T={T}", flush=True)
     res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
-    w, x = orc.points_girg(n, d, beta, seed)
-    c = orc.solve_c(w, d, T, deg)
-    assert res.info["c"] == pytest.approx(c, rel=1e-12)
-    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True)
-    rep = compare(res.edges.cpu().numpy().view(np.uint32), run)
+    w, x = gpu_points(hg, n, d, beta, seed)
+    assert res.info["c"] == pytest.approx(orc.solve_c(w, d, T, deg), rel=1e-12)
+    run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True)
+    rep = compare(res.edges.cpu().numpy().view(np.uint32), run, info=res.info)
     assert rep["gpu"] > 7 * n
     assert res.info["tests"] == run.stats["tests"]
     assert res.info["draws"] == run.stats["draws"]
@@ -77,24 +53,25 @@ def test_fullsize_hrg_n2p20(hg, orc):
     assert res.info["R"] == pytest.approx(R, rel=1e-6)
     # the sampler's R (its own quadrature) decides the graph: run the oracle on it
     R = res.info["R"]
-    r, x = orc.points_hrg(n, alpha, R, seed)
-    run = orc.run(r, x, T=T, model=1, R=R, alpha=alpha, seed=seed, keep=True)
-    rep = compare(res.edges.cpu().numpy().view(np.uint32), run)
+    r, x = hg.points(n, model=1, alpha=alpha, R=R, seed=seed)
+    run = orc.run(r.cpu().numpy(), x.cpu().numpy().T, T=T, model=1, R=R, alpha=alpha, seed=seed, keep=True)
+    rep = compare(res.edges.cpu().numpy().view(np.uint32), run, info=res.info)
     assert rep["gpu"] > 4 * n
 
 
 def test_fullsize_girg_d3_n1e7_sampled(hg, orc):
-    """GIRG d = 3, n = 10^7, beta = 2.3, T = 0.8, average degree 20, seed 4:
-    every item above level 3 and 1/512 of the level-3 subtrees."""
+    """GIRG d = 3, n = 10^7, beta = 2.3, T = 0.8, average degree 20, seed 4,
+    the FP32 filter with FP64 recheck (the benchmark's reported leg): every
+    item above level 3 and 1/512 of the level-3 subtrees."""
     import torch
     n, d, beta, T, deg, seed = 10**7, 3, 2.3, 0.8, 20.0, 4
     print(f"[fullsize] girg n={n} d={d} T={T} sampled", flush=True)
-    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
-    w, x = orc.points_girg(n, d, beta, seed)
-    c = orc.solve_c(w, d, T, deg)
-    assert res.info["c"] == pytest.approx(c, rel=1e-12)
-    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True, filter_level=3, filter_mod=512, filter_rem=0)
-    xd = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed, precision=1)
+    wd, xd = hg.points(n, d, beta, seed=seed)
+    w, x = wd.cpu().numpy(), np.ascontiguousarray(xd.cpu().numpy().T)
+    assert res.info["c"] == pytest.approx(orc.solve_c(w, d, T, deg), rel=1e-12)
+    run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True, filter_level=3, filter_mod=512,
+                  filter_rem=0)
     sub = level3_sample(res.edges, xd, run, 512)
     rep = compare(sub.cpu().numpy().view(np.uint32), run)
     assert rep["oracle"] > 10**6
@@ -115,3 +92,25 @@ def test_fullsize_mixed_equals_fp64_d3_n1e7(hg):
     assert 0 < b.info["rechecks"] < b.info["tests"] + b.info["draws"] + b.info["candidates"]
     for k in ("tests", "draws", "candidates", "type1_edges", "type2_edges"):
         assert a.info[k] == b.info[k], k
+
+
+def test_fullsize_girg_d3_n1e7_whole(hg):
+    """GIRG d = 3, n = 10^7, beta = 2.3, T = 0.8, average degree 20, seed 4,
+    the FP32 filter with FP64 recheck: the whole edge set (about 10^8 edges)
+    against the oracle on the GPU's points and c, the oracle's run split over
+    host processes (level-3 subtrees plus the levels above)."""
+    from tests.oracle_pool import run_whole, workers
+    from tests.parity import compare_large
+    n, d, beta, T, deg, seed = 10**7, 3, 2.3, 0.8, 20.0, 4
+    print(f"[fullsize] girg n={n} d={d} T={T} whole, {workers()} oracle processes", flush=True)
+    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed, precision=1)
+    ge = res.edges.cpu().numpy().view(np.uint32)
+    w, x = gpu_points(hg, n, d, beta, seed)
+    run = run_whole(w, x, level=3, nparts=32, T=T, c=res.info["c"], seed=seed)
+    print(f"[fullsize] oracle: {len(run.edges)} edges, {len(run.near)} near, {len(run.ties)} tie items",
+          flush=True)
+    rep = compare_large(ge, run, info=res.info)
+    print(f"[fullsize] {rep}", flush=True)
+    assert rep["gpu"] > 5 * n
+    for k in ("tests", "draws", "candidates"):
+        assert res.info[k] == run.stats[k], k

@@ -53,8 +53,11 @@ def test_threshold_from_points(hg, orc, d, n, beta, seed):
     x = synth.positions(n, d, seed)
     c = orc.solve_c(w, d, 0.0, 10.0)
     ge, info, run = run_both(hg, orc, w, x, T=0.0, c=c, seed=seed)
-    rep = compare(ge, run)
+    rep = compare(ge, run, info=info)
     assert info["L"] == run.stats["L"] and info["D"] == run.stats["D"]
+    # W: the GPU's sum (double-double) and the oracle's plain ascending sum
+    # differ at most by the latter's rounding, (n - 1) u W
+    assert abs(info["W"] - run.stats["W"]) <= (n - 1) * 2.0**-53 * run.stats["W"]
     assert rep["gpu"] > n
 
 
@@ -65,7 +68,7 @@ def test_binomial_from_points(hg, orc, d, n, T, seed):
     x = synth.positions(n, d, seed)
     c = orc.solve_c(w, d, T, 12.0)
     ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=seed)
-    rep = compare(ge, run)
+    rep = compare(ge, run, info=info)
     assert info["tests"] == run.stats["tests"]
     assert info["draws"] == run.stats["draws"]
     assert info["candidates"] == run.stats["candidates"]
@@ -79,7 +82,7 @@ def test_binomial_level_knobs(hg, orc, bias, depth):
     x = synth.clustered_positions(n, d, 5)
     c = orc.solve_c(w, d, T, 14.0)
     ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=5, cl_bias=bias, max_depth=depth)
-    compare(ge, run)
+    compare(ge, run, info=info)
 
 
 def test_heavy_items_split_into_segments(hg, orc):
@@ -90,7 +93,7 @@ def test_heavy_items_split_into_segments(hg, orc):
     c = orc.solve_c(w, d, T, 20.0)
     ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=6)
     assert info["heavy_items"] > 0
-    compare(ge, run)
+    compare(ge, run, info=info)
     assert info["draws"] == run.stats["draws"]
 
 
@@ -101,31 +104,36 @@ def test_hrg_from_points(hg, orc, T):
     r = synth.hrg_radii(n, alpha, R, 3)
     x = synth.positions(n, 1, 3)
     ge, info, run = run_both(hg, orc, r, x, T=T, c=0.0, seed=3, model=1, R=R, alpha=alpha)
-    compare(ge, run)
+    compare(ge, run, info=info)
+
+
+def gpu_points(hg, n, d, beta, seed):
+    """The GPU's points (the same kernel girg_generate runs), on the host as
+    the oracle takes them: w (n,), x (n, d)."""
+    w, x = hg.points(n, d, beta, seed=seed)
+    return w.cpu().numpy(), np.ascontiguousarray(x.cpu().numpy().T)
 
 
 def test_generate_end_to_end_config1(hg, orc):
     """n = 10^4, d = 1, beta = 2.5, T = 0, average degree 10, seed 1: the GPU
-    generates points, solves c and samples; the oracle does the same on its
-    own; edge sets agree."""
+    generates points, solves c and samples; the oracle samples the GPU's
+    points with the GPU's c (its own c solve agrees to 1e-12); edge sets agree."""
     res = hg.generate(10**4, d=1, beta=2.5, T=0.0, avg_deg=10.0, seed=1)
     ge = res.edges.cpu().numpy().view(np.uint32)
-    w, x = orc.points_girg(10**4, 1, 2.5, 1)
-    c = orc.solve_c(w, 1, 0.0, 10.0)
-    assert res.info["c"] == pytest.approx(c, rel=1e-12)
-    run = orc.run(w, x, T=0.0, c=c, seed=1, keep=True)
-    compare(ge, run)
+    w, x = gpu_points(hg, 10**4, 1, 2.5, 1)
+    assert res.info["c"] == pytest.approx(orc.solve_c(w, 1, 0.0, 10.0), rel=1e-12)
+    run = orc.run(w, x, T=0.0, c=res.info["c"], seed=1, keep=True)
+    compare(ge, run, info=res.info)
 
 
 def test_generate_end_to_end_binomial(hg, orc):
     n, d, beta, T, deg, seed = 2**15, 2, 2.7, 0.5, 16.0, 2
     res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
     ge = res.edges.cpu().numpy().view(np.uint32)
-    w, x = orc.points_girg(n, d, beta, seed)
-    c = orc.solve_c(w, d, T, deg)
-    assert res.info["c"] == pytest.approx(c, rel=1e-12)
-    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True)
-    compare(ge, run)
+    w, x = gpu_points(hg, n, d, beta, seed)
+    assert res.info["c"] == pytest.approx(orc.solve_c(w, d, T, deg), rel=1e-12)
+    run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True)
+    compare(ge, run, info=res.info)
 
 
 def test_deterministic_output(hg):
@@ -164,7 +172,7 @@ def test_empty_and_tiny_graphs(hg, orc):
         w = synth.pareto_weights(n, 2.5, n)
         x = synth.positions(n, 2, n)
         ge, info, run = run_both(hg, orc, w, x, T=0.5, c=0.05, seed=1)
-        compare(ge, run)
+        compare(ge, run, info=info)
     # a graph with no edges at all
     w = np.ones(64)
     x = synth.positions(64, 3, 1)
@@ -183,7 +191,7 @@ def test_torus_seam(hg, orc, T, d):
     x = synth.seam_positions(n, d, 17, width=2.0**-4)
     c = orc.solve_c(w, d, T, 10.0) / 8.0
     ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=17)
-    compare(ge, run)
+    compare(ge, run, info=info)
     assert info["tests"] == run.stats["tests"] and info["draws"] == run.stats["draws"]
     # a share of the edges joins the two sides of the seam (7-53 % here)
     e = ge.astype(np.int64)
@@ -203,7 +211,7 @@ def test_degenerate_one_point_one_layer(hg, orc, T, d):
     w = np.full(n, 3.0)
     x = np.full((n, d), 0.3125)
     ge, info, run = run_both(hg, orc, w, x, T=T, c=0.5, seed=7)
-    compare(ge, run)
+    compare(ge, run, info=info)
     assert len(ge) == n * (n - 1) // 2
     assert info["split_items"] > 0
     pairs = np.sort(ge.astype(np.int64), axis=1)
@@ -235,7 +243,7 @@ def test_mixed_precision_from_points(hg, orc, d, T, seed):
     x = synth.clustered_positions(n, d, seed)
     c = orc.solve_c(w, d, T, 14.0)
     ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=seed, precision=1)
-    compare(ge, run)
+    compare(ge, run, info=info)
     assert info["rechecks"] > 0
     assert info["draws"] == run.stats["draws"]
     assert info["candidates"] == run.stats["candidates"]
@@ -256,8 +264,7 @@ def test_c_solve_with_a_large_heavy_tail(hg, orc, n, d, beta, T, deg, seed):
     """Heavy tails whose E_R reaches far below the heaviest layers: the device
     c solve must grow its tail and still agree with the oracle."""
     res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed)
-    w, x = orc.points_girg(n, d, beta, seed)
-    c = orc.solve_c(w, d, T, deg)
-    assert res.info["c"] == pytest.approx(c, rel=1e-12)
-    run = orc.run(w, x, T=T, c=c, seed=seed, keep=True)
-    compare(res.edges.cpu().numpy().view(np.uint32), run)
+    w, x = gpu_points(hg, n, d, beta, seed)
+    assert res.info["c"] == pytest.approx(orc.solve_c(w, d, T, deg), rel=1e-12)
+    run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True)
+    compare(res.edges.cpu().numpy().view(np.uint32), run, info=res.info)
