@@ -345,17 +345,28 @@ def sweep(steps: int, warmup: int) -> int:
 
 
 def coupling(n: int = 10**6, deg: float = 100.0, alpha: float = 0.75, seed: int = 11) -> int:
-    """The HRG / GIRG comparison of the paper's Sec. 5.3 (threshold variants):
-    an HRG with average degree `deg` and the GIRG on the same points through
-    the mapping of Sec. 2.3 (w = exp((R - r) / 2), x = angle / 2 pi, d = 1).
-    Reports the edges the GIRG of expected degree `deg` lacks (HRG \ GIRG)
-    and adds (GIRG \ HRG), the largest GIRG degree whose graph is a subgraph
-    of the HRG (bisection; GIRG edge sets grow with c), and the smallest
-    degree of a supergraph (from the largest c any HRG edge needs: r <=
-    c w_u w_v / W).  One JSON line."""
+    """The HRG / GIRG comparison of the paper's Sec. 5.3 (threshold variants),
+    as one JSON line (see coupling_counts)."""
+    t_start = time.perf_counter()
+    out = coupling_counts(n, deg, alpha, seed)
+    out.pop("_inputs", None)
+    out["seconds"] = time.perf_counter() - t_start
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def coupling_counts(n: int, deg: float, alpha: float = 0.75, seed: int = 11) -> dict:
+    """An HRG (threshold) with average degree `deg` and the GIRG (threshold,
+    d = 1) on the same points through the mapping of Sec. 2.3 (w =
+    exp((R - r) / 2), x = angle / 2 pi).  Counts the edges the GIRG of
+    expected degree `deg` lacks (HRG minus GIRG) and adds (GIRG minus HRG),
+    the same for the GIRG whose expected degree is the HRG's realised one, the
+    largest GIRG degree whose graph is a subgraph of the HRG (bisection; GIRG
+    edge sets grow with c), and the smallest degree of a supergraph (from the
+    largest c any HRG edge needs: r <= c w_u w_v / W).  `_inputs` holds the
+    points and constants, for checks against the oracle."""
     import torch
     import paper_1905_06706_amd as hg
-    t_start = time.perf_counter()
     R = hg.hrg_solve_R(n, alpha, 0.0, deg)
     r, x = hg.points(n, model=1, alpha=alpha, R=R, seed=seed)
     eh = hg.from_points(r, x, T=0.0, model=1, R=R, alpha=alpha, seed=seed).edges.long()
@@ -383,16 +394,17 @@ def coupling(n: int = 10**6, deg: float = 100.0, alpha: float = 0.75, seed: int 
         i = torch.searchsorted(b, a).clamp(max=len(b) - 1)
         return int((b[i] != a).sum())
 
-    kg, c100 = girg_keys(avg_deg=deg)
+    kg, c_deg = girg_keys(avg_deg=deg)
     missing = count_not_in(kh, kg)
     additional = count_not_in(kg, kh)
     # largest degree with GIRG subset of HRG: bisection on the expected degree
     lo, hi = 0.01 * deg, deg
+    c_sub = 0.0
     for _ in range(24):
         mid = (lo * hi) ** 0.5
-        km, _ = girg_keys(avg_deg=mid)
+        km, cm = girg_keys(avg_deg=mid)
         if count_not_in(km, kh) == 0:
-            lo = mid
+            lo, c_sub = mid, cm
         else:
             hi = mid
     d_sub = lo
@@ -408,15 +420,13 @@ def coupling(n: int = 10**6, deg: float = 100.0, alpha: float = 0.75, seed: int 
     matched = {"girg_expected_degree": d_hrg, "girg_c": cm, "girg_edges": len(km),
                "missing_hrg_minus_girg": count_not_in(kh, km),
                "additional_girg_minus_hrg": count_not_in(km, kh)}
-    out = {"experiment": "HRG vs GIRG coupling (threshold variants)", "n": n, "alpha": alpha,
-           "beta": 2 * alpha + 1, "R": R, "seed": seed, "hrg_edges": len(kh), "hrg_avg_degree": d_hrg,
-           "girg_expected_degree": deg, "girg_c": c100, "girg_edges": len(kg),
-           "missing_hrg_minus_girg": missing, "additional_girg_minus_hrg": additional,
-           "subgraph_expected_degree": d_sub, "supergraph_c": c_super,
-           "supergraph_expected_degree": D_super, "at_hrg_degree": matched,
-           "seconds": time.perf_counter() - t_start}
-    print(json.dumps(out), flush=True)
-    return 0
+    return {"experiment": "HRG vs GIRG coupling (threshold variants)", "n": n, "alpha": alpha,
+            "beta": 2 * alpha + 1, "R": R, "seed": seed, "hrg_edges": len(kh), "hrg_avg_degree": d_hrg,
+            "girg_expected_degree": deg, "girg_c": c_deg, "girg_edges": len(kg),
+            "missing_hrg_minus_girg": missing, "additional_girg_minus_hrg": additional,
+            "subgraph_expected_degree": d_sub, "subgraph_c": c_sub, "supergraph_c": c_super,
+            "supergraph_expected_degree": D_super, "at_hrg_degree": matched,
+            "_inputs": {"r": r, "x": x, "w": w}}
 
 
 def hbm_copy(mib: int, steps: int, warmup: int) -> int:
@@ -558,6 +568,9 @@ def main() -> int:
     is_batch = "batch" in wl
 
     # per leg: the call, an output buffer sized by a first (counting) call
+    # (for a kernel trace every call runs its passes one after another)
+    if args.kernels_only:
+        hg.set_profiling(True, serial=True)
     L = {}
     for q in legs:
         call = make_call(hg, wl, q)

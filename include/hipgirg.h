@@ -39,7 +39,9 @@ typedef enum {
   GIRG_ENOMEM = -2,    /* device or host allocation failed */
   GIRG_EDEVICE = -3,   /* a HIP call failed (no device, launch failure) */
   GIRG_EOVERFLOW = -4, /* edge capacity too small: *m_out holds the edge count
-                          needed; the edge buffer contents are undefined */
+                          needed and *info the call's diagnostics; the edge
+                          buffer contents are undefined.  A null buffer with
+                          capacity 0 thus counts a graph without storing it */
   GIRG_ENOCONV = -5    /* the c or R solve found no bracket */
 } girg_status;
 
@@ -174,7 +176,9 @@ girg_status hrg_expected_degree(uint64_t n, double alpha, double T, double R, do
  * run concurrently, each on a worker with its own device scratch and
  * non-blocking stream (the tuned worker count, 16 by default; the
  * environment variable GIRG_BATCH_WORKERS = 1..64 overrides the table);
- * `stream` orders only the final placement of the edges. */
+ * the workers' streams start after the work queued on `stream` before the
+ * call, and the edges are put in instance order on `stream`; the call
+ * returns when they are in place. */
 girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* edges, uint64_t cap,
                                 uint64_t* offsets, girg_info* infos, void* stream);
 

@@ -1112,25 +1112,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(rb.add(&nrec, nrec_d, sizeof(nrec)));
   HIPCHK(rb.add(stt, cx.stats, sizeof(stt)));
   HIPCHK(rb.wait());
-  *m_out = mtot;
-  if (info) info->m = mtot;
-  if (mtot > cap) {
-    cx.collect();  // stage times of a counting call (null buffer, capacity 0)
-    return fail(GIRG_EOVERFLOW, "edge capacity too small");
-  }
-  if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
-  if (place) edges = (*place)(mtot);
-
-  // staged blocks to their places: chunk start + edges of the chunk before
-  if (nrec && edges) {
-    const ChunkBases cbs{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot}};
-    HIPCHK(launch_stage_copy(stage, rtag, roff, rpos, rcnt, nrec, cbs, mtot,
-                             reinterpret_cast<uint2*>(edges), st));
-    cx.mark("order", st);
-  }
-
-  HIPCHK(hipStreamSynchronize(st));
-  cx.collect();
+  // the diagnostics (also for a counting call, which ends with GIRG_EOVERFLOW)
   if (info) {
     for (int q = 0; q < 4; ++q) info->pass_edges[q] = stt[8 + q];
     info->pass_work[0] = stt[0];
@@ -1157,6 +1139,25 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     info->L = g.L;
     info->D = g.D;
   }
+  *m_out = mtot;
+  if (info) info->m = mtot;
+  if (mtot > cap) {
+    cx.collect();  // stage times of a counting call (null buffer, capacity 0)
+    return fail(GIRG_EOVERFLOW, "edge capacity too small");
+  }
+  if (nrec > rcap) return fail(GIRG_ENOMEM, "edge staging records overflowed");
+  if (place) edges = (*place)(mtot);
+
+  // staged blocks to their places: chunk start + edges of the chunk before
+  if (nrec && edges) {
+    const ChunkBases cbs{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot}};
+    HIPCHK(launch_stage_copy(stage, rtag, roff, rpos, rcnt, nrec, cbs, mtot,
+                             reinterpret_cast<uint2*>(edges), st));
+    cx.mark("order", st);
+  }
+
+  HIPCHK(hipStreamSynchronize(st));
+  cx.collect();
   return GIRG_OK;
 }
 
@@ -1307,6 +1308,16 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   }
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
+  // the workers' streams start after the work queued on the caller's stream
+  // so far (the edge buffer may be memory that work still reads or writes)
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipEvent_t start_ev = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } start_guard{start_ev};
+  HIPCHK(hipEventRecord(start_ev, hs));
   // instances run concurrently, one per worker, each on its own context and
   // stream; an instance's edges go to the caller's buffer at a position
   // reserved once its count is known (completion order), and are put into
@@ -1321,6 +1332,16 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   std::vector<std::string> msg(count);
   auto worker = [&](int slot) {
     (void)hipSetDevice(dev);
+    Ctx* wcx = nullptr;
+    if (get_ctx(&wcx, slot) != GIRG_OK || hipStreamWaitEvent(wcx->own, start_ev, 0) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(cur_mu);
+      if (!stop.load()) {
+        st[0] = GIRG_EDEVICE;
+        msg[0] = "batch worker set-up failed";
+      }
+      stop.store(true);
+      return;
+    }
     for (;;) {
       if (stop.load()) return;
       const int32_t b = next.fetch_add(1);
@@ -1361,23 +1382,29 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   for (int32_t b = 0; b < count; ++b) offsets[b + 1] = offsets[b] + m[b];
   const uint64_t total = offsets[count];
   if (total > cap) return fail(GIRG_EOVERFLOW, "edge capacity too small");
-  // completion order -> instance order
-  hipStream_t hs = static_cast<hipStream_t>(stream);
+  // completion order -> instance order, through a copy in the scratch arena
+  // of the batch's first worker (cached from call to call); the caller's
+  // stream waits for the workers' streams first
   bool same = true;
   for (int32_t b = 0; b < count; ++b) same = same && pos[b] == offsets[b];
   if (!same && total) {
-    uint32_t* tmp = nullptr;
-    HIPCHK(hipMalloc(&tmp, total * 2 * sizeof(uint32_t)));
-    girg_status s = GIRG_OK;
+    CtxLock cl;
+    girg_status s = lock_ctx(&cl, 1);
+    if (s != GIRG_OK) return s;
+    uint32_t* tmp = cl.cx->ar.get<uint32_t>(total * 2);
+    if (!tmp) return fail(GIRG_ENOMEM, "batch reorder: scratch allocation failed");
+    for (int k = 0; k < nw; ++k) {
+      Ctx* wcx = nullptr;
+      if ((s = get_ctx(&wcx, k + 1)) != GIRG_OK) return s;
+      HIPCHK(hipStreamSynchronize(wcx->own));
+    }
     hipError_t e = hipMemcpyAsync(tmp, edges, total * 2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, hs);
     for (int32_t b = 0; b < count && e == hipSuccess; ++b)
       if (m[b])
         e = hipMemcpyAsync(edges + 2 * offsets[b], tmp + 2 * pos[b], m[b] * 2 * sizeof(uint32_t),
                            hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
-    if (e != hipSuccess) s = fail(GIRG_EDEVICE, std::string("batch reorder: ") + hipGetErrorString(e));
-    (void)hipFree(tmp);
-    return s;
+    if (e != hipSuccess) return fail(GIRG_EDEVICE, std::string("batch reorder: ") + hipGetErrorString(e));
   }
   return GIRG_OK;
 }

@@ -137,3 +137,30 @@ def test_batch_full_recipe_largest_against_oracle(hg, orc):
         rep = compare_large(e[om[b]:om[b + 1]], run, info=im[b])
         assert rep["gpu"] == om[b + 1] - om[b]
         run.close()
+
+
+def test_batch_waits_for_the_callers_stream(hg):
+    """Work queued on the caller's stream before the call (here a long chain of
+    kernels that ends by filling the edge buffer with -1) finishes before any
+    instance writes an edge: the batch's workers wait for that stream."""
+    import torch
+    P = mixed_params(hg)[:6]
+    ref, roffs, _ = hg.generate_batch(P)
+    total = roffs[-1]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        buf = torch.empty((total, 2), dtype=torch.int32, device="cuda")
+        x = torch.ones(1 << 26, device="cuda")
+        for _ in range(40):
+            x = x * 1.0001 + 0.5
+        buf.fill_(-1)
+    L = hg.load()
+    arr = (hg.Params * len(P))(*P)
+    offs = (ctypes.c_uint64 * (len(P) + 1))()
+    st = L.girg_generate_batch(arr, len(P), ctypes.c_void_p(buf.data_ptr()), total, offs, None,
+                               ctypes.c_void_p(s.cuda_stream))
+    assert st == hg.GIRG_OK
+    torch.cuda.synchronize()
+    assert list(offs) == roffs
+    assert torch.equal(buf, ref)
+    del x
