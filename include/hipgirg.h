@@ -138,6 +138,25 @@ girg_status girg_from_points(const girg_params* p, const double* w, const double
                              uint32_t* edges, uint64_t cap, uint64_t* m_out, girg_info* info,
                              void* stream);
 
+/* girg_from_points_noalloc: girg_from_points for callers that cannot allocate
+ * device memory (code under HIP graph capture around it, tight serving loops,
+ * harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating routine.  Every device buffer of the call
+ * lies in one fixed array of 512 MiB of device memory that each GPU holds from
+ * the library's first use on it until the process ends; the first call on a
+ * device looks up that GPU's copy of the array.  Same arguments, edges and
+ * info as girg_from_points, with these limits: n <= 2^20, cap <= 2^24 edges,
+ * c > 0 given (GIRG; solving c needs host buffers) or R > 0 (HRG); profiling
+ * is not recorded.  GIRG_EINVAL for a limit exceeded; GIRG_ENOMEM when the
+ * graph's scratch needs more than the array (message says so).  The array
+ * keeps the last call's contents; every call clears what must start at zero.
+ * Calls on one device share the array: they run one at a time (a lock) and
+ * return only after their work on the GPU has ended, so they never overlap;
+ * a caller's own kernels must not touch the array's contents. */
+girg_status girg_from_points_noalloc(const girg_params* p, const double* w, const double* x,
+                                     uint32_t* edges, uint64_t cap, uint64_t* m_out,
+                                     girg_info* info, void* stream);
+
 /* girg_points: only the point generation of the models.  GIRG (Sec. 2.1):
  * weights of a power law with exponent beta, drawn as Pareto w = S^(-1/(beta-1))
  * with w_min = 1 (the paper fixes no sampler), positions uniform on the torus

@@ -23,7 +23,8 @@ GIRG_OK, GIRG_EINVAL, GIRG_ENOMEM, GIRG_EDEVICE, GIRG_EOVERFLOW, GIRG_ENOCONV = 
 _STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ENOCONV"}
 
 EXPORTS = (
-    "girg_generate", "girg_hrg", "girg_from_points", "girg_points", "girg_solve_c",
+    "girg_generate", "girg_hrg", "girg_from_points", "girg_from_points_noalloc", "girg_points",
+    "girg_solve_c",
     "girg_expected_degree", "hrg_solve_R", "hrg_expected_degree", "girg_generate_batch",
     "girg_release", "girg_last_error", "girg_version", "girg_set_profiling", "girg_stage_times",
     "girg_autotune", "girg_autotune_batch", "girg_tuning_get", "girg_tuning_set", "girg_tuning_save",
@@ -94,6 +95,7 @@ def load() -> ctypes.CDLL:
     L.girg_generate.argtypes = [P(Params), vp, u64, P(u64), P(Info), vp]
     L.girg_hrg.argtypes = [u64, dbl, dbl, dbl, dbl, u64, vp, u64, P(u64), P(Info), vp]
     L.girg_from_points.argtypes = [P(Params), vp, vp, vp, u64, P(u64), P(Info), vp]
+    L.girg_from_points_noalloc.argtypes = [P(Params), vp, vp, vp, u64, P(u64), P(Info), vp]
     L.girg_points.argtypes = [P(Params), vp, vp, vp]
     L.girg_solve_c.argtypes = [vp, u64, ctypes.c_int32, dbl, dbl, P(dbl)]
     L.girg_expected_degree.argtypes = [vp, u64, ctypes.c_int32, dbl, dbl, P(dbl)]
@@ -223,6 +225,26 @@ def from_points(w, x, T: float, c: float = 0.0, avg_deg: float = 0.0, seed: int 
     return _run_with_capacity(
         lambda e, k, m, i: L.girg_from_points(ctypes.byref(p), wp, xp, e, k, m, i, s), cap, w.device,
         stream)
+
+
+def from_points_noalloc(w, x, edges, T: float, c: float = 0.0, seed: int = 0, model: int = 0,
+                        alpha: float = 0.0, R: float = 0.0, precision: int = 0, max_depth: int = -1,
+                        cl_bias: int = 0, stream=None) -> tuple:
+    """girg_from_points_noalloc into a caller-provided edge buffer `edges`
+    (int32 (cap, 2) device tensor): returns (m, info); GirgError on overflow."""
+    L = load()
+    assert w.element_size() == 8 and w.is_contiguous()
+    assert x.element_size() == 8 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == w.shape[0]
+    assert edges.dtype.itemsize == 4 and edges.is_contiguous() and edges.dim() == 2 and edges.shape[1] == 2
+    n, d = int(w.shape[0]), int(x.shape[0])
+    p = make_params(n, d, 0.0, T, 0.0, c, seed, precision, max_depth, cl_bias, model, alpha, R)
+    m = ctypes.c_uint64(0)
+    info = Info()
+    _check(L.girg_from_points_noalloc(ctypes.byref(p), ctypes.c_void_p(w.data_ptr()),
+                                      ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(edges.data_ptr()),
+                                      int(edges.shape[0]), ctypes.byref(m), ctypes.byref(info),
+                                      _stream(stream)))
+    return int(m.value), info.as_dict()
 
 
 def points(n: int, d: int = 1, beta: float = 2.5, seed: int = 0, model: int = 0,

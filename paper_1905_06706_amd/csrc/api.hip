@@ -53,6 +53,15 @@ static girg_status fail(girg_status s, const std::string& msg) {
 void* Arena::raw(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (bytes == 0) bytes = 256;
+  if (ext_base_) {
+    if (failed_ || ext_size_ - ext_used_ < bytes) {
+      failed_ = true;
+      return nullptr;
+    }
+    void* p = ext_base_ + ext_used_;
+    ext_used_ += bytes;
+    return p;
+  }
   for (size_t c = cur_; c < chunks_.size(); ++c) {
     Chunk& ch = chunks_[c];
     if (ch.size - ch.used >= bytes) {
@@ -74,6 +83,8 @@ void* Arena::raw(size_t bytes) {
   return p;
 }
 void Arena::release() {
+  ext_base_ = nullptr;  // an attached buffer belongs to its owner
+  ext_size_ = ext_used_ = 0;
   for (auto& c : chunks_) (void)hipFree(c.base);
   chunks_.clear();
   cur_ = 0;
@@ -84,6 +95,10 @@ void Arena::release() {
 // ---------------------------------------------------------------------------
 struct Ctx {
   int device = -1;
+  // external: the device buffers below (and the arena) lie in memory the
+  // context does not own (the no-allocation entry point's scratch array);
+  // fixed_tuning: the built-in launch shapes, not the tuning table
+  bool external = false, fixed_tuning = false;
   Arena ar;
   Graph* gd = nullptr;       // device Graph
   double* red = nullptr;     // 6 doubles
@@ -105,6 +120,9 @@ struct Ctx {
     void* pin = nullptr;
     size_t pin_size = 0;
     void* pin_up = nullptr;  // uploads (the 40 KB Graph among them)
+    // direct: no pinned buffers; copies go straight to and from the pageable
+    // host memory of their sources and destinations (nothing is allocated)
+    bool direct = false;
     Pins() = default;
     Pins(const Pins&) = delete;
     Pins& operator=(const Pins&) = delete;
@@ -155,6 +173,10 @@ struct Ctx {
     ev_name.clear();
   }
   ~Ctx() {
+    if (external) {
+      ar.release();
+      return;
+    }
     if (gd) (void)hipFree(gd);
     if (red) (void)hipFree(red);
     if (flag) (void)hipFree(flag);
@@ -185,15 +207,16 @@ class Readback {
   // a call that returns early (an error) may leave copies in flight that
   // read or write the pinned buffers: drain them before the buffers are reused
   ~Readback() {
-    if (!items_.empty() || up_used_) (void)hipStreamSynchronize(st_);
+    if (nitems_ || up_used_) (void)hipStreamSynchronize(st_);
   }
   hipError_t begin(size_t bytes) {
-    if (!items_.empty()) {
+    if (nitems_) {
       hipError_t e = hipStreamSynchronize(st_);  // an unfinished group: let it land first
       if (e != hipSuccess) return e;
     }
-    items_.clear();
+    nitems_ = 0;
     used_ = 0;
+    if (cx_.direct) return hipSuccess;
     bytes = (bytes + 4095) & ~(size_t)4095;
     if (bytes <= cx_.pin_size) return hipSuccess;
     if (cx_.pin) (void)hipHostFree(cx_.pin);
@@ -204,9 +227,14 @@ class Readback {
     return e;
   }
   hipError_t add(void* dst, const void* src, size_t bytes) {
+    if (nitems_ == kMaxItems) return hipErrorInvalidValue;  // a group holds at most kMaxItems copies
+    if (cx_.direct) {
+      items_[nitems_++] = Item{nullptr, 0, 0};
+      return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st_);
+    }
     const size_t off = (used_ + 15) & ~(size_t)15;
     if (off + bytes > cx_.pin_size) return hipErrorInvalidValue;  // begin() reserved too little
-    items_.push_back(Item{dst, off, bytes});
+    items_[nitems_++] = Item{dst, off, bytes};
     used_ = off + bytes;
     return hipMemcpyAsync(static_cast<char*>(cx_.pin) + off, src, bytes, hipMemcpyDeviceToHost, st_);
   }
@@ -223,8 +251,10 @@ class Readback {
     ended_ = false;
     hipError_t e = ev ? hipEventSynchronize(ev_) : hipStreamSynchronize(st_);
     if (e != hipSuccess) return e;
-    for (const Item& it : items_) std::memcpy(it.dst, static_cast<char*>(cx_.pin) + it.off, it.bytes);
-    items_.clear();
+    for (int k = 0; k < nitems_; ++k)
+      if (items_[k].dst)
+        std::memcpy(items_[k].dst, static_cast<char*>(cx_.pin) + items_[k].off, items_[k].bytes);
+    nitems_ = 0;
     used_ = 0;
     // every staged upload queued before the waited point has been read
     if (!ev || up_used_ == up_end_) up_used_ = 0;
@@ -234,6 +264,11 @@ class Readback {
   // blocks the host once per copy); falls back to a direct copy when the
   // buffer is full.  The staged bytes are reused only after wait().
   hipError_t upload(void* dst, const void* src, size_t bytes) {
+    if (cx_.direct) {
+      // from pageable memory that the caller may change right after: wait
+      hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
+      return e == hipSuccess ? hipStreamSynchronize(st_) : e;
+    }
     if (!cx_.pin_up) {
       if (hipHostMalloc(&cx_.pin_up, kPinUpload, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -254,11 +289,13 @@ class Readback {
     void* dst;
     size_t off, bytes;
   };
+  static constexpr int kMaxItems = 8;
   Ctx::Pins& cx_;
   hipStream_t st_;
   hipEvent_t ev_;
   bool ended_ = false;
-  std::vector<Item> items_;
+  Item items_[kMaxItems];
+  int nitems_ = 0;
   size_t used_ = 0;
   size_t up_used_ = 0, up_end_ = 0;
 };
@@ -973,7 +1010,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   hipStream_t s1 = overlap ? cx.side : st;
   SideGuard sguard{cx};
   // persistent grids: the tuned number of workgroups, at most one wave per chunk
-  const uint32_t gblocks = tuned_blocks(tune_key(p.model, g.d, p.T, p.n), cx.batch);
+  const uint32_t gblocks = cx.fixed_tuning ? default_blocks(tune_key(p.model, g.d, p.T, p.n))
+                                           : tuned_blocks(tune_key(p.model, g.d, p.T, p.n), cx.batch);
   auto grid_for = [&](uint32_t nchunks) {
     const uint32_t need = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
     return std::max<uint32_t>(1u, std::min<uint32_t>(gblocks, need));
@@ -1177,6 +1215,76 @@ static girg_status lock_ctx(CtxLock* out, int slot = 0) {
   return GIRG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// the no-allocation variant of girg_from_points: every device buffer of a
+// call lies in one fixed array of device memory, `scratch`, which each GPU
+// holds from the library's first use on it until the process ends
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 512ull << 20;
+constexpr uint64_t kNoAllocMaxN = 1ull << 20;
+constexpr uint64_t kNoAllocMaxCap = 1ull << 24;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// per device: the address of its copy of `scratch` (the array's name is a
+// host-side stand-in, not a device address) and a context whose buffers and
+// arena are carved from it
+constexpr int kNoAllocDevices = 16;
+struct NoAllocSlot {
+  bool ready = false;
+  unsigned char* ptr = nullptr;
+  Ctx cx;
+};
+static std::mutex g_na_mu;
+static NoAllocSlot g_na[kNoAllocDevices];
+// the distant-offset tables are built here on the host, then copied once
+static uint32_t g_na_tab[1 << 14];
+
+// set-up, once per device, with that device current
+static girg_status noalloc_setup(int dev, NoAllocSlot** out) {
+  if (dev < 0 || dev >= kNoAllocDevices)
+    return fail(GIRG_EINVAL, "girg_from_points_noalloc: device index above 15");
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  NoAllocSlot& sl = g_na[dev];
+  if (!sl.ready) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(GIRG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    unsigned char* base = static_cast<unsigned char*>(ptr);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      unsigned char* q = base + off;
+      off += (bytes + 255) & ~(size_t)255;
+      return q;
+    };
+    Ctx& c = sl.cx;
+    c.device = dev;
+    c.external = true;
+    c.fixed_tuning = true;
+    c.pins.direct = true;
+    c.pins_side.direct = true;
+    c.gd = reinterpret_cast<Graph*>(carve(sizeof(Graph)));
+    c.red = reinterpret_cast<double*>(carve(8 * sizeof(double)));
+    c.red_side = reinterpret_cast<double*>(carve(8 * sizeof(double)));
+    c.flag = reinterpret_cast<uint32_t*>(carve(sizeof(uint32_t)));
+    c.stats = reinterpret_cast<unsigned long long*>(carve(16 * sizeof(unsigned long long)));
+    c.hcount = reinterpret_cast<unsigned int*>(carve(sizeof(unsigned int)));
+    for (int d = 1; d <= 4; ++d) {
+      const size_t sz = distant_table_fill(d, g_na_tab, sizeof(g_na_tab) / sizeof(uint32_t));
+      if (sz > sizeof(g_na_tab) / sizeof(uint32_t))
+        return fail(GIRG_EDEVICE, "girg_from_points_noalloc: distant table larger than its buffer");
+      uint32_t* t = reinterpret_cast<uint32_t*>(carve(sz * sizeof(uint32_t)));
+      HIPCHK(hipMemcpy(t, g_na_tab, sz * sizeof(uint32_t), hipMemcpyHostToDevice));
+      c.dtab[d] = t;
+    }
+    c.ar.attach(reinterpret_cast<char*>(base + off), kScratchBytes - off);
+    sl.ptr = base;
+    sl.ready = true;
+  }
+  *out = &sl;
+  return GIRG_OK;
+}
+
 }  // namespace hg
 
 using namespace hg;
@@ -1235,6 +1343,38 @@ girg_status girg_from_points(const girg_params* p, const double* w, const double
   if (info) std::memset(info, 0, sizeof(*info));
   cx->ev_name.clear();
   return run_graph(*cx, *p, w, x, edges, cap, m_out, info, static_cast<hipStream_t>(stream));
+}
+
+girg_status girg_from_points_noalloc(const girg_params* p, const double* w, const double* x,
+                                     uint32_t* edges, uint64_t cap, uint64_t* m_out,
+                                     girg_info* info, void* stream) {
+  if (!p || !w || !x || !m_out || (!edges && cap)) return fail(GIRG_EINVAL, "null argument");
+  girg_status s = validate(*p, false);
+  if (s != GIRG_OK) return s;
+  if (p->model == 0 && !(p->c > 0.0))
+    return fail(GIRG_EINVAL, "girg_from_points_noalloc needs c > 0 (solving c keeps host buffers)");
+  if (p->model == 1 && !(p->R > 0.0)) return fail(GIRG_EINVAL, "girg_from_points_noalloc needs R > 0");
+  if (p->n > kNoAllocMaxN) return fail(GIRG_EINVAL, "girg_from_points_noalloc: n above 2^20");
+  if (cap > kNoAllocMaxCap) return fail(GIRG_EINVAL, "girg_from_points_noalloc: cap above 2^24 edges");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  NoAllocSlot* sl = nullptr;
+  if ((s = noalloc_setup(dev, &sl)) != GIRG_OK) return s;
+  // calls on one device run one at a time and return only after their work
+  // on the GPU has ended, so no two of them use the array at once
+  std::unique_lock<std::mutex> lk(sl->cx.mu);
+  sl->cx.ar.reset_all();
+  sl->cx.ar.clear_failure();
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s = run_graph(sl->cx, *p, w, x, edges, cap, m_out, info, st);
+  if (s != GIRG_OK) {
+    (void)hipStreamSynchronize(st);  // an early return may leave work queued on the array
+    if (s == GIRG_ENOMEM && sl->cx.ar.failed())
+      return fail(GIRG_ENOMEM, "girg_from_points_noalloc: the graph needs more than the fixed 512 MiB "
+                               "scratch (" + g_err + ")");
+  }
+  return s;
 }
 
 static girg_status generate_impl(const girg_params* p, uint32_t* edges, uint64_t cap,

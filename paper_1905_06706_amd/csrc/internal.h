@@ -21,13 +21,30 @@ class Arena {
   };
   ~Arena() { release(); }
 
-  Mark mark() const { return Mark{cur_, chunks_.empty() ? 0 : chunks_[cur_].used}; }
+  // a fixed device buffer instead of chunks of its own: the arena then never
+  // calls hipMalloc or hipFree, and an allocation beyond the buffer fails
+  void attach(char* base, size_t size) {
+    ext_base_ = base;
+    ext_size_ = size;
+    ext_used_ = 0;
+  }
+  bool attached() const { return ext_base_ != nullptr; }
+
+  Mark mark() const {
+    if (ext_base_) return Mark{0, ext_used_};
+    return Mark{cur_, chunks_.empty() ? 0 : chunks_[cur_].used};
+  }
   void reset(Mark m) {
+    if (ext_base_) {
+      ext_used_ = m.used;
+      return;
+    }
     for (size_t c = m.chunk + 1; c < chunks_.size(); ++c) chunks_[c].used = 0;
     cur_ = m.chunk;
     if (!chunks_.empty()) chunks_[cur_].used = m.used;
   }
   void reset_all() {
+    ext_used_ = 0;
     for (auto& c : chunks_) c.used = 0;
     cur_ = 0;
   }
@@ -50,6 +67,8 @@ class Arena {
   std::vector<Chunk> chunks_;
   size_t cur_ = 0;
   bool failed_ = false;
+  char* ext_base_ = nullptr;
+  size_t ext_size_ = 0, ext_used_ = 0;
 };
 
 hipError_t scan_u32(Arena& ar, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,

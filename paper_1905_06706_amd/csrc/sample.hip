@@ -1471,36 +1471,54 @@ hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const C
   return hipGetLastError();
 }
 
-std::vector<uint32_t> distant_table(int d) {
-  const int npar = 1 << d;
-  std::vector<std::vector<uint32_t>> lists(npar);
+// the distant offsets of a parity pattern: children of the parent's
+// neighbours (offset delta_k = jk - 2 - parity_k) that are not neighbours,
+// listed once per unordered pair (first nonzero delta positive).  Calls f(t,
+// entry) for the t-th entry; returns the count.
+template <typename F>
+static uint32_t distant_offsets(int d, int par, F&& f) {
   int noff = 1;
   for (int k = 0; k < d; ++k) noff *= 6;
-  for (int par = 0; par < npar; ++par) {
-    for (int o = 0; o < noff; ++o) {
-      int rem = o, dm = 0, first = 0;
-      uint32_t en = 0;
-      for (int k = 0; k < d; ++k) {
-        const int jk = rem % 6;
-        rem /= 6;
-        const int delta = jk - 2 - ((par >> k) & 1);  // child of a parent-neighbour
-        const int ad = delta < 0 ? -delta : delta;
-        dm = ad > dm ? ad : dm;
-        if (first == 0) first = delta;
-        en |= (uint32_t)(delta + 3) << (3 * k);
-      }
-      if (dm < 2 || first < 0) continue;  // a neighbour, or listed at the other cell
-      lists[par].push_back(en | ((uint32_t)(dm - 1) << 28));
+  uint32_t t = 0;
+  for (int o = 0; o < noff; ++o) {
+    int rem = o, dm = 0, first = 0;
+    uint32_t en = 0;
+    for (int k = 0; k < d; ++k) {
+      const int jk = rem % 6;
+      rem /= 6;
+      const int delta = jk - 2 - ((par >> k) & 1);  // child of a parent-neighbour
+      const int ad = delta < 0 ? -delta : delta;
+      dm = ad > dm ? ad : dm;
+      if (first == 0) first = delta;
+      en |= (uint32_t)(delta + 3) << (3 * k);
     }
+    if (dm < 2 || first < 0) continue;  // a neighbour, or listed at the other cell
+    f(t++, en | ((uint32_t)(dm - 1) << 28));
   }
-  size_t stride = 1;
-  for (auto& l : lists) stride = l.size() > stride ? l.size() : stride;
-  std::vector<uint32_t> tab(kDistHead + npar * stride, 0u);
-  tab[0] = (uint32_t)stride;
+  return t;
+}
+
+size_t distant_table_fill(int d, uint32_t* out, size_t cap) {
+  const int npar = 1 << d;
+  uint32_t stride = 1;
   for (int par = 0; par < npar; ++par) {
-    tab[1 + par] = (uint32_t)lists[par].size();
-    for (size_t t = 0; t < lists[par].size(); ++t) tab[kDistHead + par * stride + t] = lists[par][t];
+    const uint32_t c = distant_offsets(d, par, [](uint32_t, uint32_t) {});
+    stride = c > stride ? c : stride;
   }
+  const size_t size = (size_t)kDistHead + (size_t)npar * stride;
+  if (!out || cap < size) return size;
+  for (size_t k = 0; k < size; ++k) out[k] = 0u;
+  out[0] = stride;
+  for (int par = 0; par < npar; ++par)
+    out[1 + par] = distant_offsets(d, par, [&](uint32_t t, uint32_t en) {
+      out[kDistHead + (size_t)par * stride + t] = en;
+    });
+  return size;
+}
+
+std::vector<uint32_t> distant_table(int d) {
+  std::vector<uint32_t> tab(distant_table_fill(d, nullptr, 0), 0u);
+  distant_table_fill(d, tab.data(), tab.size());
   return tab;
 }
 

@@ -117,6 +117,9 @@ hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const C
 // of each pair is listed at the other cell)
 constexpr int kDistHead = 32;
 std::vector<uint32_t> distant_table(int d);
+// the same table written to out[0..size) without allocating; returns its
+// size (and writes nothing when out is null or cap is smaller)
+size_t distant_table_fill(int d, uint32_t* out, size_t cap);
 
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,

@@ -29,6 +29,8 @@ void tune_init();
 // workgroups of the persistent passes of one graph; `batch` for the graphs
 // of a batch (they share the GPU with other instances)
 uint32_t tuned_blocks(const TuneKey& k, bool batch);
+// the built-in default for a single graph (no table, no environment)
+uint32_t default_blocks(const TuneKey& k);
 // forced value, else GIRG_BATCH_WORKERS, else the table, else 16
 int tuned_batch_workers();
 

@@ -130,6 +130,8 @@ bool get_int(const std::map<std::string, long>& kv, const char* key, long lo, lo
 
 }  // namespace
 
+uint32_t default_blocks(const TuneKey& k) { return default_single(k); }
+
 TuneKey tune_key(int model, int d, double T, uint64_t n) {
   int lg = 0;
   while ((n >> (lg + 1)) != 0 && lg < 63) ++lg;
