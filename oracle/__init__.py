@@ -30,7 +30,7 @@ STAT_NAMES = {
     0: "W", 1: "w0", 2: "L", 3: "D", 4: "Dmax", 5: "nb_pairs", 6: "dist_pairs",
     7: "type1_items", 8: "type2_items", 9: "tests", 10: "draws", 11: "candidates",
     12: "edges", 13: "near", 14: "ties", 15: "segments", 16: "kappa_or_coshR",
-    17: "type1_edges", 18: "type2_edges", 19: "near_expect", 20: "tie_expect",
+    17: "type1_edges", 18: "type2_edges", 19: "near_expect", 20: "tie_expect", 21: "seqs",
 }
 
 
@@ -55,6 +55,7 @@ class _Params(ctypes.Structure):
         ("cl_bias", ctypes.c_int32), ("accept_all", ctypes.c_int32),
         ("filter_level", ctypes.c_int32), ("filter_mod", ctypes.c_uint32),
         ("filter_rem", ctypes.c_uint32), ("filter_skip_top", ctypes.c_int32),
+        ("batch_type2", ctypes.c_int32),
     ]
 
 
@@ -290,7 +291,7 @@ def run(w: np.ndarray, x: np.ndarray, *, T: float, c: float = 0.0, seed: int = 0
         model: int = 0, alpha: float = 0.0, R: float = 0.0, max_depth: int = -1,
         cl_bias: int = 0, accept_all: bool = False, filter_level: int = 0,
         filter_mod: int = 0, filter_rem: int = 0, filter_skip_top: bool = False,
-        keep: bool = False) -> Run:
+        batch_type2: bool = False, keep: bool = False) -> Run:
     """Sample one graph over the given points (GIRG: weights w, HRG: radii w)."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -301,7 +302,7 @@ def run(w: np.ndarray, x: np.ndarray, *, T: float, c: float = 0.0, seed: int = 0
     p = _Params(n=n, d=d, model=model, T=T, c=c, alpha=alpha, R=R, seed=seed,
                 max_depth=max_depth, cl_bias=cl_bias, accept_all=int(accept_all),
                 filter_level=filter_level, filter_mod=filter_mod, filter_rem=filter_rem,
-                filter_skip_top=int(filter_skip_top))
+                filter_skip_top=int(filter_skip_top), batch_type2=int(batch_type2))
     L = lib()
     h = L.orc_run_graph(ctypes.byref(p), _ptr(w, ctypes.c_double), _ptr(x, ctypes.c_double))
     if not h:

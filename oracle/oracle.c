@@ -71,7 +71,7 @@ double orc_u53_open(uint32_t lo, uint32_t hi) {
 /* Stream layout (our contract; the paper uses thread-local generators,
  * App. B.5).  key = seed.  counter word 3 packs level, layer pair, kind and a
  * high index part. */
-enum { KIND_TYPE1 = 0, KIND_TYPE2 = 1, KIND_POINTS = 2 };
+enum { KIND_TYPE1 = 0, KIND_TYPE2 = 1, KIND_POINTS = 2, KIND_SEQ = 3 };
 
 static void stream_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                          uint32_t out[4]) {
@@ -507,7 +507,7 @@ struct orc_run {
 enum {
   S_NBPAIRS = 5, S_DISTPAIRS = 6, S_T1ITEMS = 7, S_T2ITEMS = 8, S_TESTS = 9, S_DRAWS = 10,
   S_CANDS = 11, S_EDGES = 12, S_NEAR = 13, S_TIES = 14, S_SEGS = 15, S_T1EDGES = 17,
-  S_T2EDGES = 18
+  S_T2EDGES = 18, S_SEQS = 21
 };
 
 void orc_free(orc_run* r) {
@@ -790,6 +790,195 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
   }
 }
 
+/* ---- type-II jump sequences over the cell pairs of one source (ours). ----
+ * Sec. 3.2 samples the candidates of a distant cell pair by geometric jumps
+ * under pbar.  The jumps need not stop at the end of a cell pair: the
+ * candidates of all distant cell pairs that share pbar are independent
+ * Bernoulli(pbar) trials too, so one jump sequence can run over their
+ * concatenation.  With batch_type2, at every level l >= 3 (d <= 3, T > 0):
+ *  - a source is a cell X at level l with vertices of layer i;
+ *  - its distant cells Y are X + delta for the offsets delta of X's parity
+ *    table: children of the parent's neighbours that are not neighbours,
+ *    with the first nonzero component positive (so each unordered cell pair is
+ *    listed at exactly one of its cells), taken in increasing order of
+ *    o = sum_k (delta_k + 2 + parity_k) 6^k;
+ *  - for each layer j with CL(i,j) >= l and gap g = max_k |delta_k| - 1, the
+ *    cell pairs (X, Y) with V_j^Y nonempty whose candidates fit one segment
+ *    (the segment rule of type2()) form a sequence in that order; the
+ *    candidates of an item are x |V_j^Y| + y (x in V_i^X, y in V_j^Y), and
+ *    the items follow each other;
+ *  - draw t of the sequence uses the counter (t, X, g, l | i | j | kind 3);
+ *  - cell pairs with more than one segment are sampled by type2() as before.
+ * Edges are written with u from the A side (the smaller cell). */
+static int batched_level(const orc_run* R, int l) {
+  return R->p.batch_type2 && R->p.T > 0.0 && R->p.d <= 3 && l >= 3;
+}
+
+/* the distant offsets of parity pattern par with gap g, in increasing o */
+static int seq_offsets(int d, int par, int g, int (*delta)[3]) {
+  int no = 1, cnt = 0;
+  for (int k = 0; k < d; k++) no *= 6;
+  for (int o = 0; o < no; o++) {
+    int rem = o, dm = 0, first = 0, dl[3] = {0, 0, 0};
+    for (int k = 0; k < d; k++) {
+      int jk = rem % 6;
+      rem /= 6;
+      dl[k] = jk - 2 - ((par >> k) & 1);
+      int ad = dl[k] < 0 ? -dl[k] : dl[k];
+      if (ad > dm) dm = ad;
+      if (first == 0) first = dl[k];
+    }
+    if (dm < 2 || first < 0 || dm - 1 != g) continue;
+    for (int k = 0; k < 3; k++) delta[cnt][k] = dl[k];
+    cnt++;
+  }
+  return cnt;
+}
+
+typedef struct {
+  uint64_t x0, nx, y0, ny, A, B; /* ranges of V_i^X and V_j^Y; A <= B the cells */
+  int x_is_a;
+} seq_item;
+
+static void run_sequence(orc_run* R, int l, uint64_t X, int i, int j, int g, const seq_item* it,
+                         int nit) {
+  const orc_params* p = &R->p;
+  double pbar_raw;
+  double pbar = type2_pbar(R, l, i, j, g, &pbar_raw);
+  double lg1 = log1p(-pbar);
+  uint64_t total = 0;
+  for (int k = 0; k < nit; k++) total += it[k].nx * it[k].ny;
+  R->ctr[S_SEQS]++;
+  int tie = 0;
+  uint64_t pos = 0; /* candidates of the sequence before the next jump */
+  int k = 0;        /* item holding position pos */
+  uint64_t kstart = 0;
+  for (uint64_t t = 0;; t++) {
+    uint32_t o[4];
+    stream_block(p->seed, (uint32_t)t, (uint32_t)X, (uint32_t)g,
+                 word3(l, i, j, KIND_SEQ, (uint32_t)(t >> 32)), o);
+    R->ctr[S_DRAWS]++;
+    double S = orc_u53_open(o[0], o[1]);
+    double Acc = orc_u53(o[2], o[3]);
+    /* X ~ Geom_0(pbar) candidates skipped */
+    double q = pbar >= 1.0 ? 0.0 : log(S) / lg1;
+    double rest = (double)(total - pos);
+    double fl = floor(q + 0.5);
+    if (pbar < 1.0 && fl >= 1.0 && fabs(q - fl) < 1e-12 * q && q < rest + 1.0) tie = 1;
+    R->tie_expect += tie_mass(pbar, -lg1, rest);
+    if (q >= rest) break;
+    pos += (uint64_t)q;
+    while (pos >= kstart + it[k].nx * it[k].ny) { kstart += it[k].nx * it[k].ny; k++; }
+    uint64_t loc = pos - kstart;
+    uint64_t sx = it[k].x0 + loc / it[k].ny, sy = it[k].y0 + loc % it[k].ny;
+    uint32_t ux = R->sid[sx], uy = R->sid[sy];
+    uint32_t u = it[k].x_is_a ? ux : uy, v = it[k].x_is_a ? uy : ux;
+    R->ctr[S_CANDS]++;
+    if (p->accept_all) {
+      emit(R, u, v, 1);
+    } else {
+      double r = torus_dist(R->sx + sx * (uint64_t)p->d, R->sx + sy * (uint64_t)p->d, p->d);
+      double puv = p->model == 0 ? girg_p(R, R->sw[sx], R->sw[sy], r)
+                                 : hrg_pT(R, hrg_coshd(R->sw[sx], R->sw[sy], r));
+      /* accepted with probability p_uv / pbar; near when Acc is within
+       * 1e-12 of that ratio */
+      if (fabs(Acc - puv / pbar) < 1e-12) near_pair(R, u, v);
+      R->near_expect += near_mass(puv / pbar);
+      if (pbar * Acc < puv) emit(R, u, v, 1);
+    }
+    pos += 1;
+    if (pos >= total) break;
+  }
+  if (tie) {
+    /* every pair of the sequence may come out differently: log its items */
+    for (int q = 0; q < nit; q++) {
+      uint64_t a0 = it[q].x_is_a ? it[q].x0 : it[q].y0, na = it[q].x_is_a ? it[q].nx : it[q].ny;
+      uint64_t b0 = it[q].x_is_a ? it[q].y0 : it[q].x0, nb = it[q].x_is_a ? it[q].ny : it[q].nx;
+      if (push64x4(&R->ties, a0, na, b0, nb)) R->failed = 1;
+    }
+    R->ctr[S_TIES]++;
+  }
+}
+
+/* whether the items of sources at level l >= filter level are selected by
+ * the source's ancestor (filtered runs) */
+static int source_selected(const orc_run* R, int l, uint64_t X) {
+  const orc_params* p = &R->p;
+  if (!p->filter_mod) return 1;
+  if (l < p->filter_level) return !p->filter_skip_top;
+  uint64_t anc = X >> (p->d * (l - p->filter_level));
+  return (anc % p->filter_mod) == p->filter_rem;
+}
+
+static void type2_batched(orc_run* R) {
+  const orc_params* p = &R->p;
+  int d = p->d;
+  static int delta[1296][3];
+  seq_item* items = (seq_item*)malloc(sizeof(seq_item) * 1296);
+  if (!items) { R->failed = 1; return; }
+  for (int l = 3; l <= R->D; l++) {
+    if (!batched_level(R, l)) continue;
+    uint64_t side = (uint64_t)1 << l;
+    for (int i = 0; i < R->L; i++) {
+      if (!R->count[i] || R->I[i] < l) continue;
+      /* the cells X of layer i at level l: runs of sorted positions */
+      uint64_t s = R->lstart[i];
+      while (s < R->lstart[i + 1]) {
+        uint64_t X = cell_of_sorted(R, s, l), x0, nx;
+        vertex_range(R, i, l, X, &x0, &nx);
+        s = x0 + nx;
+        if (!source_selected(R, l, X)) continue;
+        uint32_t cx[8];
+        orc_morton_decode(X, d, l, cx);
+        int par = 0;
+        for (int k = 0; k < d; k++) par |= (int)(cx[k] & 1u) << k;
+        for (int g = 1; g <= 2; g++) {
+          int no = seq_offsets(d, par, g, delta);
+          for (int j = 0; j < R->L; j++) {
+            if (!R->count[j] || R->CL[i][j] < l) continue;
+            int nit = 0;
+            for (int t = 0; t < no; t++) {
+              uint32_t cy[8];
+              for (int k = 0; k < d; k++) cy[k] = (uint32_t)((cx[k] + side + (uint64_t)(int64_t)delta[t][k]) % side);
+              uint64_t Y = orc_morton_encode(cy, d, l), y0, ny;
+              vertex_range(R, j, l, Y, &y0, &ny);
+              if (ny == 0) continue;
+              int xa = X < Y;
+              uint64_t A = xa ? X : Y, B = xa ? Y : X;
+              int ia = xa ? i : j, jb = xa ? j : i;
+              /* the segment rule of type2(): items of more than one segment
+               * are sampled there, with their own streams */
+              double pr;
+              double pb = type2_pbar(R, l, ia, jb, g, &pr);
+              if (!(pb > 0.0)) continue;
+              uint64_t N = nx * ny;
+              int e = SEG_EXP - ilogb(pb), emin = bitlen(N - 1) - SEG_MAX_BITS;
+              if (e < emin) e = emin;
+              uint64_t G = (e >= 63 || ((uint64_t)1 << e) >= N) ? N : ((uint64_t)1 << e);
+              if ((N + G - 1) / G > 1) {
+                type2(R, l, A, B, ia, jb);
+                continue;
+              }
+              R->ctr[S_T2ITEMS]++;
+              if (near_pow2(pr) && e > emin) {
+                /* a segment count that another pow could change: log the item */
+                uint64_t a0 = xa ? x0 : y0, na = xa ? nx : ny, b0 = xa ? y0 : x0, nb = xa ? ny : nx;
+                if (push64x4(&R->ties, a0, na, b0, nb)) R->failed = 1;
+                R->ctr[S_TIES]++;
+              }
+              items[nit].x0 = x0; items[nit].nx = nx; items[nit].y0 = y0; items[nit].ny = ny;
+              items[nit].A = A; items[nit].B = B; items[nit].x_is_a = xa;
+              nit++;
+            }
+            if (nit) run_sequence(R, l, X, i, j, g, items, nit);
+          }
+        }
+      }
+    }
+  }
+  free(items);
+}
+
 /* ---- Algorithm 1: recursive iteration of cell pairs (Sec. 3.3). ---- */
 static int any_nonempty(const orc_run* R, int l, uint64_t A) {
   /* some layer with I(i) > l has vertices in A (a recursion below l can only
@@ -821,8 +1010,9 @@ static void recur(orc_run* R, int l, uint64_t A, uint64_t B, int nb, int selecte
           if (R->CL[i][j] == l) type1(R, l, A, B, i, j);
         } else {
           /* threshold variants: distant cells hold no edges (their points are
-           * farther apart than the cell side, which is at least the threshold) */
-          if (R->CL[i][j] >= l && p->T > 0.0) type2(R, l, A, B, i, j);
+           * farther apart than the cell side, which is at least the threshold);
+           * batched runs sample levels >= 3 by source cell afterwards */
+          if (R->CL[i][j] >= l && p->T > 0.0 && !batched_level(R, l)) type2(R, l, A, B, i, j);
         }
       }
     }
@@ -992,6 +1182,7 @@ orc_run* orc_run_graph(const orc_params* pin, const double* w, const double* x) 
   }
 
   recur(R, 0, 0, 0, 1, p->filter_mod == 0 || p->filter_level > 0);
+  if (p->batch_type2 && p->T > 0.0 && d <= 3) type2_batched(R);
   if (R->failed) { orc_free(R); set_err("out of memory (edges)"); return NULL; }
   return R;
 }
