@@ -116,7 +116,7 @@ def batch_params(hg, wl: dict, precision: int) -> list:
     return out
 
 
-def make_call(hg, wl: dict, precision: int):
+def make_call(hg, wl: dict, precision: int, type2_batch: int = 0):
     L = hg.load()
     if "batch" in wl:
         params = batch_params(hg, wl, precision)
@@ -152,7 +152,8 @@ def make_call(hg, wl: dict, precision: int):
         call.params = hg.make_params(wl["n"], 1, 0.0, wl["T"], wl["avg_deg"], 0.0, wl["seed"], model=1,
                                      alpha=wl["alpha"])
         return call
-    p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"], precision)
+    p = hg.make_params(wl["n"], wl["d"], wl["beta"], wl["T"], wl["avg_deg"], 0.0, wl["seed"], precision,
+                       type2_batch=type2_batch)
 
     def call(buf, cap, m, info, stream):
         return L.girg_generate(ctypes.byref(p), buf, cap, m, info, stream)
@@ -178,7 +179,7 @@ def cpu_info() -> dict:
     return {"nproc": nproc, "cpu_model": model}
 
 
-def oracle_check(hg, wl: dict, edges, info: dict) -> tuple:
+def oracle_check(hg, wl: dict, edges, info: dict, type2_batch: int = 0) -> tuple:
     """The oracle on the GPU's own points and constant (c, or R for the HRG),
     the same seed: the whole graph up to n = 2^21, above that every cell-pair
     item above level 3 plus the level-3 subtrees whose A-side ancestor is
@@ -197,7 +198,7 @@ def oracle_check(hg, wl: dict, edges, info: dict) -> tuple:
         kw = dict(T=wl["T"], model=1, R=R, alpha=wl["alpha"], seed=wl["seed"])
     else:
         w, x = hg.points(n, wl["d"], wl["beta"], seed=wl["seed"])
-        kw = dict(T=wl["T"], c=info["c"], seed=wl["seed"])
+        kw = dict(T=wl["T"], c=info["c"], seed=wl["seed"], batch_type2=bool(type2_batch))
     sample = "the whole graph"
     if n > 2**21:
         kw.update(filter_level=3, filter_mod=512, filter_rem=0)
@@ -210,7 +211,7 @@ def oracle_check(hg, wl: dict, edges, info: dict) -> tuple:
     dt = time.perf_counter() - t0
     m_orc = len(run.edges)
     if n > 2**21:
-        edges = level3_sample(edges, x, run, 512)
+        edges = level3_sample(edges, x, run, 512, batched=bool(type2_batch))
     t1 = time.perf_counter()
     rep = {"sample": sample, "inputs": "the GPU's points and constant, same seed"}
     try:
@@ -526,6 +527,8 @@ def main() -> int:
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
                     help="legs to run (default both where the FP32 filter applies)")
+    ap.add_argument("--type2-batch", type=int, default=0, choices=[0, 1],
+                    help="1: batched type-II jump sequences (GIRG d = 2, 3)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (both its timing and the oracle-match check)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -573,7 +576,7 @@ def main() -> int:
         hg.set_profiling(True, serial=True)
     L = {}
     for q in legs:
-        call = make_call(hg, wl, q)
+        call = make_call(hg, wl, q, args.type2_batch)
         m = ctypes.c_uint64(0)
         info = hg.Info()
         st = call(None, 0, ctypes.byref(m), ctypes.byref(info), sp)
@@ -683,7 +686,7 @@ def main() -> int:
             out["cpu_baseline"] = cpu_baseline_batch(lt["call"].params)
         else:
             t0 = time.perf_counter()
-            rep, cpu = oracle_check(hg, wl, lt["buf"][:lt["m"]], lt["info"])
+            rep, cpu = oracle_check(hg, wl, lt["buf"][:lt["m"]], lt["info"], args.type2_batch)
             out["oracle_match"] = rep
             out["cpu_baseline"] = cpu
             print(f"[bench] oracle check ({time.perf_counter() - t0:.1f} s): {rep}", file=sys.stderr)

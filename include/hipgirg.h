@@ -72,7 +72,14 @@ typedef struct {
   int32_t max_depth;  /* debug knob, -1 = none: caps the comparison levels */
   int32_t cl_bias;    /* debug knob, 0 = none: shifts the comparison levels
                          (> 0 only for T > 0); every value samples exactly */
-  int32_t reserved;
+  int32_t type2_batch; /* 1: at levels >= 3 of binomial GIRGs with d = 2 or 3,
+                          one geometric-jump sequence (Sec. 3.2) runs over the
+                          distant cell pairs of a source cell that share the
+                          bound pbar and have at most 2^(1 - ilogb(pbar))
+                          candidates each (fewer draws; another random
+                          stream, the same distribution); needs at most 32
+                          weight layers (GIRG_EINVAL otherwise); 0: one
+                          sequence per cell pair */
 } girg_params;
 
 /* Diagnostics of one call. */

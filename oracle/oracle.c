@@ -795,7 +795,8 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
  * under pbar.  The jumps need not stop at the end of a cell pair: the
  * candidates of all distant cell pairs that share pbar are independent
  * Bernoulli(pbar) trials too, so one jump sequence can run over their
- * concatenation.  With batch_type2, at every level l >= 3 (d <= 3, T > 0):
+ * concatenation.  With batch_type2, at every level l >= 3 (GIRG, d = 2 or 3,
+ * T > 0; at d = 1 a source has at most one distant cell per gap):
  *  - a source is a cell X at level l with vertices of layer i;
  *  - its distant cells Y are X + delta for the offsets delta of X's parity
  *    table: children of the parent's neighbours that are not neighbours,
@@ -803,15 +804,18 @@ static void type2(orc_run* R, int l, uint64_t A, uint64_t B, int i, int j) {
  *    listed at exactly one of its cells), taken in increasing order of
  *    o = sum_k (delta_k + 2 + parity_k) 6^k;
  *  - for each layer j with CL(i,j) >= l and gap g = max_k |delta_k| - 1, the
- *    cell pairs (X, Y) with V_j^Y nonempty whose candidates fit one segment
- *    (the segment rule of type2()) form a sequence in that order; the
- *    candidates of an item are x |V_j^Y| + y (x in V_i^X, y in V_j^Y), and
- *    the items follow each other;
+ *    cell pairs (X, Y) with V_j^Y nonempty and at most 2^(e0 - 4)
+ *    candidates, e0 = 5 - ilogb(pbar) (about 2 / pbar; such a pair also fits
+ *    one segment of type2()), form a sequence in that order; the candidates
+ *    of an item are x |V_j^Y| + y (x in V_i^X, y in V_j^Y), and the items
+ *    follow each other;
  *  - draw t of the sequence uses the counter (t, X, g, l | i | j | kind 3);
- *  - cell pairs with more than one segment are sampled by type2() as before.
+ *  - the other cell pairs are sampled by type2() as before: the larger ones
+ *    (few of their first draws come up empty, and long sequences would hold
+ *    many draws) and those of more than one segment.
  * Edges are written with u from the A side (the smaller cell). */
 static int batched_level(const orc_run* R, int l) {
-  return R->p.batch_type2 && R->p.T > 0.0 && R->p.d <= 3 && l >= 3;
+  return R->p.batch_type2 && R->p.T > 0.0 && R->p.model == 0 && R->p.d >= 2 && R->p.d <= 3 && l >= 3;
 }
 
 /* the distant offsets of parity pattern par with gap g, in increasing o */
@@ -936,7 +940,7 @@ static void type2_batched(orc_run* R) {
           int no = seq_offsets(d, par, g, delta);
           for (int j = 0; j < R->L; j++) {
             if (!R->count[j] || R->CL[i][j] < l) continue;
-            int nit = 0;
+            int nit = 0, seq_near = 0;
             for (int t = 0; t < no; t++) {
               uint32_t cy[8];
               for (int k = 0; k < d; k++) cy[k] = (uint32_t)((cx[k] + side + (uint64_t)(int64_t)delta[t][k]) % side);
@@ -946,29 +950,38 @@ static void type2_batched(orc_run* R) {
               int xa = X < Y;
               uint64_t A = xa ? X : Y, B = xa ? Y : X;
               int ia = xa ? i : j, jb = xa ? j : i;
-              /* the segment rule of type2(): items of more than one segment
-               * are sampled there, with their own streams */
               double pr;
               double pb = type2_pbar(R, l, ia, jb, g, &pr);
               if (!(pb > 0.0)) continue;
+              /* an exponent that another pow could change may move items
+               * between the classes below: the sequence's items are logged */
+              if (near_pow2(pr)) seq_near = 1;
               uint64_t N = nx * ny;
-              int e = SEG_EXP - ilogb(pb), emin = bitlen(N - 1) - SEG_MAX_BITS;
+              int e0 = SEG_EXP - ilogb(pb), e = e0, emin = bitlen(N - 1) - SEG_MAX_BITS;
               if (e < emin) e = emin;
               uint64_t G = (e >= 63 || ((uint64_t)1 << e) >= N) ? N : ((uint64_t)1 << e);
-              if ((N + G - 1) / G > 1) {
+              /* items of more than one segment (the segment rule of type2()),
+               * and items of more than 2^(e0 - 4) candidates (about 2 / pbar
+               * or more, so that few of their first draws come up empty), are
+               * sampled by type2() with their own streams */
+              if ((N + G - 1) / G > 1 || (e0 - 4 < 63 && N > ((uint64_t)1 << (e0 - 4)))) {
                 type2(R, l, A, B, ia, jb);
                 continue;
               }
               R->ctr[S_T2ITEMS]++;
-              if (near_pow2(pr) && e > emin) {
-                /* a segment count that another pow could change: log the item */
-                uint64_t a0 = xa ? x0 : y0, na = xa ? nx : ny, b0 = xa ? y0 : x0, nb = xa ? ny : nx;
-                if (push64x4(&R->ties, a0, na, b0, nb)) R->failed = 1;
-                R->ctr[S_TIES]++;
-              }
               items[nit].x0 = x0; items[nit].nx = nx; items[nit].y0 = y0; items[nit].ny = ny;
               items[nit].A = A; items[nit].B = B; items[nit].x_is_a = xa;
               nit++;
+            }
+            if (nit && seq_near) {
+              for (int q = 0; q < nit; q++) {
+                uint64_t a0 = items[q].x_is_a ? items[q].x0 : items[q].y0;
+                uint64_t na = items[q].x_is_a ? items[q].nx : items[q].ny;
+                uint64_t b0 = items[q].x_is_a ? items[q].y0 : items[q].x0;
+                uint64_t nb = items[q].x_is_a ? items[q].ny : items[q].nx;
+                if (push64x4(&R->ties, a0, na, b0, nb)) R->failed = 1;
+              }
+              R->ctr[S_TIES]++;
             }
             if (nit) run_sequence(R, l, X, i, j, g, items, nit);
           }
@@ -1182,7 +1195,7 @@ orc_run* orc_run_graph(const orc_params* pin, const double* w, const double* x) 
   }
 
   recur(R, 0, 0, 0, 1, p->filter_mod == 0 || p->filter_level > 0);
-  if (p->batch_type2 && p->T > 0.0 && d <= 3) type2_batched(R);
+  if (batched_level(R, 3)) type2_batched(R);
   if (R->failed) { orc_free(R); set_err("out of memory (edges)"); return NULL; }
   return R;
 }

@@ -49,9 +49,10 @@ typedef struct orc_params {
                            /* filter_level are walked but not sampled, so that  */
                            /* runs over the remainders mod filter_mod and one   */
                            /* run of the top levels alone partition the graph   */
-  int32_t batch_type2;     /* 1: at levels >= 3 (d <= 3, T > 0) the type-II     */
+  int32_t batch_type2;     /* 1: at levels >= 3 (GIRG, d = 2, 3, T > 0) the     */
                            /* cell pairs of one source cell X and layer i that  */
-                           /* share a bound pbar (layer j, gap g) run one jump  */
+                           /* share a bound pbar (layer j, gap g) and have at   */
+                           /* most 2^(1 - ilogb(pbar)) candidates run one jump  */
                            /* sequence over their concatenated candidates; the  */
                            /* filter then selects a sequence by X's ancestor    */
 } orc_params;

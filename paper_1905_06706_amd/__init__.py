@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("beta", ctypes.c_double), ("T", ctypes.c_double), ("avg_deg", ctypes.c_double),
         ("c", ctypes.c_double), ("alpha", ctypes.c_double), ("R", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("max_depth", ctypes.c_int32),
-        ("cl_bias", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("cl_bias", ctypes.c_int32), ("type2_batch", ctypes.c_int32),
     ]
 
 
@@ -141,9 +141,10 @@ def _stream(stream):
 
 
 def make_params(n, d=1, beta=2.5, T=0.0, avg_deg=0.0, c=0.0, seed=0, precision=0,
-                max_depth=-1, cl_bias=0, model=0, alpha=0.0, R=0.0) -> Params:
+                max_depth=-1, cl_bias=0, model=0, alpha=0.0, R=0.0, type2_batch=0) -> Params:
     return Params(n=n, d=d, model=model, beta=beta, T=T, avg_deg=avg_deg, c=c, alpha=alpha,
-                  R=R, seed=seed, precision=precision, max_depth=max_depth, cl_bias=cl_bias)
+                  R=R, seed=seed, precision=precision, max_depth=max_depth, cl_bias=cl_bias,
+                  type2_batch=type2_batch)
 
 
 def capacity_guess(n: int, avg_deg: float) -> int:
@@ -185,10 +186,12 @@ def _run_with_capacity(call, cap: int, device, stream=None):
 
 def generate(n: int, d: int = 1, beta: float = 2.5, T: float = 0.0, avg_deg: float = 0.0,
              c: float = 0.0, seed: int = 0, precision: int = 0, max_depth: int = -1,
-             cl_bias: int = 0, cap: int | None = None, stream=None, device="cuda") -> Result:
+             cl_bias: int = 0, cap: int | None = None, stream=None, device="cuda",
+             type2_batch: int = 0) -> Result:
     """girg_generate: a GIRG with Pareto weights (w_min = 1) and uniform positions."""
     L = load()
-    p = make_params(n, d, beta, T, avg_deg, c, seed, precision, max_depth, cl_bias)
+    p = make_params(n, d, beta, T, avg_deg, c, seed, precision, max_depth, cl_bias,
+                    type2_batch=type2_batch)
     if cap is None:
         cap = capacity_guess(n, avg_deg if avg_deg > 0 else 16.0)
     s = _stream(stream)
@@ -211,13 +214,14 @@ def hrg(n: int, alpha: float, T: float = 0.0, R: float = 0.0, avg_deg: float = 0
 def from_points(w, x, T: float, c: float = 0.0, avg_deg: float = 0.0, seed: int = 0,
                 model: int = 0, alpha: float = 0.0, R: float = 0.0, precision: int = 0,
                 max_depth: int = -1, cl_bias: int = 0, cap: int | None = None,
-                stream=None) -> Result:
+                stream=None, type2_batch: int = 0) -> Result:
     """girg_from_points over device tensors: w (n,) float64, x (d, n) float64."""
     L = load()
     assert w.dtype.is_floating_point and w.element_size() == 8 and w.is_contiguous()
     assert x.element_size() == 8 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == w.shape[0]
     n, d = int(w.shape[0]), int(x.shape[0])
-    p = make_params(n, d, 0.0, T, avg_deg, c, seed, precision, max_depth, cl_bias, model, alpha, R)
+    p = make_params(n, d, 0.0, T, avg_deg, c, seed, precision, max_depth, cl_bias, model, alpha, R,
+                    type2_batch)
     if cap is None:
         cap = capacity_guess(n, avg_deg if avg_deg > 0 else 16.0)
     s = _stream(stream)
@@ -229,7 +233,7 @@ def from_points(w, x, T: float, c: float = 0.0, avg_deg: float = 0.0, seed: int 
 
 def from_points_noalloc(w, x, edges, T: float, c: float = 0.0, seed: int = 0, model: int = 0,
                         alpha: float = 0.0, R: float = 0.0, precision: int = 0, max_depth: int = -1,
-                        cl_bias: int = 0, stream=None) -> tuple:
+                        cl_bias: int = 0, stream=None, type2_batch: int = 0) -> tuple:
     """girg_from_points_noalloc into a caller-provided edge buffer `edges`
     (int32 (cap, 2) device tensor): returns (m, info); GirgError on overflow."""
     L = load()
@@ -237,7 +241,8 @@ def from_points_noalloc(w, x, edges, T: float, c: float = 0.0, seed: int = 0, mo
     assert x.element_size() == 8 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == w.shape[0]
     assert edges.dtype.itemsize == 4 and edges.is_contiguous() and edges.dim() == 2 and edges.shape[1] == 2
     n, d = int(w.shape[0]), int(x.shape[0])
-    p = make_params(n, d, 0.0, T, 0.0, c, seed, precision, max_depth, cl_bias, model, alpha, R)
+    p = make_params(n, d, 0.0, T, 0.0, c, seed, precision, max_depth, cl_bias, model, alpha, R,
+                    type2_batch)
     m = ctypes.c_uint64(0)
     info = Info()
     _check(L.girg_from_points_noalloc(ctypes.byref(p), ctypes.c_void_p(w.data_ptr()),

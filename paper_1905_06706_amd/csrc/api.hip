@@ -106,6 +106,7 @@ struct Ctx {
   unsigned long long* stats = nullptr;  // 16
   unsigned int* hcount = nullptr;
   uint32_t* dtab[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // distant offsets per d
+  uint32_t* dtab2[5] = {nullptr, nullptr, nullptr, nullptr, nullptr}; // the same split by gap (d = 2, 3)
   hipStream_t own = nullptr;  // batch workers: the slot's own stream
   bool batch = false;         // a batch worker's context
   // a second stream on which type I and the split type-I pass run beside
@@ -183,6 +184,8 @@ struct Ctx {
     if (stats) (void)hipFree(stats);
     if (hcount) (void)hipFree(hcount);
     for (auto t : dtab)
+      if (t) (void)hipFree(t);
+    for (auto t : dtab2)
       if (t) (void)hipFree(t);
     if (own) (void)hipStreamDestroy(own);
     if (side) (void)hipStreamDestroy(side);
@@ -694,6 +697,7 @@ static girg_status validate(const girg_params& p, bool need_beta) {
   if (p.n < 2 || p.n > 0xFFFFFFFFull) return fail(GIRG_EINVAL, "n must be in [2, 2^32-1]");
   if (!(p.T >= 0.0 && p.T < 1.0)) return fail(GIRG_EINVAL, "T must be in [0, 1)");
   if (p.precision != 0 && p.precision != 1) return fail(GIRG_EINVAL, "precision must be 0 or 1");
+  if (p.type2_batch != 0 && p.type2_batch != 1) return fail(GIRG_EINVAL, "type2_batch must be 0 or 1");
   if (p.model == 0) {
     if (p.d < 1 || p.d > 4) return fail(GIRG_EINVAL, "d must be in [1, 4]");
     if (need_beta && !(p.beta > 2.0)) return fail(GIRG_EINVAL, "beta must be > 2");
@@ -988,6 +992,19 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     HIPCHK(hipStreamSynchronize(st));
     cx.dtab[d] = t;
   }
+  // batched type-II sequences at levels >= 3 (GIRG, d = 2, 3, T > 0)
+  const bool batched = p.type2_batch == 1 && p.T > 0.0 && p.model == 0 && (d == 2 || d == 3);
+  if (batched && g.L > 32) return fail(GIRG_EINVAL, "type2_batch = 1 needs at most 32 weight layers");
+  if (batched && !cx.dtab2[d]) {
+    std::vector<uint32_t> tab(seq_table_fill(d, nullptr, 0), 0u);
+    if (tab.empty()) return fail(GIRG_EDEVICE, "sequence offset table longer than the kernel holds");
+    seq_table_fill(d, tab.data(), tab.size());
+    uint32_t* t = nullptr;
+    HIPCHK(hipMalloc(&t, tab.size() * sizeof(uint32_t)));
+    HIPCHK(hipMemcpyAsync(t, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    cx.dtab2[d] = t;
+  }
 
   Verts v{rec, ids, smort, slayer};
   const bool binomial = p.T > 0.0;
@@ -1034,13 +1051,17 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   };
   Sched sch[4] = {make_sched_src(nsrc, 0), make_sched(0, 1),
                   make_sched_src(binomial ? nsrc : 0, 2), make_sched(0, 3)};
+  // the type-II pass's chunks: those of k_type2, then (batched) as many of
+  // k_type2s over the same sources
+  const uint32_t nch2 = sch[2].nchunks * (batched ? 2u : 1u);
   for (int q = 0; q <= 2; q += 2) {
-    sch[q].ctot = ar.get<uint64_t>(sch[q].nchunks);
-    sch[q].dtot = ar.get<uint64_t>(sch[q].nchunks);
+    const uint32_t nc = q == 2 ? nch2 : sch[q].nchunks;
+    sch[q].ctot = ar.get<uint64_t>(nc);
+    sch[q].dtot = ar.get<uint64_t>(nc);
   }
   uint2* stage = cap ? ar.get<uint2>(cap) : nullptr;
   // every flush but the last of a chunk holds more than 128 edges
-  const uint64_t rcap64 = cap / 128 + 2ull * (sch[0].nchunks + sch[2].nchunks) + (1u << 16);
+  const uint64_t rcap64 = cap / 128 + 2ull * (sch[0].nchunks + nch2) + (1u << 16);
   const uint32_t rcap = (uint32_t)std::min<uint64_t>(rcap64, 0xFFFFFFF0ull);
   uint64_t* rtag = ar.get<uint64_t>(rcap);
   uint64_t* roff = ar.get<uint64_t>(rcap);
@@ -1084,13 +1105,23 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     if (sch[0].nchunks) HIPCHK(launch_type1(g, cx.gd, v, cl, crec, src, sch[0], sg, df0, s1));
     cx.mark("type1", s1);
     cx.mark("-", st);
-    if (sch[2].nchunks)
-      HIPCHK(launch_type2(g, cx.gd, v, cl, crec, src, sch[2], pbt, nlev, cx.dtab[d], sg, df1, st));
+    if (sch[2].nchunks) {
+      HIPCHK(launch_type2(g, cx.gd, v, cl, crec, src, sch[2], pbt, nlev, cx.dtab[d], sg, df1,
+                          batched ? 3u : 255u, st));
+      if (batched) {
+        Sched s2 = sch[2];
+        s2.next = tickets + 4;
+        s2.ctot = sch[2].ctot + sch[2].nchunks;
+        s2.dtot = sch[2].dtot + sch[2].nchunks;
+        HIPCHK(launch_type2s(g, cx.gd, v, cl, crec, src, s2, pbt, nlev, cx.dtab2[d], sg, df1,
+                             sch[2].nchunks, st));
+      }
+    }
     cx.mark("type2", st);
     HIPCHK(join_side(cx, st, overlap, sguard));
     // where each chunk's deferred items start
     HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
-                                {sch[0].nchunks, sch[2].nchunks, 0, 0}, 3u},
+                                {sch[0].nchunks, nch2, 0, 0}, 3u},
                         st));
     HIPCHK(rb.begin(kSmallReadback));
     HIPCHK(rb.add(dn, dcount, 2 * sizeof(unsigned int)));
@@ -1138,7 +1169,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   if (binomial) HIPCHK(launch_near2(g, cx.gd, v, pbt, nlev, sg, st));
   // where each chunk's edges start, in pass order
   HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].ctot, sch[1].ctot, sch[2].ctot, sch[3].ctot},
-                              {sch[0].nchunks, sch[1].nchunks, sch[2].nchunks, sch[3].nchunks}, 1u},
+                              {sch[0].nchunks, sch[1].nchunks, nch2, sch[3].nchunks}, 1u},
                       st));
 
   // total, capacity, records, and the counters (final once the passes end)
@@ -1276,6 +1307,14 @@ static girg_status noalloc_setup(int dev, NoAllocSlot** out) {
       uint32_t* t = reinterpret_cast<uint32_t*>(carve(sz * sizeof(uint32_t)));
       HIPCHK(hipMemcpy(t, g_na_tab, sz * sizeof(uint32_t), hipMemcpyHostToDevice));
       c.dtab[d] = t;
+    }
+    for (int d = 2; d <= 3; ++d) {
+      const size_t sz = seq_table_fill(d, g_na_tab, sizeof(g_na_tab) / sizeof(uint32_t));
+      if (sz == 0 || sz > sizeof(g_na_tab) / sizeof(uint32_t))
+        return fail(GIRG_EDEVICE, "girg_from_points_noalloc: sequence table larger than its buffer");
+      uint32_t* t = reinterpret_cast<uint32_t*>(carve(sz * sizeof(uint32_t)));
+      HIPCHK(hipMemcpy(t, g_na_tab, sz * sizeof(uint32_t), hipMemcpyHostToDevice));
+      c.dtab2[d] = t;
     }
     c.ar.attach(reinterpret_cast<char*>(base + off), kScratchBytes - off);
     sl.ptr = base;

@@ -15,7 +15,7 @@ constexpr int kWave = 64;
 constexpr int kSegExp = 5;       // type-II segment: about 2^5..2^6 expected candidates
 constexpr int kSegMaxBits = 12;  // at most 2^12 segments per item
 
-enum Kind : uint32_t { kKindType1 = 0, kKindType2 = 1, kKindPoints = 2 };
+enum Kind : uint32_t { kKindType1 = 0, kKindType2 = 1, kKindPoints = 2, kKindSeq = 3 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy

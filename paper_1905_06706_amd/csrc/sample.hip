@@ -301,6 +301,13 @@ __device__ __forceinline__ void segment_size(uint64_t N, int e, uint64_t* G, uin
   *nseg = (N + *G - 1) / *G;
 }
 
+// whether an item of N >= 1 candidates has more than one segment, without
+// segment_size's division: raising e to emin keeps 2^e < N (2^emin < N for
+// every N >= 2), so the test on the pbar exponent e (>= 5) decides alone
+__device__ __forceinline__ bool multi_segment(uint64_t N, int e) {
+  return e < 63 && N > (1ull << e);
+}
+
 // ---------------------------------------------------------------------------
 // per-wave edge buffer and its flushes to the staging array
 // ---------------------------------------------------------------------------
@@ -1074,9 +1081,7 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
     const uint32_t cb0 = fwd ? b0 : sr.s, cnb = fwd ? nb : sr.na;
     if (pv.pbar > 0.0 && nb > 0) {
       const uint64_t N = (uint64_t)cna * cnb;
-      uint64_t G, nseg;
-      segment_size(N, pv.e, &G, &nseg);
-      if (nseg > 1) {
+      if (multi_segment(N, pv.e)) {
         rec = ItemRec{ca0, cna, cb0, cnb, cA, cB, lvl | (ci << 8) | (cj << 16) | (gp << 24),
                       (uint32_t)pv.e};
         hv = true;
@@ -1147,7 +1152,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                const Src* __restrict__ src, Sched sc,
                                                const Pbar* __restrict__ pbt, int nlev,
                                                const uint32_t* __restrict__ dtab, Stage sg,
-                                               DeferOut dfo) {
+                                               DeferOut dfo, uint32_t lvl_skip) {
   __shared__ IEnt ibs[4][kICap];
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
@@ -1183,7 +1188,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const Src sr = src[si];
         const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8;
         mine.A = sr.A;
-        if (g->jII[li][lvl]) {
+        // (levels >= lvl_skip: the batched sequences of k_type2s)
+        if (lvl < lvl_skip && g->jII[li][lvl]) {
           if (lvl >= 3) {
             uint32_t qa[D];
             morton_decode<D>(sr.A, qa);
@@ -1339,6 +1345,418 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// batched type-II jump sequences (GIRG, d = 2 or 3, levels >= 3).  The
+// candidates of the distant cell pairs of one source that share pbar are
+// independent Bernoulli(pbar) trials, so one jump sequence runs over their
+// concatenation (Sec. 3.2 applied across cell pairs): for source (layer i,
+// level l, cell X), layer j with CL(i,j) >= l and gap g, the distant cells Y
+// of X's parity table with gap g, in table order, whose V_j^Y is nonempty
+// and whose candidates fit one segment; candidate x |V_j^Y| + y of a pair,
+// the pairs one after another.  Draw t of the sequence uses the counter
+// (t, X, g, l | i << 6 | j << 12 | 3 << 18).  Pairs of more than one segment
+// are deferred to the segmented pass, as in k_type2.
+//
+// A wave keeps rings of staged sources and of their kept cells in LDS.  A
+// source is staged by the whole wave (lanes over its table offsets, one cell
+// record load each; the cells with some layer j of the source are kept in
+// table order, gap 1 first) whenever fewer than 64 sequences wait and the
+// rings have room.  Each lane runs one sequence at a time and takes the next
+// waiting one as soon as its own ends, so the lanes stay busy across
+// sources.  A round walks every lane to the pair holding its next candidate
+// (cell records from the ring, the (first, count) record of V_j^Y from
+// global memory), then takes every lane's candidate and next draw at once;
+// candidates go to the candidate ring, evaluated 64 at a time.  A source's
+// cells are released when its last sequence ends and all older sources are
+// released.  Layers j < 32: a kept cell stores the low 32 bits of its layer
+// mask, which give the rank of V_j^Y among the cell's records.  Pairs of more
+// than 2^(e - 4) candidates (e = 5 - ilogb(pbar)) are not part of a sequence:
+// the walk queues them as items with their own streams, drawn as in k_type2
+// (draws2) whenever 64 are queued, so that no lane holds a long sequence.
+// ---------------------------------------------------------------------------
+constexpr int kSeqWaves = 2;    // waves per workgroup
+constexpr int kSeqEnt = 768;    // kept cells per wave (ring)
+constexpr int kSeqRing = 32;    // staged sources per wave (ring, power of two)
+constexpr int kSeqOff = 120;    // >= the largest parity table (116 offsets at d = 3)
+
+struct SSrc {
+  uint32_t s0, na, X, info;  // info = level | layer << 8 | parity << 16
+  uint32_t e0;               // ring position of its first kept cell
+  uint32_t n1, n;            // kept cells of gap 1; kept cells
+  uint32_t cs;               // sequences of the chunk's sources up to this one
+  uint32_t U1, U2;           // layers among its kept cells of gap 1 / gap 2
+  uint32_t left;             // its sequences not yet ended
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+  return x;
+}
+
+// one draw of a sequence: the skip floor(ln S / ln(1 - pbar)) (clamped at
+// 2^62) and the acceptance uniform Acc; tie: the quotient lies within 1e-12
+// (relative) of an integer >= 1 (decided by the walk: it counts when the skip
+// lands in the sequence or ends exactly at its end).  Mixed precision: the
+// FP32 quotient when both ends of its 2^-13 interval have the same floor.
+template <bool MX>
+__device__ __forceinline__ uint64_t seq_draw(uint32_t k0s, uint32_t k1s, uint32_t X, uint32_t g,
+                                             uint32_t w3, uint32_t t, const PB& pe, double& acc,
+                                             bool& tie, uint32_t& nre) {
+  const U4 o = philox(t, X, g, w3, k0s, k1s);
+  const uint64_t vv = (((uint64_t)o.y << 32) | o.x) >> 11;
+  acc = u53(o.z, o.w);
+  tie = false;
+  if (pe.pbar >= 1.0) return 0;  // every candidate is drawn
+  if (MX) {
+    const uint64_t om = (1ull << 53) - 1 - vv;  // (1 - S) 2^53, exact
+    float l2s = 0.0f;
+    if (om) {
+      const float tt = (float)om * 0x1p-53f;
+      if (tt < 0.0625f)
+        l2s = -tt * (1.0f + tt * (0.5f + tt * (0.33333334f + tt * (0.25f + tt * 0.2f)))) * 1.44269504f;
+      else
+        l2s = __log2f((float)((double)(vv + 1) * 0x1p-53));
+    }
+    const double q32 = (double)(l2s * pe.qs);
+    const double qe = 0x1p-13 * (q32 + 1.0);
+    const double qlo = q32 - qe > 0.0 ? q32 - qe : 0.0, qhi = q32 + qe;
+    if (qhi < 0x1p62 && floor(qlo) == floor(qhi)) return (uint64_t)qhi;
+    ++nre;
+  }
+  const double S = (double)(vv + 1) * 0x1p-53;
+  const double ls = log_pos(S);
+  const double q = ls == 0.0 ? 0.0 : ls * pe.ilg;
+  if (q >= 0.5) {
+    const double fl = rint(q);
+    tie = fabs(q - fl) < 1e-12 * q;
+  }
+  return q >= 0x1p62 ? (1ull << 62) : (uint64_t)q;
+}
+
+// the cell at table offset en of cell X (coordinates qa) at level lvl
+template <int D>
+__device__ __forceinline__ uint32_t offset_cell(const uint32_t* qa, uint32_t en, uint32_t lvl) {
+  const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
+  uint32_t b[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) b[k] = (qa[k] + ((en >> (3 * k)) & 7u) - 3u) & cm;
+  return morton_encode<D>(b);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int D, bool MX>
+__global__ __launch_bounds__(kSeqWaves * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_type2s(
+    const Graph* __restrict__ g, Verts v, const CellL* __restrict__ cl, const uint2* __restrict__ crec,
+    const Src* __restrict__ src, Sched sc, const Pbar* __restrict__ pbt, int nlev,
+    const uint32_t* __restrict__ dtab2, Stage sg, DeferOut dfo, uint32_t coff) {
+  __shared__ uint32_t ltab[kDistHead + (1 << D) * kSeqOff];
+  __shared__ uint32_t ems[kSeqWaves][kSeqEnt];
+  __shared__ uint32_t ebs_[kSeqWaves][kSeqEnt];
+  __shared__ uint8_t eas[kSeqWaves][kSeqEnt];
+  __shared__ SSrc sss[kSeqWaves][kSeqRing];
+  __shared__ Cand cqs[kSeqWaves][kCCap];
+  __shared__ QItem2 iqs[kSeqWaves][kQCap];
+  __shared__ uint2 obs[kSeqWaves][kEdgeBuf2];
+  // the parity tables (offsets of each parity, gap 1 first), once per workgroup
+  {
+    const uint32_t tsz = kDistHead + (1u << D) * dtab2[0];
+    for (uint32_t k = threadIdx.x; k < tsz; k += blockDim.x) ltab[k] = dtab2[k];
+    __syncthreads();
+  }
+  const uint32_t wv = threadIdx.x / kWave;
+  uint32_t* em = ems[wv];   // kept cells: low 32 bits of the layer mask
+  uint32_t* eb = ebs_[wv];  // kept cells: index of the first (first, count) record
+  uint8_t* ea = eas[wv];    // kept cells: table offset | (X < Y) << 7
+  SSrc* ss = sss[wv];
+  Cand* cq = cqs[wv];
+  QItem2* iq = iqs[wv];
+  const uint32_t lane = lane_id();
+  const uint32_t dstride = ltab[0];
+  const uint32_t k0s = g->seed_lo, k1s = g->seed_hi;
+  const int L = g->L;
+  constexpr uint32_t QM = kSeqRing - 1;
+  uint32_t ndraws = 0, ncand = 0, nre = 0;
+  uint64_t nedge = 0;
+  for (;;) {
+    const uint32_t c = next_chunk(sc.next);
+    if (c >= sc.nchunks) break;
+    const uint32_t cc = coff + c;  // the chunk's index among the pass's chunks
+    const uint64_t sb = (uint64_t)c * sc.chunk;
+    const uint64_t se = sb + sc.chunk < sc.nunits ? sb + sc.chunk : sc.nunits;
+    uint32_t dseq = 0;
+    Ring2 r{0, 0, 0, 0};
+    Out out{obs[wv], 0, 0, ((uint64_t)sc.pass << 32) | cc, v.id};
+    // the source window: lane k holds source wb - 64 + k; wm = its eligible
+    // sources not yet staged
+    uint64_t wb = sb, wm = 0;
+    Src wsr{0, 0, 0, 0};
+    bool srcs = sb < se;
+    // rings (positions count from the chunk's start): sources [qt, qh), kept
+    // cells [et, eh); sequences [0, zs) staged, [0, za) taken by lanes
+    uint32_t qt = 0, qh = 0, et = 0, eh = 0, zs = 0, za = 0;
+    // the lane's queued item (draws2)
+    bool iact = false;
+    QItem2 icur{};
+    PB ipe{0.0, 0.0, 0.0f};
+    // the lane's sequence: its source's ring position, gap, layer j, kept
+    // cells [ecur, eend) still ahead; walk state: the current cell pair
+    // (b0, nb, N, orientation xa); rem = the position, from the pair's start,
+    // of the next candidate (once drawn) or of the next draw's start (need);
+    // the last draw's acc and tie; the draw counter td
+    bool act = false, have = false, need = true, tie = false, xa = false;
+    uint32_t slot = 0, gp = 1, j = 0, ecur = 0, eend = 0, s0 = 0, na = 0, X = 0, lvl = 0, li = 0,
+             par = 0, w3 = 0, b0 = 0, nb = 0, td = 0, pidx = 0;
+    PB pe{0.0, 0.0, 0.0f};
+    int pexp = 0;
+    uint64_t rem = 0, N = 0;
+    double acc = 0.0;
+    for (;;) {
+      // --- stage sources while fewer than 64 sequences wait and the rings have room
+      while (srcs && zs - za < (uint32_t)kWave) {
+        if (wm == 0) {
+          if (wb >= se) {
+            srcs = false;
+            break;
+          }
+          const uint64_t sj = wb + lane;
+          bool elig = false;
+          if (sj < se) {
+            wsr = src[sj];
+            const uint32_t lv = wsr.meta & 255u, lj = wsr.meta >> 8;
+            elig = lv >= 3 && g->jII[lj][lv] != 0;
+          }
+          wm = __ballot(elig);
+          wb += kWave;
+          continue;
+        }
+        const int f = __ffsll((long long)wm) - 1;
+        const uint32_t fX = __shfl(wsr.A, f, 64), fmeta = __shfl(wsr.meta, f, 64);
+        const uint32_t flv = fmeta & 255u, fli = fmeta >> 8;
+        uint32_t qa[D], fpar = 0;
+        morton_decode<D>(fX, qa);
+#pragma unroll
+        for (int k = 0; k < D; ++k) fpar |= (qa[k] & 1u) << k;
+        const uint32_t c1 = ltab[1 + 2 * fpar], cn = c1 + ltab[2 + 2 * fpar];
+        if (eh - et + cn > (uint32_t)kSeqEnt || qh - qt >= (uint32_t)kSeqRing) break;  // no room yet
+        const uint32_t fs0 = __shfl(wsr.s, f, 64), fna = __shfl(wsr.na, f, 64);
+        wm &= wm - 1;
+        const uint64_t J = g->jII[fli][flv];
+        const uint32_t mo = g->moff[flv];
+        uint32_t nk = 0, nk1 = 0, u1 = 0, u2 = 0;
+        for (uint32_t k0 = 0; k0 < cn; k0 += kWave) {
+          const uint32_t k = k0 + lane;
+          bool keep = false;
+          const bool g1 = k < c1;
+          uint32_t m = 0, bs = 0, ax = 0;
+          if (k < cn) {
+            const uint32_t Yc = offset_cell<D>(qa, ltab[kDistHead + fpar * dstride + k], flv);
+            const CellL ce = cl[mo + Yc];
+            keep = (ce.mask & J) != 0;
+            m = (uint32_t)ce.mask;
+            bs = ce.base;
+            ax = k | (fX < Yc ? 0x80u : 0u);
+          }
+          const uint64_t mk = __ballot(keep);
+          if (keep) {
+            const uint32_t p = (eh + nk + lanes_below(mk)) % (uint32_t)kSeqEnt;
+            em[p] = m;
+            eb[p] = bs;
+            ea[p] = (uint8_t)ax;
+            if (g1) u1 |= m & (uint32_t)J;
+            else u2 |= m & (uint32_t)J;
+          }
+          nk += (uint32_t)__popcll(mk);
+          nk1 += (uint32_t)__popcll(__ballot(keep && g1));
+        }
+        u1 = wave_or32(u1);
+        u2 = wave_or32(u2);
+        if (nk) {
+          const uint32_t ns = (uint32_t)(__popc(u1) + __popc(u2));
+          if (lane == 0)
+            ss[qh & QM] = SSrc{fs0, fna, fX, flv | (fli << 8) | (fpar << 16), eh, nk1, nk, zs + ns,
+                               u1, u2, ns, 0u};
+          eh += nk;
+          zs += ns;
+          qh += 1;
+        }
+        wave_sync_lds();
+      }
+      // --- idle lanes take the next waiting sequences
+      {
+        const uint64_t mi = __ballot(!act);
+        const uint32_t z = za + lanes_below(mi);
+        if (!act && z < zs) {
+          // the source: the first ring position a with cs(a) > z
+          uint32_t lo = qt, hi = qh;
+          while (lo != hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if (ss[mid & QM].cs <= z) lo = mid + 1;
+            else hi = mid;
+          }
+          const SSrc sv = ss[lo & QM];
+          slot = lo;
+          const uint32_t n1s = (uint32_t)__popc(sv.U1), ns = n1s + (uint32_t)__popc(sv.U2);
+          uint32_t h = z - (sv.cs - ns);
+          uint32_t mm = sv.U1;
+          gp = 1;
+          if (h >= n1s) {
+            h -= n1s;
+            mm = sv.U2;
+            gp = 2;
+          }
+          for (; h > 0; --h) mm &= mm - 1;
+          j = (uint32_t)__ffs(mm) - 1;
+          s0 = sv.s0;
+          na = sv.na;
+          X = sv.X;
+          lvl = sv.info & 255u;
+          li = (sv.info >> 8) & 255u;
+          par = sv.info >> 16;
+          ecur = gp == 1 ? sv.e0 : sv.e0 + sv.n1;
+          eend = gp == 1 ? sv.e0 + sv.n1 : sv.e0 + sv.n;
+          pidx = (uint32_t)((((uint64_t)li * L + j) * nlev + lvl) * 2 + (gp - 1));
+          const Pbar pv = pbt[pidx];
+          pe = PB{pv.pbar, pv.ilg, pv.qscale};
+          pexp = pv.e;
+          w3 = ctr_word3(lvl, li, j, kKindSeq, 0);
+          have = false;
+          need = true;
+          tie = false;
+          rem = 0;
+          N = 0;
+          td = 0;
+          act = pv.pbar > 0.0;
+          if (!act) atomicSub(&ss[slot & QM].left, 1u);  // no candidates: ends at once
+        }
+        const uint32_t nid = (uint32_t)__popcll(mi);
+        za = zs - za < nid ? zs : za + nid;
+      }
+      // the chunk's sequences have all ended: its queued items follow
+      const bool fin = !srcs && za == zs && !__any(act);
+      if (!fin) {
+        // --- walk: move every lane past the pairs that rem passes (a lane
+        // that meets a pair of many candidates queues it as an item; the
+        // walk pauses while the item queue lacks room for 64)
+        bool mv = act && (!have || rem >= N);
+        while (__any(mv) && r.qt - r.qh <= (uint32_t)(kQCap - 64)) {
+          bool hv = false, dn = false;
+          ItemRec rec{};
+          QItem2 dq{};
+          if (mv) {
+            if (have) {
+              rem -= N;
+              have = false;
+            }
+            bool found = false;
+            uint32_t m = 0, p = 0;
+            while (ecur != eend && !found) {
+              p = ecur % (uint32_t)kSeqEnt;
+              m = em[p];
+              ++ecur;
+              found = ((m >> j) & 1u) != 0;
+            }
+            if (found) {
+              const uint32_t ax = ea[p];
+              const uint2 cr = crec[eb[p] + (uint32_t)__popc(m & ((1u << j) - 1u))];
+              b0 = cr.x;
+              nb = cr.y;
+              xa = (ax >> 7) != 0;
+              N = (uint64_t)na * nb;
+              const bool heavy = multi_segment(N, pexp), dense = multi_segment(N, pexp - 4);
+              if (heavy || dense) {
+                uint32_t qa[D];
+                morton_decode<D>(X, qa);
+                const uint32_t Yc = offset_cell<D>(qa, ltab[kDistHead + par * dstride + (ax & 127u)], lvl);
+                const uint32_t cA = xa ? X : Yc, cB = xa ? Yc : X, ci = xa ? li : j, cj = xa ? j : li;
+                if (heavy) {
+                  // more than one segment: the segmented pass, with the pair's own streams
+                  rec = ItemRec{xa ? s0 : b0, xa ? na : nb, xa ? b0 : s0, xa ? nb : na, cA, cB,
+                                lvl | (ci << 8) | (cj << 16) | (gp << 24), (uint32_t)pexp};
+                  hv = true;
+                } else {
+                  // one segment of many candidates: an item with its own stream, as in k_type2
+                  dq = QItem2{cA, cB, ctr_word3(lvl, ci, cj, kKindType2, 0), xa ? s0 : b0, xa ? b0 : s0,
+                              xa ? nb : na, 0u, pidx, 0ull, N};
+                  dn = true;
+                }
+              } else {
+                have = true;
+              }
+            } else {
+              // the sequence ends (no draw after a candidate at its very
+              // end); a tie of its last draw counts when that draw's skip
+              // ends exactly at the end of the sequence
+              if (!need && tie && rem == 0) count_stat(sg.stats, kStatTie);
+              act = false;
+              atomicSub(&ss[slot & QM].left, 1u);
+            }
+          }
+          if (__any(hv)) defer_item(hv, rec, cc, dseq, dfo);
+          enqueue2(dn, dq, iq, r);
+          mv = act && (!have || rem >= N);
+        }
+        // --- the lanes whose rem lies inside their pair: the candidate there
+        // (unless a draw is due first), then the next draw while the
+        // position stays inside the pair
+        bool hc = false;
+        Cand cd{0, 0, 0.0};
+        if (act && have && rem < N) {
+          if (!need) {
+            // the candidate at rem: x rem / nb of V_i^X, y rem % nb of V_j^Y
+            const uint64_t xi = rem / nb, yi = rem - xi * nb;
+            const uint32_t sx = s0 + (uint32_t)xi, sy = b0 + (uint32_t)yi;
+            cd = Cand{xa ? sx : sy, xa ? sy : sx, acc * pe.pbar};
+            hc = true;
+            if (tie) count_stat(sg.stats, kStatTie);
+            rem += 1;
+            need = true;
+          }
+          if (need && rem < N) {
+            rem += seq_draw<MX>(k0s, k1s, X, gp, w3, td, pe, acc, tie, nre);
+            ++td;
+            ++ndraws;
+            need = false;
+          }
+        }
+        const uint64_t mc = __ballot(hc);
+        if (hc) cq[(r.ct + lanes_below(mc)) & (kCCap - 1)] = cd;
+        r.ct += (uint32_t)__popcll(mc);
+        ncand += hc ? 1 : 0;
+        if (r.ct - r.ch >= 64) eval_cands<D, 0, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
+      }
+      // --- the queued items: while 64 are queued or held; at the end all
+      if (fin || r.qt - r.qh >= 64)
+        draws2<D, 0, MX>(g, v, pbt, nlev, iq, cq, r, iact, icur, ipe, fin ? 0u : 64u, sg, out, ndraws,
+                         ncand, nre);
+      if (fin) break;
+      // --- release the oldest sources whose sequences have all ended
+      wave_sync_lds();
+      while (qt != qh && ss[qt & QM].left == 0) {
+        ++qt;
+        et = qt != qh ? ss[qt & QM].e0 : eh;
+      }
+    }
+    while (r.ct != r.ch) eval_cands<D, 0, MX>(g, v, pbt, nlev, cq, r, sg, out, nre);
+    end_chunk(sg, out, sc, c, dseq);
+    nedge += out.off;
+  }
+  const uint64_t sdraws = wave_sum((uint64_t)ndraws), scand = wave_sum((uint64_t)ncand),
+                 sre = wave_sum((uint64_t)nre);
+  if (lane == 0) {
+    if (nedge) atomicAdd(&sg.stats[8 + sc.pass], (unsigned long long)nedge);
+    atomicAdd(&sg.stats[2], (unsigned long long)sdraws);
+    atomicAdd(&sg.stats[4], (unsigned long long)scand);
+    if (sre) atomicAdd(&sg.stats[6], (unsigned long long)sre);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rec_units(const ItemRec* __restrict__ rec, uint32_t nrec,
                                                    int kind, uint64_t* __restrict__ units) {
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1459,17 +1877,37 @@ hipError_t launch_big1(const Graph& g, const Graph* gd, const Verts& v, const It
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
                         int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
-                        hipStream_t st) {
+                        uint32_t lvl_skip, hipStream_t st) {
   const dim3 grid(sc.blocks), block(kWavesPerBlock * kWave);
   const bool mx = use_mixed(g);
   HG_DISPATCH_D({
     if constexpr (MM == 0) {
-      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
-      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
-    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo);
+      if (mx) hipLaunchKernelGGL((k_type2<DD, 0, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo, lvl_skip);
+      else hipLaunchKernelGGL((k_type2<DD, 0, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo, lvl_skip);
+    } else hipLaunchKernelGGL((k_type2<DD, MM, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab, sg, dfo, lvl_skip);
   });
   return hipGetLastError();
 }
+
+hipError_t launch_type2s(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
+                         int nlev, const uint32_t* dtab2, const Stage& sg, const DeferOut& dfo,
+                         uint32_t coff, hipStream_t st) {
+  // workgroups of kSeqWaves waves, as many waves as sc.blocks workgroups hold
+  const dim3 grid(sc.blocks * (kWavesPerBlock / kSeqWaves)), block(kSeqWaves * kWave);
+  const bool mx = use_mixed(g);
+  if (g.model != 0 || g.d < 2 || g.d > 3 || g.L > 32) return hipErrorInvalidValue;
+  if (g.d == 2) {
+    if (mx) hipLaunchKernelGGL((k_type2s<2, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab2, sg, dfo, coff);
+    else hipLaunchKernelGGL((k_type2s<2, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab2, sg, dfo, coff);
+  } else {
+    if (mx) hipLaunchKernelGGL((k_type2s<3, true>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab2, sg, dfo, coff);
+    else hipLaunchKernelGGL((k_type2s<3, false>), grid, block, 0, st, gd, v, cl, crec, src, sc, pbt, nlev, dtab2, sg, dfo, coff);
+  }
+  return hipGetLastError();
+}
+
+
 
 // the distant offsets of a parity pattern: children of the parent's
 // neighbours (offset delta_k = jk - 2 - parity_k) that are not neighbours,
@@ -1520,6 +1958,37 @@ std::vector<uint32_t> distant_table(int d) {
   std::vector<uint32_t> tab(distant_table_fill(d, nullptr, 0), 0u);
   distant_table_fill(d, tab.data(), tab.size());
   return tab;
+}
+
+// the distant offsets of each parity split by gap: head[1 + 2p] = gap-1
+// count, head[2 + 2p] = gap-2 count; row p holds the gap-1 entries, then the
+// gap-2 entries, each in the table order of distant_offsets
+size_t seq_table_fill(int d, uint32_t* out, size_t cap) {
+  const int npar = 1 << d;
+  uint32_t stride = 1;
+  for (int par = 0; par < npar; ++par) {
+    const uint32_t c = distant_offsets(d, par, [](uint32_t, uint32_t) {});
+    stride = c > stride ? c : stride;
+  }
+  if (stride > (uint32_t)kSeqOff) return 0;  // (k_type2s holds kSeqOff offsets per parity)
+  const size_t size = (size_t)kDistHead + (size_t)npar * stride;
+  if (!out || cap < size) return size;
+  for (size_t k = 0; k < size; ++k) out[k] = 0u;
+  out[0] = stride;
+  for (int par = 0; par < npar; ++par) {
+    uint32_t t = 0;
+    for (uint32_t gp = 1; gp <= 2; ++gp) {
+      uint32_t cnt = 0;
+      distant_offsets(d, par, [&](uint32_t, uint32_t en) {
+        if ((en >> 28) == gp) {
+          out[kDistHead + (size_t)par * stride + t++] = en;
+          ++cnt;
+        }
+      });
+      out[gp == 1 ? 1 + 2 * par : 2 + 2 * par] = cnt;
+    }
+  }
+  return size;
 }
 
 hipError_t launch_heavy2(const Graph& g, const Graph* gd, const Verts& v, const ItemRec* rec,

@@ -121,10 +121,25 @@ std::vector<uint32_t> distant_table(int d);
 // size (and writes nothing when out is null or cap is smaller)
 size_t distant_table_fill(int d, uint32_t* out, size_t cap);
 
+// sources at levels >= lvl_skip are left to launch_type2s (255: none)
 hipError_t launch_type2(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
                         int nlev, const uint32_t* dtab, const Stage& sg, const DeferOut& dfo,
-                        hipStream_t st);
+                        uint32_t lvl_skip, hipStream_t st);
+// batched type-II sequences of the sources at levels >= 3 (GIRG, d = 2, 3):
+// sc covers the same source chunks as the type-II pass, with its own ticket;
+// chunk c writes its totals at sc.ctot[c] / sc.dtot[c] and tags its edges
+// and deferred pairs as chunk coff + c of the type-II pass
+hipError_t launch_type2s(const Graph& g, const Graph* gd, const Verts& v, const CellL* cl,
+                         const uint2* crec, const Src* src, const Sched& sc, const Pbar* pbt,
+                         int nlev, const uint32_t* dtab2, const Stage& sg, const DeferOut& dfo,
+                         uint32_t coff, hipStream_t st);
+// the distant offsets per parity split by gap (launch_type2s): head[0] =
+// stride, head[1 + 2p] / head[2 + 2p] = gap-1 / gap-2 counts, row p at
+// kDistHead + p * stride (gap-1 entries first); returns the size, writes
+// nothing when out is null or cap is smaller; 0 if a row is longer than the
+// batched kernel holds
+size_t seq_table_fill(int d, uint32_t* out, size_t cap);
 // the listed type-II candidates inside the band |Acc - p_uv / pbar| < 1e-12
 // counted into stats[12] (one small grid; after both type-II passes)
 hipError_t launch_near2(const Graph& g, const Graph* gd, const Verts& v, const Pbar* pbt, int nlev,

@@ -112,7 +112,7 @@ def compare(gpu_edges: np.ndarray, run, *, allow_extra: int = 0, oriented: bool 
     return rep
 
 
-def level3_sample(edges, x, run, mod: int):
+def level3_sample(edges, x, run, mod: int, batched: bool = False):
     """Edges of the items the oracle samples with filter_level = 3 and
     filter_mod = mod, filter_rem = 0: every item above level 3, and below it
     those whose A-side level-3 ancestor is 0 mod `mod`.  An item of a pair
@@ -138,7 +138,34 @@ def level3_sample(edges, x, run, mod: int):
     far2 = torch.zeros(len(u), dtype=torch.bool, device=dev)
     for k in range(d):
         far2 |= torch.remainder((c3[k] >> 1)[u] - (c3[k] >> 1)[v], 4) == 2
-    keep = (CL[layer[u], layer[v]] < 3) | far2 | (torch.remainder(torch.minimum(m3[u], m3[v]), mod) == 0)
+    sel = torch.minimum(m3[u], m3[v])
+    if batched:
+        # type-II pairs at levels >= 3 belong to the sequence of the source
+        # cell X that lists the other cell (first nonzero offset positive):
+        # selected by X's level-3 ancestor
+        cl_uv = CL[layer[u], layer[v]]
+        lvl = torch.full_like(u, 1 << 20)  # the first level at which the cells are not neighbours
+        for lv in range(1, 33 // d + 1):
+            side = 1 << lv
+            cu = (x * float(side)).long()
+            far = torch.zeros(len(u), dtype=torch.bool, device=dev)
+            for k in range(d):
+                df = torch.remainder(cu[k][u] - cu[k][v], side)
+                far |= torch.minimum(df, side - df) > 1
+            lvl = torch.where(far & (lvl == (1 << 20)), torch.full_like(lvl, lv), lvl)
+        t2 = (lvl >= 3) & (lvl <= cl_uv)
+        if bool(t2.any()):
+            side = (1 << lvl.clamp(max=30)).to(torch.int64)
+            first = torch.zeros(len(u), dtype=torch.int64, device=dev)
+            for k in range(d):
+                cu = torch.floor(x[k][u] * side.double()).long()
+                cv = torch.floor(x[k][v] * side.double()).long()
+                dl = torch.remainder(cv - cu, side)
+                dl = torch.where(dl >= side // 2, dl - side, dl)
+                first = torch.where(first == 0, dl, first)
+            xs_u = first > 0  # u's cell is the source
+            sel = torch.where(t2, torch.where(xs_u, m3[u], m3[v]), sel)
+    keep = (CL[layer[u], layer[v]] < 3) | far2 | (torch.remainder(sel, mod) == 0)
     return edges[keep]
 
 

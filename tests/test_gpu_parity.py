@@ -30,6 +30,8 @@ def run_both(hg, orc, w, x, *, T, c, seed, model=0, R=0.0, alpha=0.0, **kw):
     res = hg.from_points(dev(w), dev(x.T), T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, **kw)
     ge = res.edges.cpu().numpy().view(np.uint32)
     kw.pop("precision", None)  # the oracle decides in FP64 only
+    if kw.pop("type2_batch", 0):
+        kw["batch_type2"] = True
     run = orc.run(w, x, T=T, c=c, seed=seed, model=model, R=R, alpha=alpha, keep=True, **kw)
     return ge, res.info, run
 
@@ -268,3 +270,46 @@ def test_c_solve_with_a_large_heavy_tail(hg, orc, n, d, beta, T, deg, seed):
     assert res.info["c"] == pytest.approx(orc.solve_c(w, d, T, deg), rel=1e-12)
     run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True)
     compare(res.edges.cpu().numpy().view(np.uint32), run, info=res.info)
+
+
+@pytest.mark.parametrize("d,n,T,seed,prec,bias", [(2, 12000, 0.5, 2, 0, 0), (3, 9000, 0.8, 4, 0, 0),
+                                                  (3, 9000, 0.8, 4, 1, 0), (2, 6000, 0.3, 9, 1, 2),
+                                                  (3, 4000, 0.6, 12, 0, 2), (2, 20000, 0.9, 13, 0, -1)])
+def test_batched_from_points(hg, orc, d, n, T, seed, prec, bias):
+    """type2_batch = 1: the batched type-II sequences against the oracle's
+    (batch_type2), in FP64 and with the FP32 filter."""
+    w = synth.pareto_weights(n, 2.4, seed)
+    x = synth.positions(n, d, seed)
+    c = orc.solve_c(w, d, T, 14.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=seed, cl_bias=bias, type2_batch=1,
+                             precision=prec)
+    compare(ge, run, info=info)
+    assert run.stats["seqs"] > 0
+    assert info["tests"] == run.stats["tests"]
+    assert info["draws"] == run.stats["draws"]
+    assert info["candidates"] == run.stats["candidates"]
+    assert info["type2_edges"] == run.stats["type2_edges"]
+
+
+def test_batched_clustered_and_heavy(hg, orc):
+    """Clustered points and heavy tails: sequences with many cell pairs,
+    segmented pairs deferred from inside sequences."""
+    n, d, T = 12000, 2, 0.7
+    w = synth.pareto_weights(n, 2.1, 31)
+    x = synth.clustered_positions(n, d, 31)
+    c = orc.solve_c(w, d, T, 14.0)
+    ge, info, run = run_both(hg, orc, w, x, T=T, c=c, seed=31, cl_bias=1, type2_batch=1)
+    compare(ge, run, info=info)
+    assert info["heavy_items"] > 0
+    assert info["draws"] == run.stats["draws"]
+
+
+@pytest.mark.parametrize("d,n,beta,T,seed", [(2, 2**17, 2.7, 0.5, 22), (3, 2**17, 2.3, 0.8, 23)])
+def test_batched_mixed_equals_fp64(hg, d, n, beta, T, seed):
+    kw = dict(d=d, beta=beta, T=T, avg_deg=16.0, seed=seed, type2_batch=1)
+    a = hg.generate(n, precision=0, **kw)
+    b = hg.generate(n, precision=1, **kw)
+    assert np.array_equal(a.edges.cpu().numpy(), b.edges.cpu().numpy())
+    assert b.info["rechecks"] > 0
+    for k in ("tests", "draws", "candidates", "type1_edges", "type2_edges"):
+        assert a.info[k] == b.info[k], k

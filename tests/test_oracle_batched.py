@@ -11,7 +11,7 @@ from tests import synth
 from tests.test_oracle_sampler import _chi2_pvalue, girg_p_numpy, pairset
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d", [2, 3])
 def test_batched_coverage_every_pair_exactly_once(orc, d):
     """pbar = 1 and every candidate accepted: every unordered vertex pair is
     emitted once, and the sequences hold several cell pairs."""
@@ -23,8 +23,7 @@ def test_batched_coverage_every_pair_exactly_once(orc, d):
         assert len(e) == n * (n - 1) // 2 == len(pairset(e))
         assert np.all(e[:, 0] != e[:, 1])
         assert run.stats["seqs"] > 0
-        if d > 1:  # at d = 1 a source has at most one distant cell per gap
-            assert run.stats["type2_items"] > 1.5 * run.stats["seqs"]
+        assert run.stats["type2_items"] > 1.5 * run.stats["seqs"]
 
 
 def _batched_freqs(orc, w, x, c, T, S, **kw):
@@ -40,7 +39,7 @@ def _batched_freqs(orc, w, x, c, T, S, **kw):
     return cnt + cnt.T, acc
 
 
-@pytest.mark.parametrize("d,n,T,bias", [(1, 16, 0.5, 4), (2, 16, 0.4, 4), (3, 40, 0.8, 3)])
+@pytest.mark.parametrize("d,n,T,bias", [(2, 16, 0.4, 4), (2, 24, 0.7, 3), (3, 40, 0.8, 3)])
 def test_batched_chi_square(orc, d, n, T, bias):
     """Per-pair edge frequencies over many seeds against p_uv of Eq. (1)."""
     w = synth.pareto_weights(n, 2.5, 40 + d)
@@ -51,8 +50,7 @@ def test_batched_chi_square(orc, d, n, T, bias):
     S = 6000
     cnt, acc = _batched_freqs(orc, w, x, c, T, S, cl_bias=bias)
     assert acc["seqs"] > 0 and acc["candidates"] > 0
-    if d > 1:
-        assert acc["type2_items"] > 1.5 * acc["seqs"]
+    assert acc["type2_items"] > 1.5 * acc["seqs"]
     assert _chi2_pvalue(cnt, p, S) > 1e-4
 
 
@@ -123,3 +121,16 @@ def test_batched_split_runs_equal_plain_run(orc, d, T):
     assert np.array_equal(okeys(split.edges), okeys(plain.edges))
     for k in ("draws", "candidates"):
         assert split.stats[k] == plain.stats[k], k
+
+
+def test_batching_applies_to_girg_d2_d3_only(orc):
+    """At d = 1 (one distant cell per gap) and for the HRG the option changes
+    nothing: the same edges from the same per-cell-pair streams."""
+    n = 3000
+    w = synth.pareto_weights(n, 2.5, 6)
+    x = synth.positions(n, 1, 6)
+    c = orc.solve_c(w, 1, 0.5, 10.0)
+    a = orc.run(w, x, T=0.5, c=c, seed=2)
+    b = orc.run(w, x, T=0.5, c=c, seed=2, batch_type2=True)
+    assert b.stats["seqs"] == 0
+    assert np.array_equal(a.edges, b.edges)

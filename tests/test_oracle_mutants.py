@@ -11,6 +11,7 @@ import oracle
 from tests import test_oracle_degree as deg
 from tests import test_oracle_primitives as prim
 from tests import test_oracle_sampler as smp
+from tests import test_oracle_batched as bat
 from tests import test_oracle_segments as seg
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -48,6 +49,14 @@ def pin_coverage(orc):
     smp.test_coverage_every_pair_exactly_once(orc, 2, 2, -1)
 
 
+def pin_batched_chi2(orc):
+    bat.test_batched_chi_square(orc, 2, 16, 0.4, 4)
+
+
+def pin_batched_coverage(orc):
+    bat.test_batched_coverage_every_pair_exactly_once(orc, 2)
+
+
 # (name, text in oracle.c, its replacement, the pin that must fail)
 MUTANTS = [
     ("segment start skips a candidate", "uint64_t k = s * G, kend",
@@ -81,6 +90,12 @@ MUTANTS = [
      "int pos = b * d + k;", pin_morton),
     ("neighbour pairs miss the own-cell layer pairs", "if (A == B && j < i) continue;",
      "if (A == B && j <= i) continue;", pin_coverage),
+    ("sequences: acceptance without the bound", "if (pbar * Acc < puv) emit(R, u, v, 1);",
+     "if (Acc < puv) emit(R, u, v, 1);", pin_batched_chi2),
+    ("sequences: skip rate of half the bound", "double lg1 = log1p(-pbar);",
+     "double lg1 = log1p(-0.5 * pbar);", pin_batched_chi2),
+    ("sequences: the last cell pair never sampled", "for (int k = 0; k < nit; k++) total +=",
+     "for (int k = 0; k + 1 < nit; k++) total +=", pin_batched_coverage),
 ]
 
 
