@@ -292,8 +292,9 @@ def test_batched_from_points(hg, orc, d, n, T, seed, prec, bias):
 
 
 def test_batched_clustered_and_heavy(hg, orc):
-    """Clustered points and heavy tails: sequences with many cell pairs,
-    segmented pairs deferred from inside sequences."""
+    """Clustered points and heavy tails: sequences with many cell pairs, and
+    from inside sequences both pairs of many candidates (queued with their own
+    streams) and segmented pairs (deferred)."""
     n, d, T = 12000, 2, 0.7
     w = synth.pareto_weights(n, 2.1, 31)
     x = synth.clustered_positions(n, d, 31)
