@@ -114,3 +114,21 @@ def test_fullsize_girg_d3_n1e7_whole(hg):
     assert rep["gpu"] > 5 * n
     for k in ("tests", "draws", "candidates"):
         assert res.info[k] == run.stats[k], k
+
+
+def test_fullsize_girg_d3_n1e7_batched_sampled(hg, orc):
+    """The same graph with batched type-II sequences (type2_batch = 1), the
+    FP32 filter with FP64 recheck: every item above level 3 and the sequences
+    of 1/512 of the level-3 subtrees (by the source cell's ancestor) against
+    the oracle's batched run on the GPU's points and c."""
+    n, d, beta, T, deg, seed = 10**7, 3, 2.3, 0.8, 20.0, 4
+    print(f"[fullsize] girg n={n} d={d} T={T} batched sampled", flush=True)
+    res = hg.generate(n, d=d, beta=beta, T=T, avg_deg=deg, seed=seed, precision=1, type2_batch=1)
+    wd, xd = hg.points(n, d, beta, seed=seed)
+    w, x = wd.cpu().numpy(), np.ascontiguousarray(xd.cpu().numpy().T)
+    run = orc.run(w, x, T=T, c=res.info["c"], seed=seed, keep=True, filter_level=3, filter_mod=512,
+                  filter_rem=0, batch_type2=True)
+    sub = level3_sample(res.edges, xd, run, 512, batched=True)
+    rep = compare(sub.cpu().numpy().view(np.uint32), run)
+    assert rep["oracle"] > 10**6
+    del xd, sub
