@@ -49,6 +49,12 @@ def test_noalloc_equals_from_points_twice(hg):
     one_case(hg, 30000, 3, 0.8, 4, precision=1)
 
 
+def test_noalloc_batched_type2(hg):
+    # the batched type-II sequences use the array's own offset tables
+    one_case(hg, 60000, 3, 0.8, 6, type2_batch=1)
+    one_case(hg, 20000, 2, 0.5, 7, precision=1, type2_batch=1)
+
+
 def test_noalloc_threshold_and_hrg(hg):
     one_case(hg, 50000, 1, 0.0, 5)
     import torch
