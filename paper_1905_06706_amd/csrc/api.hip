@@ -91,6 +91,183 @@ void Arena::release() {
 }
 
 // ---------------------------------------------------------------------------
+// constant c from the average degree (Sec. 4.1, App. B.2).  f(c) = E[avg
+// degree] is monotone in c; its closed form has an error term over E_R, the
+// ordered pairs whose saturation radius k exceeds 1/2.  E_R only involves the
+// heaviest vertices: with weights sorted in descending order, the partners of
+// u form a prefix whose length shrinks as u gets lighter, so prefix sums of w
+// and w^(1/T) give each vertex's term in O(1) (the O(|R|) evaluation).
+// ---------------------------------------------------------------------------
+struct CSolve {
+  uint64_t n;
+  int d;
+  double T, W;
+  std::vector<double> h;        // heaviest weights (the tail), descending
+  std::vector<double> hp;       // h^(1/T)
+  std::vector<double> sw, sw2;  // suffix sums over h: w, w^2
+  std::vector<double> sp, sp2;  // suffix sums over h: w^(1/T), w^(2/T)
+  // sums over the weights outside h: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
+  double out_w = 0.0, out_q1 = 0.0, out_p = 0.0, out_q2 = 0.0;
+  double wcut;  // every weight not in h is <= wcut
+
+  // a running sum in two doubles (Knuth's two-sum), products added exactly
+  // (FMA error term): at least as accurate as a 64-bit long double sum, and
+  // several times faster than x87 arithmetic
+  struct DSum {
+    double hi = 0.0, lo = 0.0;
+    void add(double x) {
+      const double s = hi + x, bb = s - hi;
+      lo += (hi - (s - bb)) + (x - bb);
+      hi = s;
+    }
+    void add_sq(double x) {
+      const double p = x * x;
+      add(p);
+      lo += std::fma(x, x, -p);
+    }
+    double value() const { return hi + lo; }
+  };
+
+  // h must already be in descending order; hp (h^(1/T), same order) may be
+  // given, else it is computed here
+  void prepare(bool have_hp = false) {
+    const size_t K = h.size();
+    if (!have_hp) hp.resize(K);
+    sw.resize(K + 1);
+    sw2.resize(K + 1);
+    sp.resize(K + 1);
+    sp2.resize(K + 1);
+    sw[K] = sw2[K] = sp[K] = sp2[K] = 0.0;
+    DSum a, b, e, f;
+    for (size_t k = K; k-- > 0;) {
+      if (!have_hp) hp[k] = T > 0.0 ? std::pow(h[k], 1.0 / T) : 0.0;
+      a.add(h[k]);
+      b.add_sq(h[k]);
+      e.add(hp[k]);
+      f.add_sq(hp[k]);
+      sw[k] = a.value();
+      sw2[k] = b.value();
+      sp[k] = e.value();
+      sp2[k] = f.value();
+    }
+  }
+
+  // a pair (u, v) is in E_R iff w_u w_v > th(c)
+  double th(double c) const {
+    return T > 0.0 ? std::ldexp(W / std::pow(c, T), -d) : W / std::ldexp(std::pow(c, (double)d), d);
+  }
+  // E_R within h, i.e. no pair with a weight outside h, at this c (and at
+  // every smaller c: th decreases in c)
+  bool complete_at(double c) const { return h.empty() || !(h[0] * wcut > th(c)); }
+
+  // expected average degree (App. B.2): E[X_uv] = 1 on E_R and the closed
+  // form A x - B x^(1/T) (T = 0: A x), x = w_u w_v / W, elsewhere.  The pairs
+  // outside E_R are summed directly from suffix sums over h and the sums over
+  // the weights outside h (all of whose pairs are outside E_R when h is
+  // complete), so no large excess over E_R is formed and subtracted.
+  double f(double c) {
+    const double th = this->th(c);
+    double A, B = 0.0;
+    if (T > 0.0) {
+      A = std::pow(c, T) * std::ldexp(1.0, d) / (1.0 - T);
+      B = c * std::pow(2.0, d / T) / (1.0 / T - 1.0);
+    } else {
+      A = std::ldexp(std::pow(c, (double)d), d);
+    }
+    const double WT = T > 0.0 ? std::pow(W, 1.0 / T) : 1.0;
+    const size_t K = h.size();
+    const double P = (K ? sp[0] : 0.0) + out_p;
+    long double cnt = 0.0L, s1 = 0.0L, s2 = 0.0L;  // s1 = sum x, s2 = sum x^(1/T) off E_R
+    size_t m = K;
+    for (size_t u = 0; u < K; ++u) {
+      const double wu = h[u];
+      while (m > 0 && !(wu * h[m - 1] > th)) --m;
+      if (m == 0) {
+        // no vertex of h from u on has an E_R partner
+        s1 += ((long double)W * sw[u] - sw2[u]) / W;
+        if (T > 0.0) s2 += ((long double)P * sp[u] - sp2[u]) / WT;
+        break;
+      }
+      const bool self_out = u >= m;
+      cnt += (long double)(m - (self_out ? 0 : 1));
+      s1 += (long double)(wu / W) * (sw[m] - (self_out ? wu : 0.0) + out_w);
+      if (T > 0.0) s2 += (long double)(hp[u] / WT) * (sp[m] - (self_out ? hp[u] : 0.0) + out_p);
+    }
+    // vertices outside h: every other vertex is a partner off E_R
+    s1 += (long double)out_w - out_q1;
+    if (T > 0.0) s2 += (long double)out_p * P / WT - out_q2;
+    return (double)(((long double)A * s1 - (long double)B * s2 + cnt) / (long double)n);
+  }
+
+  // bracket by doubling / halving, then regula falsi on log c with the
+  // Anderson-Bjorck scaling of a stale end, until the bracket is a few ulps
+  // wide; returns its upper end.  When f hits the target exactly at the upper
+  // end (common once the bracket is narrow, and where the secant would stall),
+  // a point two ulps below closes the bracket.  f is
+  // evaluated exactly wherever h is complete, i.e. at every c up to some
+  // bound.  A lower end is only taken where f < target and an upper end where
+  // f >= target, so when h is complete at the final upper end (checked by the
+  // caller) both ends were evaluated exactly and the root lies between them,
+  // whatever inexact values steered the search on the way.
+  // A hint (an earlier estimate of c, e.g. from a shorter tail) starts the
+  // bracket at hint (1 -+ 1/64), widened by factors of 2 until f changes sign.
+  int solve(double target, double* out, double hint = 0.0) {
+    double lo = 1.0, hi = 1.0, flo, fhi;
+    int it = 0;
+    if (hint > 0.0 && std::isfinite(hint)) {
+      lo = hint * (1.0 - 1.0 / 64.0);
+      hi = hint * (1.0 + 1.0 / 64.0);
+      flo = f(lo) - target;
+      fhi = f(hi) - target;
+      // f increases with c: at most one of these loops runs
+      while (!(flo < 0.0)) { hi = lo; fhi = flo; lo *= 0.5; flo = f(lo) - target; if (++it > 2000) return -1; }
+      while (fhi < 0.0) { lo = hi; flo = fhi; hi *= 2.0; fhi = f(hi) - target; if (++it > 2000) return -1; }
+    } else {
+      flo = fhi = f(1.0) - target;
+      if (flo < 0.0) {
+        while (fhi < 0.0) { lo = hi; flo = fhi; hi *= 2.0; fhi = f(hi) - target; if (++it > 2000) return -1; }
+      } else {
+        while (!(flo < 0.0)) { hi = lo; fhi = flo; lo *= 0.5; flo = f(lo) - target; if (++it > 2000) return -1; }
+      }
+    }
+    double a = std::log(lo), b = std::log(hi);
+    int side = 0;
+    for (it = 0; it < 200; ++it) {
+      if (!(hi > lo) || hi - lo <= 4.0 * std::ldexp(hi, -52)) break;
+      if (fhi == 0.0) {
+        const double c = hi - 2.0 * std::ldexp(hi, -52);
+        if (!(c > lo)) break;
+        const double fc = f(c) - target;
+        if (fc < 0.0) { lo = c; a = std::log(c); flo = fc; }
+        else { hi = c; b = std::log(c); fhi = fc; }
+        side = 0;
+        continue;
+      }
+      double x = (fhi == flo) ? 0.5 * (a + b) : b - fhi * (b - a) / (fhi - flo);
+      if (!(x > a && x < b)) x = 0.5 * (a + b);
+      double c = std::exp(x);
+      if (!(c > lo && c < hi)) {
+        c = lo + 0.5 * (hi - lo);
+        x = std::log(c);
+        if (!(c > lo && c < hi)) break;
+      }
+      const double fc = f(c) - target;
+      if (fc < 0.0) {
+        if (side == -1) { const double m = 1.0 - fc / flo; fhi *= m > 0.0 ? m : 0.5; }
+        lo = c; a = x; flo = fc;
+        side = -1;
+      } else {
+        if (side == 1) { const double m = 1.0 - fc / fhi; flo *= m > 0.0 ? m : 0.5; }
+        hi = c; b = x; fhi = fc;
+        side = 1;
+      }
+    }
+    *out = hi;
+    return 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // per-device context
 // ---------------------------------------------------------------------------
 struct Ctx {
@@ -138,6 +315,9 @@ struct Ctx {
   // allocation of the main stream reuses memory still in use there
   Arena ar_side;
   double* red_side = nullptr;  // 8 doubles
+  // the c solve's host buffers (the tail and its sums), kept from call to call
+  CSolve cs;
+  std::vector<double> cs_asc, cs_ascp;
   std::mutex mu;
   // stage timing (HIP events), enabled by girg_set_profiling: a stage's time
   // runs from the event before it to its own, both on the stream it ran on;
@@ -305,9 +485,12 @@ class Readback {
 constexpr size_t kSmallReadback = 1 << 16;
 
 // contexts per (device, slot): slot 0 serves the single-graph calls, slots
-// 1.. the workers of girg_generate_batch (each with its own stream)
+// 1.. the workers of girg_generate_batch (each with its own stream).  The map
+// is never destroyed: a context's destructor calls HIP, whose runtime (and a
+// profiler attached to it) may already be shut down when static objects are
+// destroyed at process exit.  girg_release frees a device's contexts.
 static std::mutex g_ctx_mu;
-static std::map<std::pair<int, int>, std::unique_ptr<Ctx>> g_ctx;
+static auto& g_ctx = *new std::map<std::pair<int, int>, std::unique_ptr<Ctx>>();
 
 static girg_status get_ctx(Ctx** out, int slot = 0) {
   int dev = 0;
@@ -384,152 +567,6 @@ static int bitlen(uint64_t v) {
   while (v) { ++b; v >>= 1; }
   return b;
 }
-
-// ---------------------------------------------------------------------------
-// constant c from the average degree (Sec. 4.1, App. B.2).  f(c) = E[avg
-// degree] is monotone in c; its closed form has an error term over E_R, the
-// ordered pairs whose saturation radius k exceeds 1/2.  E_R only involves the
-// heaviest vertices: with weights sorted in descending order, the partners of
-// u form a prefix whose length shrinks as u gets lighter, so prefix sums of w
-// and w^(1/T) give each vertex's term in O(1) (the O(|R|) evaluation).
-// ---------------------------------------------------------------------------
-struct CSolve {
-  uint64_t n;
-  int d;
-  double T, W;
-  std::vector<double> h;        // heaviest weights (the tail), descending
-  std::vector<double> hp;       // h^(1/T)
-  std::vector<double> sw, sw2;  // suffix sums over h: w, w^2
-  std::vector<double> sp, sp2;  // suffix sums over h: w^(1/T), w^(2/T)
-  // sums over the weights outside h: w, w^2 / W, w^(1/T), (w^2 / W)^(1/T)
-  double out_w = 0.0, out_q1 = 0.0, out_p = 0.0, out_q2 = 0.0;
-  double wcut;  // every weight not in h is <= wcut
-
-  // h must already be in descending order; hp (h^(1/T), same order) may be
-  // given, else it is computed here
-  void prepare(bool have_hp = false) {
-    const size_t K = h.size();
-    if (!have_hp) hp.assign(K, 0.0);
-    sw.assign(K + 1, 0.0);
-    sw2.assign(K + 1, 0.0);
-    sp.assign(K + 1, 0.0);
-    sp2.assign(K + 1, 0.0);
-    long double a = 0.0L, b = 0.0L, e = 0.0L, f = 0.0L;
-    for (size_t k = K; k-- > 0;) {
-      if (!have_hp) hp[k] = T > 0.0 ? std::pow(h[k], 1.0 / T) : 0.0;
-      a += h[k];
-      b += (long double)h[k] * h[k];
-      e += hp[k];
-      f += (long double)hp[k] * hp[k];
-      sw[k] = (double)a;
-      sw2[k] = (double)b;
-      sp[k] = (double)e;
-      sp2[k] = (double)f;
-    }
-  }
-
-  // a pair (u, v) is in E_R iff w_u w_v > th(c)
-  double th(double c) const {
-    return T > 0.0 ? std::ldexp(W / std::pow(c, T), -d) : W / std::ldexp(std::pow(c, (double)d), d);
-  }
-  // E_R within h, i.e. no pair with a weight outside h, at this c (and at
-  // every smaller c: th decreases in c)
-  bool complete_at(double c) const { return h.empty() || !(h[0] * wcut > th(c)); }
-
-  // expected average degree (App. B.2): E[X_uv] = 1 on E_R and the closed
-  // form A x - B x^(1/T) (T = 0: A x), x = w_u w_v / W, elsewhere.  The pairs
-  // outside E_R are summed directly from suffix sums over h and the sums over
-  // the weights outside h (all of whose pairs are outside E_R when h is
-  // complete), so no large excess over E_R is formed and subtracted.
-  double f(double c) {
-    const double th = this->th(c);
-    double A, B = 0.0;
-    if (T > 0.0) {
-      A = std::pow(c, T) * std::ldexp(1.0, d) / (1.0 - T);
-      B = c * std::pow(2.0, d / T) / (1.0 / T - 1.0);
-    } else {
-      A = std::ldexp(std::pow(c, (double)d), d);
-    }
-    const double WT = T > 0.0 ? std::pow(W, 1.0 / T) : 1.0;
-    const size_t K = h.size();
-    const double P = (K ? sp[0] : 0.0) + out_p;
-    long double cnt = 0.0L, s1 = 0.0L, s2 = 0.0L;  // s1 = sum x, s2 = sum x^(1/T) off E_R
-    size_t m = K;
-    for (size_t u = 0; u < K; ++u) {
-      const double wu = h[u];
-      while (m > 0 && !(wu * h[m - 1] > th)) --m;
-      if (m == 0) {
-        // no vertex of h from u on has an E_R partner
-        s1 += ((long double)W * sw[u] - sw2[u]) / W;
-        if (T > 0.0) s2 += ((long double)P * sp[u] - sp2[u]) / WT;
-        break;
-      }
-      const bool self_out = u >= m;
-      cnt += (long double)(m - (self_out ? 0 : 1));
-      s1 += (long double)(wu / W) * (sw[m] - (self_out ? wu : 0.0) + out_w);
-      if (T > 0.0) s2 += (long double)(hp[u] / WT) * (sp[m] - (self_out ? hp[u] : 0.0) + out_p);
-    }
-    // vertices outside h: every other vertex is a partner off E_R
-    s1 += (long double)out_w - out_q1;
-    if (T > 0.0) s2 += (long double)out_p * P / WT - out_q2;
-    return (double)(((long double)A * s1 - (long double)B * s2 + cnt) / (long double)n);
-  }
-
-  // bracket by doubling / halving, then regula falsi on log c with the
-  // Anderson-Bjorck scaling of a stale end, until the bracket is a few ulps
-  // wide; returns its upper end.  When f hits the target exactly at the upper
-  // end (common once the bracket is narrow, and where the secant would stall),
-  // a point two ulps below closes the bracket.  f is
-  // evaluated exactly wherever h is complete, i.e. at every c up to some
-  // bound.  A lower end is only taken where f < target and an upper end where
-  // f >= target, so when h is complete at the final upper end (checked by the
-  // caller) both ends were evaluated exactly and the root lies between them,
-  // whatever inexact values steered the search on the way.
-  int solve(double target, double* out) {
-    double lo = 1.0, hi = 1.0;
-    double flo = f(1.0) - target, fhi = flo;
-    int it = 0;
-    if (flo < 0.0) {
-      while (fhi < 0.0) { lo = hi; flo = fhi; hi *= 2.0; fhi = f(hi) - target; if (++it > 2000) return -1; }
-    } else {
-      while (!(flo < 0.0)) { hi = lo; fhi = flo; lo *= 0.5; flo = f(lo) - target; if (++it > 2000) return -1; }
-    }
-    double a = std::log(lo), b = std::log(hi);
-    int side = 0;
-    for (it = 0; it < 200; ++it) {
-      if (!(hi > lo) || hi - lo <= 4.0 * std::ldexp(hi, -52)) break;
-      if (fhi == 0.0) {
-        const double c = hi - 2.0 * std::ldexp(hi, -52);
-        if (!(c > lo)) break;
-        const double fc = f(c) - target;
-        if (fc < 0.0) { lo = c; a = std::log(c); flo = fc; }
-        else { hi = c; b = std::log(c); fhi = fc; }
-        side = 0;
-        continue;
-      }
-      double x = (fhi == flo) ? 0.5 * (a + b) : b - fhi * (b - a) / (fhi - flo);
-      if (!(x > a && x < b)) x = 0.5 * (a + b);
-      double c = std::exp(x);
-      if (!(c > lo && c < hi)) {
-        c = lo + 0.5 * (hi - lo);
-        x = std::log(c);
-        if (!(c > lo && c < hi)) break;
-      }
-      const double fc = f(c) - target;
-      if (fc < 0.0) {
-        if (side == -1) { const double m = 1.0 - fc / flo; fhi *= m > 0.0 ? m : 0.5; }
-        lo = c; a = x; flo = fc;
-        side = -1;
-      } else {
-        if (side == 1) { const double m = 1.0 - fc / fhi; flo *= m > 0.0 ? m : 0.5; }
-        hi = c; b = x; fhi = fc;
-        side = 1;
-      }
-    }
-    *out = hi;
-    return 0;
-  }
-};
 
 // the sums over the weights outside the tail (w, w^2 / W, w^(1/T), (w^2 / W)^(1/T))
 static void csolve_take_sums(const double* r, double T, CSolve* cs) {
@@ -839,9 +876,10 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   // result slots and pinned buffers) while the main stream sorts and gathers.
   // Further rounds, when E_R needs a longer tail, run after the gather.
   Readback rbs(cx, scs, true);
-  CSolve cs;
+  CSolve& cs = cx.cs;
   int i0 = g.L;
-  std::vector<double> asc, ascp;
+  std::vector<double>& asc = cx.cs_asc;
+  std::vector<double>& ascp = cx.cs_ascp;
   double rs[6];
   auto cs_round = [&]() -> girg_status {
     // the tail (layers >= i0), sorted by value, its powers w^(1/T), and the
@@ -896,7 +934,8 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
         for (int i = i0 - 1; i >= 0; --i)
           if (g.count[i] > 0) { cs.wcut = g.ext[i]; break; }
         cs.prepare(true);
-        if (cs.solve(p.avg_deg, &c) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
+        // (a later round starts from the c of the round before)
+        if (cs.solve(p.avg_deg, &c, c) != 0) return fail(GIRG_ENOCONV, "c solve found no bracket");
         if (cs.complete_at(c) || i0 == 0) break;
         // take every layer whose largest weight could pair with the heaviest
         // vertex inside E_R at this c, with a factor 2 of margin for the next
