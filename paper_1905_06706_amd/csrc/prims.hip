@@ -449,14 +449,39 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __rest
   hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// The tile's keys are ranked stably by digit (ballots per round, as they
+// arrive in tile order) into LDS, grouped by digit, and then written out in
+// that order: a digit's keys from one tile go to consecutive positions, so the
+// stores are coalesced runs instead of one cache line per key.
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, uint64_t n, int shift, uint32_t ntiles,
     const uint32_t* __restrict__ offs) {
-  __shared__ uint32_t run[256];
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
+  __shared__ uint32_t gofs[256];  // output position of the tile's first key of each digit
+  __shared__ uint32_t lofs[256];  // the digit's first slot in the tile's LDS copy
+  __shared__ uint32_t run[256];   // next free slot per digit
   __shared__ uint32_t wc[kSortThreads / 64][256];
   const int t = threadIdx.x, w = t / 64;
-  run[t] = offs[(uint64_t)t * ntiles + blockIdx.x];
+  // digit t of this tile: [offs[t ntiles + b], the next entry of the scanned
+  // histogram) holds its keys (the next entry is the same digit's next tile,
+  // or the next digit's first tile, or the end)
+  const uint64_t fi = (uint64_t)t * ntiles + blockIdx.x;
+  const uint32_t g0 = offs[fi];
+  const uint32_t g1 = fi + 1 < (uint64_t)256 * ntiles ? offs[fi + 1] : (uint32_t)n;
+  gofs[t] = g0;
+  lofs[t] = g1 - g0;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive scan of the tile's digit counts
+    const uint32_t v = t >= o ? lofs[t - o] : 0u;
+    __syncthreads();
+    lofs[t] += v;
+    __syncthreads();
+  }
+  lofs[t] -= g1 - g0;
+  run[t] = lofs[t];
+  __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortRounds; ++r) {
     for (int q = 0; q < kSortThreads / 64; ++q) wc[q][t] = 0;
@@ -479,14 +504,22 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(
     if (valid) {
       uint32_t pos = run[dig] + rank;
       for (int q = 0; q < w; ++q) pos += wc[q][dig];
-      kout[pos] = key;
-      vout[pos] = val;
+      sk[pos] = key;
+      sv[pos] = val;
     }
     __syncthreads();
     uint32_t add = 0;
     for (int q = 0; q < kSortThreads / 64; ++q) add += wc[q][t];
     run[t] += add;
     __syncthreads();
+  }
+  const uint32_t tn = n - base < (uint64_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
+  for (uint32_t e = t; e < tn; e += kSortThreads) {
+    const uint64_t key = sk[e];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint32_t gp = gofs[d] + (e - lofs[d]);
+    kout[gp] = key;
+    vout[gp] = sv[e];
   }
 }
 
