@@ -810,11 +810,12 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(hipMemsetAsync(cx.flag, 0, sizeof(uint32_t), st));
   uint64_t* keys = ar.get<uint64_t>(n);
   uint32_t* ids = ar.get<uint32_t>(n);
+  double* pts = ar.get<double>(n * (uint64_t)pts_stride(d, p.model));
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (keys)");
   HIPCHK(reduce_terms(ar, w, n, p.model == 0 ? 1 : 0, 0, 1.0, 0.0, cx.red, st));
   if (p.model == 0) HIPCHK(launch_set_weight_sums(cx.gd, cx.red, st));
   cx.mark("-", st);
-  HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, cx.flag, st));
+  HIPCHK(launch_layer_key(g, cx.gd, w, x, keys, ids, pts, cx.flag, st));
   cx.mark("layer_key", st);
   double red[6];
   uint32_t flag = 0;
@@ -845,7 +846,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   uint32_t* smort = ar.get<uint32_t>(n);
   uint8_t* slayer = ar.get<uint8_t>(n);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
-  HIPCHK(launch_gather(g, cx.gd, keys, ids, w, x, sw, rec, smort, slayer, st));
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, pts, sw, rec, smort, slayer, st));
   cx.mark("gather", st);
   HIPCHK(rb.wait());
   if (p.model == 0) {

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_layer_key(Graph* __restrict__ g,
                                                    const double* __restrict__ x,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ ids,
+                                                   double* __restrict__ pts,
                                                    uint32_t* __restrict__ flag) {
   // per-block layer sizes and extreme weights, merged once per block
   __shared__ int scount[kMaxLayers];
@@ -97,12 +98,19 @@ __global__ __launch_bounds__(256) void k_layer_key(Graph* __restrict__ g,
       }
       if (!bad && (layer < 0 || layer >= kMaxLayers)) bad |= 2u;
       uint32_t q[D];
+      // the point packed for the gather (one record load per vertex there)
+      const int P = pts_stride(D, model);
+      double* pu = pts + (uint64_t)u * P;
+      pu[0] = wu;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         const double xk = x[(uint64_t)k * n + u];
         if (!(xk >= 0.0 && xk < 1.0)) bad |= 4u;
         q[k] = bad ? 0u : (uint32_t)(xk * scale);
+        if (model == 0 || k == 0) pu[1 + k] = xk;
       }
+      if (model == 0)
+        for (int k = 1 + D; k < P; ++k) pu[k] = 0.0;
       if (bad) {
         atomicOr(flag, bad);
       } else {
@@ -144,13 +152,13 @@ __global__ __launch_bounds__(256) void k_layer_key(Graph* __restrict__ g,
 }
 
 hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const double* x,
-                            uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st) {
+                            uint64_t* keys, uint32_t* ids, double* pts, uint32_t* flag, hipStream_t st) {
   const unsigned blocks = (unsigned)std::min<uint64_t>((g.n + 255) / 256, 512);
   switch (g.d) {
-    case 1: hipLaunchKernelGGL(k_layer_key<1>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
-    case 2: hipLaunchKernelGGL(k_layer_key<2>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
-    case 3: hipLaunchKernelGGL(k_layer_key<3>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
-    default: hipLaunchKernelGGL(k_layer_key<4>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, flag); break;
+    case 1: hipLaunchKernelGGL(k_layer_key<1>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, pts, flag); break;
+    case 2: hipLaunchKernelGGL(k_layer_key<2>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, pts, flag); break;
+    case 3: hipLaunchKernelGGL(k_layer_key<3>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, pts, flag); break;
+    default: hipLaunchKernelGGL(k_layer_key<4>, dim3(blocks), dim3(256), 0, st, gd, w, x, keys, ids, pts, flag); break;
   }
   return hipGetLastError();
 }
@@ -170,11 +178,12 @@ hipError_t launch_set_weight_sums(Graph* gd, const double* red, hipStream_t st) 
 }
 
 // sorted structure-of-arrays copy
+// sorted arrays from the packed points: one scattered record load per vertex
+// (the point of sorted position s is pts[ids[s]])
 __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
                                                 const uint64_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ ids,
-                                                const double* __restrict__ w,
-                                                const double* __restrict__ x, double* __restrict__ sw,
+                                                const double* __restrict__ pts, double* __restrict__ sw,
                                                 double* __restrict__ rec, uint32_t* __restrict__ smort,
                                                 uint8_t* __restrict__ slayer) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,29 +191,31 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
   if (s >= n) return;
   const uint32_t u = ids[s];
   const uint64_t key = keys[s];
-  const double wu = w[u];
-  sw[s] = wu;
   smort[s] = g->bits == 32 ? (uint32_t)key : (uint32_t)(key & ((1ull << g->bits) - 1));
   slayer[s] = (uint8_t)(key >> g->bits);
   const int S = rec_stride(g->d, g->model);
   double* r = rec + s * (uint64_t)S;
   if (g->model == 1) {
-    r[0] = x[u];
+    const double wu = pts[2 * (uint64_t)u], xu = pts[2 * (uint64_t)u + 1];
+    sw[s] = wu;
+    r[0] = xu;
     r[1] = exp(wu);
     r[2] = exp(-wu);
     r[3] = sinh(wu);
   } else {
-    r[0] = wu;
-    for (int k = 0; k < g->d; ++k) r[1 + k] = x[(uint64_t)k * n + u];
-    for (int k = 1 + g->d; k < S; ++k) r[k] = 0.0;
+    // the GIRG record is the packed point itself (same stride)
+    const double2* p2 = reinterpret_cast<const double2*>(pts + (uint64_t)u * S);
+    double2* r2 = reinterpret_cast<double2*>(r);
+    for (int k = 0; k < S / 2; ++k) r2[k] = p2[k];
+    sw[s] = r[0];
   }
 }
 
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
-                         const double* w, const double* x, double* sw, double* rec, uint32_t* smort,
+                         const double* pts, double* sw, double* rec, uint32_t* smort,
                          uint8_t* slayer, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, gd, keys, ids, w,
-                     x, sw, rec, smort, slayer);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, gd, keys, ids, pts,
+                     sw, rec, smort, slayer);
   return hipGetLastError();
 }
 

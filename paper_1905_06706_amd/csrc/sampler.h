@@ -87,10 +87,13 @@ struct ChunkBases {
 
 hipError_t launch_points(const Graph& g, double beta, double* w, double* x, hipStream_t st);
 hipError_t launch_set_weight_sums(Graph* gd, const double* red, hipStream_t st);
+// pts (written): each vertex's point packed in pts_stride(d, model) doubles
+// (GIRG w, x_0 .. x_{d-1} and zero padding; HRG r, x), for the gather
+__host__ __device__ constexpr int pts_stride(int d, int model) { return model == 1 ? 2 : rec_stride(d, 0); }
 hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const double* x,
-                            uint64_t* keys, uint32_t* ids, uint32_t* flag, hipStream_t st);
+                            uint64_t* keys, uint32_t* ids, double* pts, uint32_t* flag, hipStream_t st);
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
-                         const double* w, const double* x, double* sw, double* rec, uint32_t* smort,
+                         const double* pts, double* sw, double* rec, uint32_t* smort,
                          uint8_t* slayer, hipStream_t st);
 // level tables (CL, D, I, layer masks) in one workgroup, then the pbar table
 // (pb non-null for T > 0; L * L * (Dcap + 1) * 2 entries) over a grid
