@@ -235,7 +235,7 @@ hipError_t seg_scan_u64(Arena& ar, const SegScan& s, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // reductions: fixed grid, fixed order => bitwise reproducible
 // ---------------------------------------------------------------------------
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;
 constexpr int kRedThreads = 256;
 
 // error-free transformation (Knuth TwoSum)
@@ -257,13 +257,14 @@ __device__ __forceinline__ void dd_merge(double& hi, double& lo, double h2, doub
   lo = lo + l2 + e;
 }
 
-// mode: per-vertex terms.  0 = w; 1 = w^2 / W; 2 = w^(1/T); 3 = (w^2 / W)^(1/T)
-__device__ __forceinline__ double red_term(int mode, double w, double W, double invT) {
+// mode: per-vertex terms.  0 = w; 1 = w^2 / W; 2 = w^(1/T); 3 = (w^2 / W)^(1/T),
+// the last two from one power p = w^(1/T) and WT = W^(-1/T): 3 = p^2 WT
+__device__ __forceinline__ double red_term(int mode, double w, double W, double p, double WT) {
   switch (mode) {
     case 0: return w;
     case 1: return w * w / W;
-    case 2: return pow(w, invT);
-    default: return pow(w * w / W, invT);
+    case 2: return p;
+    default: return p * p * WT;
   }
 }
 
@@ -272,7 +273,7 @@ __device__ __forceinline__ double red_term(int mode, double w, double W, double 
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ w,
                                                                  uint64_t n, int nterms,
                                                                  int mode0, double W, double invT,
-                                                                 double fw0, int fi0,
+                                                                 double WT, double fw0, int fi0,
                                                                  double* __restrict__ part) {
   __shared__ double shi[4][kRedThreads], slo[4][kRedThreads], smin[kRedThreads], smax[kRedThreads];
   const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -284,7 +285,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* _
     if (fi0 >= 0 && ilogb(v / fw0) >= fi0) continue;
     mn = fmin(mn, v);
     mx = fmax(mx, v);
-    for (int t = 0; t < nterms; ++t) dd_add(hi[t], lo[t], red_term(mode0 + t, v, W, invT));
+    const double p = mode0 + nterms > 2 ? pow(v, invT) : 0.0;
+    for (int t = 0; t < nterms; ++t) dd_add(hi[t], lo[t], red_term(mode0 + t, v, W, p, WT));
   }
   for (int t = 0; t < nterms; ++t) {
     shi[t][threadIdx.x] = hi[t];
@@ -367,8 +369,9 @@ hipError_t reduce_terms(Arena& ar, const double* w, uint64_t n, int nterms, int 
     ar.reset(m);
     return hipErrorOutOfMemory;
   }
+  const double WT = mode0 + nterms > 3 ? std::pow(W, -invT) : 0.0;
   hipLaunchKernelGGL(k_reduce_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, n, nterms,
-                     mode0, W, invT, fw0, fi0, part);
+                     mode0, W, invT, WT, fw0, fi0, part);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, part, kRedBlocks, out6);
   ar.reset(m);
   return hipGetLastError();
