@@ -314,3 +314,31 @@ def test_batched_mixed_equals_fp64(hg, d, n, beta, T, seed):
     assert b.info["rechecks"] > 0
     for k in ("tests", "draws", "candidates", "type1_edges", "type2_edges"):
         assert a.info[k] == b.info[k], k
+
+
+def test_batched_option_where_it_does_not_apply(hg):
+    """type2_batch = 1 changes nothing at d = 1, for T = 0 and for the HRG
+    (no batched sequences there), and is rejected with more than 32 weight
+    layers (a kept cell stores 32 bits of its layer mask)."""
+    import torch
+    for kw in (dict(d=1, beta=2.5, T=0.5, avg_deg=12.0, seed=41), dict(d=2, beta=2.5, T=0.0, avg_deg=12.0, seed=42)):
+        a = hg.generate(30000, type2_batch=0, **kw)
+        b = hg.generate(30000, type2_batch=1, **kw)
+        assert torch.equal(a.edges, b.edges), kw
+        assert a.info["draws"] == b.info["draws"]
+    R = hg.hrg_solve_R(20000, 0.75, 0.5, 10.0)
+    r = torch.from_numpy(synth.hrg_radii(20000, 0.75, R, 44)).cuda()
+    xh = torch.from_numpy(np.ascontiguousarray(synth.positions(20000, 1, 44).T)).cuda()
+    a = hg.from_points(r, xh, T=0.5, seed=44, model=1, R=R, alpha=0.75, type2_batch=0)
+    b = hg.from_points(r, xh, T=0.5, seed=44, model=1, R=R, alpha=0.75, type2_batch=1)
+    assert torch.equal(a.edges, b.edges)
+    n = 4000
+    w = synth.pareto_weights(n, 2.5, 43)
+    w[0] = 2.0**40  # layers 0 .. 40
+    x = synth.positions(n, 2, 43)
+    wd = torch.from_numpy(w).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    with pytest.raises(hg.GirgError, match="32 weight layers"):
+        hg.from_points(wd, xd, T=0.5, c=0.5, seed=43, type2_batch=1)
+    ok = hg.from_points(wd, xd, T=0.5, c=0.5, seed=43, type2_batch=0)
+    assert ok.edges.shape[0] > 0
