@@ -1542,6 +1542,16 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
   // reserved once its count is known (completion order), and are put into
   // instance order at the end
   const int nw = std::min<int>(count, tuned_batch_workers());
+  // instances are started largest first (expected edges n * degree, ties in
+  // instance order), so that no large one starts when the others are done;
+  // the order changes no edge array (the edges are put into instance order)
+  std::vector<int32_t> order(count);
+  for (int32_t b = 0; b < count; ++b) order[b] = b;
+  auto cost = [&](int32_t b) {
+    const double deg = p[b].avg_deg > 0.0 ? p[b].avg_deg : 16.0;
+    return (double)p[b].n * deg;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
   std::atomic<int32_t> next{0};
   std::atomic<bool> stop{false};
   std::mutex cur_mu;
@@ -1563,8 +1573,9 @@ girg_status girg_generate_batch(const girg_params* p, int32_t count, uint32_t* e
     }
     for (;;) {
       if (stop.load()) return;
-      const int32_t b = next.fetch_add(1);
-      if (b >= count) return;
+      const int32_t k = next.fetch_add(1);
+      if (k >= count) return;
+      const int32_t b = order[k];
       const girg_params& q = p[b];
       const double deg = q.avg_deg > 0.0 ? q.avg_deg : 16.0;
       uint64_t scap = (uint64_t)(1.25 * 0.5 * deg * (double)q.n) + 4096;
