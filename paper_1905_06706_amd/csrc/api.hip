@@ -965,14 +965,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     pbt = ar.get<Pbar>((uint64_t)std::max(g.L, 1) * std::max(g.L, 1) * nlev * 2);
     if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (pbar)");
   }
+  tables_host(g, Dcap);
   HIPCHK(rb.upload(cx.gd, &g, sizeof(Graph)));
   cx.mark("-", st);
-  HIPCHK(launch_tables(cx.gd, g.L, Dcap, pbt, st));
+  HIPCHK(launch_pbar(cx.gd, g.L, Dcap, pbt, st));
   cx.mark("tables", st);
-  HIPCHK(rb.begin(kSmallReadback));
-  HIPCHK(rb.add(&g, cx.gd, sizeof(Graph)));
-  HIPCHK(rb.wait());
-  early.armed = false;  // the main stream has drained
 
   // prefix sums per layer at its insertion level
   uint64_t cells = 0;
@@ -1009,6 +1006,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   HIPCHK(rb.begin(kSmallReadback));
   HIPCHK(rb.add(&nsrc, scnt + n, sizeof(uint32_t)));
   HIPCHK(rb.wait());
+  early.armed = false;  // the main stream has drained
   Src* src = ar.get<Src>(std::max<uint64_t>(nsrc, 1));
   const uint64_t ncl = g.moff[kMaxLevels];
   CellL* cl = ar.get<CellL>(ncl);

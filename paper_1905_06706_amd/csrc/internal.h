@@ -95,6 +95,8 @@ hipError_t seg_scan_u64(Arena& ar, const SegScan& s, hipStream_t st);
 hipError_t launch_iota(uint32_t* p, uint64_t n, hipStream_t st);
 // out[i] = x_i^e, x_i positive doubles given as bit patterns (u64)
 hipError_t launch_pow_bits(const uint64_t* xb, double* out, uint64_t n, double e, hipStream_t st);
+// stable sort of (keys, vals) by key; keys below 2^bits, vals distinct
+// indices below n (every caller passes 0 .. n - 1)
 hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
                       hipStream_t st);
 

@@ -223,70 +223,69 @@ hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, 
 // level tables: comparison level CL(i,j) (Sec. 3.1; HRG by search over
 // levels, Sec. 4.3), insertion level I(i), deepest level D, the masks of
 // layer pairs served by neighbouring (CL == level) and distant (CL >= level)
-// cell pairs (loop swap, Sec. 3.3), and the type-II bounds pbar.
-// One block; the sizes are tiny (<= 64 x 64 layer pairs).
+// cell pairs (loop swap, Sec. 3.3), and the type-II bounds pbar.  The
+// tables are tiny (<= 64 x 64 layer pairs) and the host needs I(i) to size
+// the cell arrays: they are computed on the host and uploaded with the
+// Graph, which saves a readback; pbar runs on the device over a grid.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tables(Graph* __restrict__ g, int Dcap) {
-  __shared__ int dmax;
-  __shared__ int8_t scl[kMaxLayers][kMaxLayers];
-  const int L = g->L, d = g->d;
-  if (threadIdx.x == 0) dmax = 0;
-  __syncthreads();
-  for (int p = threadIdx.x; p < kMaxLayers * kMaxLayers; p += blockDim.x) {
-    const int i = p / kMaxLayers, j = p % kMaxLayers;
-    int l = -1;
-    if (i < L && j < L && g->count[i] > 0 && g->count[j] > 0) {
-      l = 0;
-      const double ei = g->ext[i], ej = g->ext[j];
-      if (g->model == 0 && g->T == 0.0) {
-        const double tmax = g->c * pow(ei * ej / g->W, 1.0 / d);
-        while (l < Dcap && ldexp(1.0, -(l + 1)) >= tmax) ++l;
-      } else if (g->model == 0) {
-        const double V = g->kappa * ei * ej / g->W;
-        while (l < Dcap && ldexp(1.0, -(l + 1) * d) >= V) ++l;
-      } else {
-        const double shh = 2.0 * sinh(ei) * sinh(ej);
-        while (l < Dcap) {
-          const int nl = l + 1;
-          if (nl >= 2) {
-            const double s = sin(3.141592653589793 * ldexp(1.0, -nl));
-            if (!(1.0 + shh * s * s >= g->coshR)) break;
+void tables_host(Graph& g, int Dcap) {
+  const int L = g.L, d = g.d;
+  int dmax = 0;
+  for (int i = 0; i < kMaxLayers; ++i) {
+    for (int j = 0; j < kMaxLayers; ++j) {
+      int l = -1;
+      if (i < L && j < L && g.count[i] > 0 && g.count[j] > 0) {
+        l = 0;
+        const double ei = g.ext[i], ej = g.ext[j];
+        if (g.model == 0 && g.T == 0.0) {
+          const double tmax = g.c * std::pow(ei * ej / g.W, 1.0 / d);
+          while (l < Dcap && std::ldexp(1.0, -(l + 1)) >= tmax) ++l;
+        } else if (g.model == 0) {
+          const double V = g.kappa * ei * ej / g.W;
+          while (l < Dcap && std::ldexp(1.0, -(l + 1) * d) >= V) ++l;
+        } else {
+          const double shh = 2.0 * std::sinh(ei) * std::sinh(ej);
+          while (l < Dcap) {
+            const int nl = l + 1;
+            if (nl >= 2) {
+              const double s = std::sin(3.141592653589793 * std::ldexp(1.0, -nl));
+              if (!(1.0 + shh * s * s >= g.coshR)) break;
+            }
+            l = nl;
           }
-          l = nl;
         }
+        l += g.cl_bias;
+        if (l < 0) l = 0;
+        if (l > Dcap) l = Dcap;
+        if (g.max_depth >= 0 && l > g.max_depth) l = g.max_depth;
+        dmax = std::max(dmax, l);
       }
-      l += g->cl_bias;
-      if (l < 0) l = 0;
-      if (l > Dcap) l = Dcap;
-      if (g->max_depth >= 0 && l > g->max_depth) l = g->max_depth;
-      atomicMax(&dmax, l);
+      g.CL[i][j] = (int8_t)l;
     }
-    g->CL[i][j] = (int8_t)l;
-    scl[i][j] = (int8_t)l;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) g->D = dmax;
-  for (int i = threadIdx.x; i < kMaxLayers; i += blockDim.x) {
+  g.D = dmax;
+  for (int i = 0; i < kMaxLayers; ++i) {
     int I = -1;
-    for (int j = 0; j < kMaxLayers; ++j) I = scl[i][j] > I ? scl[i][j] : I;
-    g->I[i] = (int8_t)I;
+    for (int j = 0; j < kMaxLayers; ++j) I = std::max<int>(I, g.CL[i][j]);
+    g.I[i] = (int8_t)I;
   }
-  for (int p = threadIdx.x; p < kMaxLayers * kMaxLevels; p += blockDim.x) {
-    const int i = p / kMaxLevels, l = p % kMaxLevels;
-    uint64_t m1 = 0, m2 = 0;
-    for (int j = 0; j < (i < L ? L : 0); ++j) {  // CL is -1 outside the L x L block
-      const int cl = scl[i][j];
-      if (cl < 0) continue;
-      if (cl == l) m1 |= 1ull << j;
-      if (cl >= l && l >= 2) m2 |= 1ull << j;  // distant pairs exist from level 2
+  for (int i = 0; i < kMaxLayers; ++i) {
+    for (int l = 0; l < kMaxLevels; ++l) {
+      uint64_t m1 = 0, m2 = 0;
+      for (int j = 0; j < (i < L ? L : 0); ++j) {  // CL is -1 outside the L x L block
+        const int cl = g.CL[i][j];
+        if (cl < 0) continue;
+        if (cl == l) m1 |= 1ull << j;
+        if (cl >= l && l >= 2) m2 |= 1ull << j;  // distant pairs exist from level 2
+      }
+      g.jI[i][l] = m1;
+      g.jII[i][l] = g.T > 0.0 ? m2 : 0ull;  // threshold: distant cells hold no edges
     }
-    g->jI[i][l] = m1;
-    g->jII[i][l] = g->T > 0.0 ? m2 : 0ull;  // threshold: distant cells hold no edges
   }
 }
 
 // pbar for (i, j, level, gap): largest weights, smallest distance gap
-// 2^-level; one entry per thread over the whole grid (after k_tables)
+// 2^-level; one entry per thread over the whole grid (CL from tables_host)
 __global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int Dcap,
                                               Pbar* __restrict__ pb, int total) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,8 +318,7 @@ __global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int D
   }
 }
 
-hipError_t launch_tables(Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st) {
-  hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, st, gd, Dcap);
+hipError_t launch_pbar(const Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st) {
   if (pb && L > 0) {
     const int total = L * L * (Dcap + 1) * 2;
     hipLaunchKernelGGL(k_pbar, dim3((total + 255) / 256), dim3(256), 0, st, gd, Dcap, pb, total);

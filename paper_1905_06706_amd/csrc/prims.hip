@@ -564,9 +564,53 @@ __global__ __launch_bounds__(1024) void k_small_sort(uint64_t* __restrict__ keys
   }
 }
 
+// up to 16384 pairs whose key and value fit one word together (key below
+// 2^bits, value below 2^vbits, bits + vbits <= 63): the word key << vbits |
+// value, sorted by a bitonic network in LDS in one workgroup.  With distinct
+// values (the callers' indices) the words are distinct, and this is the
+// stable sort by key.
+constexpr int kSmallSortPacked = 16384;
+__global__ __launch_bounds__(1024) void k_small_sort_packed(uint64_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ vals, uint32_t n,
+                                                            uint32_t np, int vbits) {
+  __shared__ uint64_t s[kSmallSortPacked];
+  for (uint32_t i = threadIdx.x; i < np; i += blockDim.x)
+    s[i] = i < n ? (keys[i] << vbits) | (uint64_t)vals[i] : ~0ull;
+  __syncthreads();
+  for (uint32_t size = 2; size <= np; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < np / 2; t += blockDim.x) {
+        const uint32_t i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint64_t a = s[i], b = s[j];
+        if ((a > b) == up) {
+          s[i] = b;
+          s[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint64_t vm = (1ull << vbits) - 1ull;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    keys[i] = s[i] >> vbits;
+    vals[i] = (uint32_t)(s[i] & vm);
+  }
+}
+
 hipError_t radix_sort(Arena& ar, uint64_t* keys, uint32_t* vals, uint64_t n, int bits,
                       hipStream_t st) {
   if (n <= 1 || bits <= 0) return hipSuccess;
+  // the values are indices below n (every caller's): bitlen(n - 1) bits
+  int vbits = 0;
+  while ((1ull << vbits) < n) ++vbits;
+  if (n <= (uint64_t)kSmallSortPacked && bits + vbits <= 63) {
+    uint32_t np = 2;
+    while (np < n) np <<= 1;
+    hipLaunchKernelGGL(k_small_sort_packed, dim3(1), dim3(1024), 0, st, keys, vals, (uint32_t)n, np,
+                       vbits);
+    return hipGetLastError();
+  }
   if (n <= (uint64_t)kSmallSort) {
     uint32_t np = 2;
     while (np < n) np <<= 1;

@@ -95,9 +95,15 @@ hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const do
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* pts, double* sw, double* rec, uint32_t* smort,
                          uint8_t* slayer, hipStream_t st);
-// level tables (CL, D, I, layer masks) in one workgroup, then the pbar table
-// (pb non-null for T > 0; L * L * (Dcap + 1) * 2 entries) over a grid
-hipError_t launch_tables(Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st);
+// level tables on the host: comparison level CL(i,j) (Sec. 3.1; HRG by
+// search over levels, Sec. 4.3), insertion level I(i), deepest level D, and
+// the masks of layer pairs served by neighbouring (CL == level) and distant
+// (CL >= level) cell pairs (loop swap, Sec. 3.3), from the layer counts and
+// extremes, W and c already in g
+void tables_host(Graph& g, int Dcap);
+// the pbar table on the device from the uploaded Graph (pb non-null for
+// T > 0; L * L * (Dcap + 1) * 2 entries), over a grid
+hipError_t launch_pbar(const Graph* gd, int L, int Dcap, Pbar* pb, hipStream_t st);
 hipError_t launch_cell_count(const Graph& g, const Graph* gd, const uint32_t* smort,
                              const uint8_t* slayer, uint32_t* cnt, hipStream_t st);
 hipError_t launch_sources(const Graph& g, const Graph* gd, const uint32_t* smort,
