@@ -1126,12 +1126,6 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   ItemRec* drec[2] = {nullptr, nullptr};
   uint64_t* dkey[2] = {nullptr, nullptr};
   unsigned int dn[2] = {0, 0};
-  // deferred items in (chunk, sequence) order and their work units, per list
-  ItemRec* dsorted[2] = {nullptr, nullptr};
-  uint64_t* uoff[2] = {nullptr, nullptr};
-  uint64_t nunits[2] = {0, 0};
-  // the split type-I pass, when it has already been started beside type II
-  bool early1 = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     Arena::Mark mk = ar.mark();
     for (int q = 0; q < 2; ++q) {
@@ -1162,67 +1156,28 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
       }
     }
     cx.mark("type2", st);
-    // type I ends long before type II: its deferred items are placed, and their
-    // split pass started, on the side stream while type II still runs (the host
-    // waits for the side stream only; every allocation below is made after the
-    // side-stream work that used the memory before has ended)
-    early1 = false;
-    bool scanned0 = false;  // type I's chunk offsets already scanned on the side stream
-    if (overlap && sch[0].nchunks) {
-      Readback rb1(cx, s1, true);
-      HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, nullptr, nullptr, nullptr},
-                                  {sch[0].nchunks, 0, 0, 0}, 1u},
-                          s1));
-      scanned0 = true;
-      HIPCHK(rb1.begin(kSmallReadback));
-      HIPCHK(rb1.add(dn, dcount, sizeof(unsigned int)));
-      HIPCHK(rb1.wait());
-      if (dn[0] <= dcap[0]) {
-        const uint32_t nd = dn[0];
-        nunits[0] = 0;
-        if (nd) {
-          dsorted[0] = ar.get<ItemRec>(nd);
-          uoff[0] = ar.get<uint64_t>(nd + 1);
-          if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred items)");
-          HIPCHK(launch_defer_place(drec[0], dkey[0], nd, sch[0].dtot, dsorted[0], s1));
-          HIPCHK(launch_rec_units(dsorted[0], nd, 1, uoff[0], s1));
-          HIPCHK(scan_u64(ar, uoff[0], uoff[0], nd, uoff[0] + nd, s1));
-          HIPCHK(rb1.begin(kSmallReadback));
-          HIPCHK(rb1.add(nunits + 0, uoff[0] + nd, sizeof(uint64_t)));
-          HIPCHK(rb1.wait());
-        }
-        sch[1] = make_sched(nunits[0], 1);
-        sch[1].ctot = ar.get<uint64_t>(sch[1].nchunks);
-        if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred passes)");
-        cx.mark("-", s1);
-        if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, s1));
-        cx.mark("split1", s1);
-        early1 = true;
-      }
-    }
     HIPCHK(join_side(cx, st, overlap, sguard));
     // where each chunk's deferred items start
-    if (scanned0)
-      HIPCHK(seg_scan_u64(ar, SegScan{{sch[2].dtot, nullptr, nullptr, nullptr}, {nch2, 0, 0, 0}, 1u}, st));
-    else
-      HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
-                                  {sch[0].nchunks, nch2, 0, 0}, 3u},
-                          st));
+    HIPCHK(seg_scan_u64(ar, SegScan{{sch[0].dtot, sch[2].dtot, nullptr, nullptr},
+                                {sch[0].nchunks, nch2, 0, 0}, 3u},
+                        st));
     HIPCHK(rb.begin(kSmallReadback));
     HIPCHK(rb.add(dn, dcount, 2 * sizeof(unsigned int)));
     HIPCHK(rb.wait());
     if (dn[0] <= dcap[0] && dn[1] <= dcap[1]) break;
     if (attempt == 1) return fail(GIRG_ENOMEM, "deferred item lists overflowed");
-    // (the stream waited for the side stream's work, the early split pass included)
     ar.reset(mk);
     dcap[0] = std::max(dcap[0], dn[0]);
     dcap[1] = std::max(dcap[1], dn[1]);
   }
 
   // deferred items in (chunk, sequence) order, their work units, then their passes
+  ItemRec* dsorted[2] = {nullptr, nullptr};
+  uint64_t* uoff[2] = {nullptr, nullptr};
+  uint64_t nunits[2] = {0, 0};
   cx.mark("-", st);
   HIPCHK(rb.begin(kSmallReadback));
-  for (int q = early1 ? 1 : 0; q < 2; ++q) {
+  for (int q = 0; q < 2; ++q) {
     const uint32_t nd = dn[q];
     if (!nd) continue;
     dsorted[q] = ar.get<ItemRec>(nd);
@@ -1233,21 +1188,16 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     HIPCHK(scan_u64(ar, uoff[q], uoff[q], nd, uoff[q] + nd, st));
     HIPCHK(rb.add(nunits + q, uoff[q] + nd, sizeof(uint64_t)));
   }
-  if ((!early1 && dn[0]) || dn[1]) HIPCHK(rb.wait());
+  if (dn[0] || dn[1]) HIPCHK(rb.wait());
   cx.mark("deferred_prep", st);
-  if (!early1) {
-    sch[1] = make_sched(nunits[0], 1);
-    sch[1].ctot = ar.get<uint64_t>(sch[1].nchunks);
-  }
+  sch[1] = make_sched(nunits[0], 1);
   sch[3] = make_sched(nunits[1], 3);
-  sch[3].ctot = ar.get<uint64_t>(sch[3].nchunks);
+  for (int q = 1; q <= 3; q += 2) sch[q].ctot = ar.get<uint64_t>(sch[q].nchunks);
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (deferred passes)");
   HIPCHK(fork_side(cx, st, overlap, sguard));
-  if (!early1) {
-    cx.mark("-", s1);
-    if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, s1));
-    cx.mark("split1", s1);
-  }
+  cx.mark("-", s1);
+  if (sch[1].nchunks) HIPCHK(launch_big1(g, cx.gd, v, dsorted[0], uoff[0], dn[0], sch[1], sg, s1));
+  cx.mark("split1", s1);
   cx.mark("-", st);
   if (sch[3].nchunks)
     HIPCHK(launch_heavy2(g, cx.gd, v, dsorted[1], uoff[1], dn[1], sch[3], pbt, nlev, sg, st));
