@@ -845,8 +845,11 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   double* rec = ar.get<double>(n * (uint64_t)rec_stride(d, p.model));
   uint32_t* smort = ar.get<uint32_t>(n);
   uint8_t* slayer = ar.get<uint8_t>(n);
+  // the mixed path's 16-byte FP32 filter records (GIRG, T > 0, d <= 3)
+  const bool frecs = p.precision == 1 && p.model == 0 && p.T > 0.0 && d <= 3;
+  uint4* frec = frecs ? ar.get<uint4>(n) : nullptr;
   if (ar.failed()) return fail(GIRG_ENOMEM, "scratch allocation failed (sorted arrays)");
-  HIPCHK(launch_gather(g, cx.gd, keys, ids, pts, sw, rec, smort, slayer, st));
+  HIPCHK(launch_gather(g, cx.gd, keys, ids, pts, sw, rec, smort, slayer, frec, st));
   cx.mark("gather", st);
   HIPCHK(rb.wait());
   if (p.model == 0) {
@@ -1044,7 +1047,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
     cx.dtab2[d] = t;
   }
 
-  Verts v{rec, ids, smort, slayer};
+  Verts v{rec, ids, smort, slayer, frec};
   const bool binomial = p.T > 0.0;
 
   // staging of the edges: capacity = the caller's; flush records.  The

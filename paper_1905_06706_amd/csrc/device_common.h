@@ -63,6 +63,35 @@ __device__ __forceinline__ double u53_open(uint32_t lo, uint32_t hi) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 logarithm of the type-II skip filter.  A skip is
+// floor(log2 S / log2(1 - pbar)) for S = (vv + 1) 2^-53 in (0, 1].
+// * 1 - S = om 2^-53 is exact.  Below 1/16 the series
+//   -(t + t^2/2 + ... + t^5/5) / ln 2 of log2(1 - t) is taken in t = fl32(1 - S)
+//   (truncation below t^5 / (6 (1 - t)) < 2^-22.5 relative, t's rounding
+//   2^-24 relative).
+// * Otherwise v_log_f32 of fl32(S).  There |log2 S| >= 0.093, so the rounding
+//   of S moves the result by less than 2^-20 relative.
+// tests/log2_probe.hip measures both pieces on every float of their ranges
+// (series and v_log_f32 each below 2^-21 relative), so the result is within
+// 2^-19.4 of log2 S, relative; with the rounding of 1 / log2(1 - pbar) and of
+// the product the FP32 quotient is within 2^-19.3 of the exact one, and the
+// filter decides only outside kSkipRel (relative) of it.
+// ---------------------------------------------------------------------------
+constexpr double kSkipRel = 0x1p-17;
+
+__device__ __forceinline__ float log2_1m_series_f32(float t) {
+  return -t * (1.0f + t * (0.5f + t * (0.33333334f + t * (0.25f + t * 0.2f)))) * 1.44269504f;
+}
+
+__device__ __forceinline__ float log2_unit_f32(uint64_t vv) {
+  const uint64_t om = (1ull << 53) - 1 - vv;
+  if (!om) return 0.0f;
+  const float t = (float)om * 0x1p-53f;
+  if (t < 0.0625f) return log2_1m_series_f32(t);
+  return __log2f((float)((double)(vv + 1) * 0x1p-53));
+}
+
+// ---------------------------------------------------------------------------
 // Morton codes (Sec. 3.4 / App. B.3): coordinate bits interleaved, dimension 0
 // most significant in every group.  Shift-and-mask spreading for fixed d.
 // ---------------------------------------------------------------------------
@@ -221,6 +250,9 @@ struct Verts {
   const uint32_t* id;   // original id
   const uint32_t* mort; // Morton code at level Dmax
   const uint8_t* layer;
+  // FP32 filter records of the mixed path (GIRG, d <= 3; null otherwise):
+  // (log2 w as FP32 bits, floor(x_k 2^32) for k < d, zero after)
+  const uint4* frec;
 };
 
 // Per cell and level (index moff[l] + cell): the layers with vertices there

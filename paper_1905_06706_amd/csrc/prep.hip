@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
                                                 const uint32_t* __restrict__ ids,
                                                 const double* __restrict__ pts, double* __restrict__ sw,
                                                 double* __restrict__ rec, uint32_t* __restrict__ smort,
-                                                uint8_t* __restrict__ slayer) {
+                                                uint8_t* __restrict__ slayer, uint4* __restrict__ frec) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = g->n;
   if (s >= n) return;
@@ -208,14 +208,25 @@ __global__ __launch_bounds__(256) void k_gather(const Graph* __restrict__ g,
     double2* r2 = reinterpret_cast<double2*>(r);
     for (int k = 0; k < S / 2; ++k) r2[k] = p2[k];
     sw[s] = r[0];
+    if (frec) {
+      // the mixed path's FP32 filter record: log2 w, coordinates in 32-bit
+      // fixed point (x in [0, 1), so x 2^32 < 2^32 and its floor is exact)
+      const int d = g->d;
+      uint4 f;
+      f.x = __float_as_uint((float)log2(r[0]));
+      f.y = (uint32_t)(uint64_t)(r[1] * 0x1p32);
+      f.z = d > 1 ? (uint32_t)(uint64_t)(r[2] * 0x1p32) : 0u;
+      f.w = d > 2 ? (uint32_t)(uint64_t)(r[3] * 0x1p32) : 0u;
+      frec[s] = f;
+    }
   }
 }
 
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* pts, double* sw, double* rec, uint32_t* smort,
-                         uint8_t* slayer, hipStream_t st) {
+                         uint8_t* slayer, uint4* frec, hipStream_t st) {
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, gd, keys, ids, pts,
-                     sw, rec, smort, slayer);
+                     sw, rec, smort, slayer, frec);
   return hipGetLastError();
 }
 

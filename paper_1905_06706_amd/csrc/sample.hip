@@ -193,8 +193,9 @@ __device__ __forceinline__ bool pair_thresh(const Graph* __restrict__ g, const V
 // ---------------------------------------------------------------------------
 // mixed precision (GIRG, T > 0).  log2 min(p_uv, 1) is evaluated in FP32 as
 // C + (1/T)(log2 w_u + log2 w_v - d log2 r) with C = log2 c - (1/T) log2 W
-// (w and r exact in FP64, rounded to FP32, then __log2f).  Every term carries
-// a relative error of a few 2^-24 and __log2f one of about 2^-22, so
+// (here, for d = 4: w and r exact in FP64, rounded to FP32, then __log2f).
+// Every term carries a relative error of a few 2^-24, and __log2f one below
+// 2^-23 (1 + |log2 x|) (tests/log2_probe.hip, on every positive float), so
 // |L32 - log2 p| < 2^-20 (1 + |C| + (1/T)(|log2 w_u| + |log2 w_v| + d |log2 r|));
 // the filter decides only outside 2^-13 times that sum (a factor 128 of
 // slack) and re-decides every other pair with the FP64 formula, so the result
@@ -212,22 +213,76 @@ __device__ __forceinline__ bool mixed_logp(const Graph* __restrict__ g, double w
   return true;
 }
 
+// The same filter from the 16-byte records of Verts::frec (d <= 3): log2 w
+// in FP32 (rounded from the FP64 log2: 2^-24 relative) and each coordinate as
+// floor(x 2^32).  Per dimension the torus difference of two such coordinates
+// is exact in 32-bit unsigned arithmetic, and it lies within 2^-32 of that of
+// the points (it is 1-Lipschitz in each coordinate), so the L-infinity
+// distance R 2^-32 is within 2^-32 of r.  For R >= 2^12 that moves log2 r by
+// less than 1.5 / R, which the margin takes as (1/T) d 2 / R; closer pairs are
+// decided in FP64.  log2 r = __log2f(fl32(R) 2^-32) keeps the error budget
+// above, since |log2 r| >= 1 (r <= 1/2).
+template <int D>
+__device__ __forceinline__ bool mixed_logp_f(const Graph* __restrict__ g,
+                                             const uint4* __restrict__ frec, uint32_t su,
+                                             uint32_t sv, float& Lc, float& err) {
+  const uint4 a = frec[su], b = frec[sv];
+  const uint32_t ax[3] = {a.y, a.z, a.w}, bx[3] = {b.y, b.z, b.w};
+  uint32_t R = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const uint32_t df = ax[k] - bx[k];
+    const uint32_t m = df < 0u - df ? df : 0u - df;
+    R = m > R ? m : R;
+  }
+  if (R < 4096u) return false;
+  const float fr = (float)R;
+  const float lr = __log2f(fr * 0x1p-32f);
+  const float la = __uint_as_float(a.x), lb = __uint_as_float(b.x);
+  const float L = g->C32 + g->invT32 * (la + lb - (float)D * lr);
+  err = 0x1p-13f * (1.0f + fabsf(g->C32) + g->invT32 * (fabsf(la) + fabsf(lb) + (float)D * fabsf(lr))) +
+        g->invT32 * (float)(2 * D) * __builtin_amdgcn_rcpf(fr);
+  Lc = fminf(L, 0.0f);
+  return true;
+}
+
+// the FP64 decision of the mixed path's rechecks
+template <int D>
+__device__ __forceinline__ double mixed_prob64(const Graph* __restrict__ g, const Verts& v,
+                                               uint32_t su, uint32_t sv) {
+  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+  return girg_prob<D>(g, a.v[0], b.v[0], torus_r<D, 0>(a, b));
+}
+
 // type-I test: edge iff U < p_uv (nr: |U - p_uv| < 1e-12)
 template <int D>
 __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Verts& v, uint32_t su,
                                            uint32_t sv, double U, uint32_t& nre, bool& nr) {
-  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
-  const double r = torus_r<D, 0>(a, b);
-  float Lc, err;
-  if (U > 0.0 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
-    const float lu = __log2f((float)U);
-    if (lu < Lc - err) return true;
-    if (lu > Lc + err) return false;
+  if constexpr (D <= 3) {
+    float Lc, err;
+    if (U > 0.0 && mixed_logp_f<D>(g, v.frec, su, sv, Lc, err)) {
+      const float lu = __log2f((float)U);
+      if (lu < Lc - err) return true;
+      if (lu > Lc + err) return false;
+    }
+    ++nre;
+    const double p = mixed_prob64<D>(g, v, su, sv);
+    nr = fabs(U - p) < 1e-12;
+    return U < p;
+  } else {
+    const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+    const double r = torus_r<D, 0>(a, b);
+    float Lc, err;
+    if (U > 0.0 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
+      const float lu = __log2f((float)U);
+      if (lu < Lc - err) return true;
+      if (lu > Lc + err) return false;
+    }
+    ++nre;
+    const double p = girg_prob<D>(g, a.v[0], b.v[0], r);
+    nr = fabs(U - p) < 1e-12;
+    return U < p;
   }
-  ++nre;
-  const double p = girg_prob<D>(g, a.v[0], b.v[0], r);
-  nr = fabs(U - p) < 1e-12;
-  return U < p;
 }
 
 // type-II candidate: accepted iff Acc * pbar < p_uv (apb = Acc * pbar in FP64;
@@ -235,17 +290,30 @@ __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Ve
 template <int D>
 __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Verts& v, uint32_t su,
                                            uint32_t sv, double apb, uint32_t& nre, const Stage& sg) {
-  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
-  const double r = torus_r<D, 0>(a, b);
-  float Lc, err;
-  if (apb >= 0x1p-120 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
-    const float la = __log2f((float)apb);
-    const float e2 = err + 0x1p-13f * (1.0f + fabsf(la));
-    if (la < Lc - e2) return true;
-    if (la > Lc + e2) return false;
+  double p;
+  if constexpr (D <= 3) {
+    float Lc, err;
+    if (apb >= 0x1p-120 && mixed_logp_f<D>(g, v.frec, su, sv, Lc, err)) {
+      const float la = __log2f((float)apb);
+      const float e2 = err + 0x1p-13f * (1.0f + fabsf(la));
+      if (la < Lc - e2) return true;
+      if (la > Lc + e2) return false;
+    }
+    ++nre;
+    p = mixed_prob64<D>(g, v, su, sv);
+  } else {
+    const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+    const double r = torus_r<D, 0>(a, b);
+    float Lc, err;
+    if (apb >= 0x1p-120 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
+      const float la = __log2f((float)apb);
+      const float e2 = err + 0x1p-13f * (1.0f + fabsf(la));
+      if (la < Lc - e2) return true;
+      if (la > Lc + e2) return false;
+    }
+    ++nre;
+    p = girg_prob<D>(g, a.v[0], b.v[0], r);
   }
-  ++nre;
-  const double p = girg_prob<D>(g, a.v[0], b.v[0], r);
   if (fabs(apb - p) < 1e-12) list_near2(sg.nbuf, sg.ncnt, sg.ncap, su, sv, apb);
   return apb < p;
 }
@@ -834,10 +902,9 @@ struct Ring2 {
 // one geometric draw without the candidate test: X ~ Geom_0(pbar) candidates
 // are skipped (X = floor(ln S / ln(1 - pbar))); returns true with the
 // candidate's sorted indices when it lies in the range.  Mixed precision:
-// log2 S in FP32 (a series in the exact 1 - S near S = 1, else __log2f; both
-// within a few 2^-22 relative), times 1 / log2(1 - pbar); X and the end test
-// are taken from it only when both ends of a 2^-13 relative interval agree,
-// otherwise from the FP64 quotient.
+// log2 S in FP32 (log2_unit_f32), times 1 / log2(1 - pbar); X and the end
+// test are taken from it only when both ends of its kSkipRel relative interval
+// agree, otherwise from the FP64 quotient.
 template <bool MX>
 __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it, const PB& pe,
                                          bool& done, Cand& cd, uint32_t& nre,
@@ -852,17 +919,8 @@ __device__ __forceinline__ bool geo_draw(uint32_t k0s, uint32_t k1s, QItem2& it,
   if (pe.pbar >= 1.0) {
     decided = true;  // every candidate is drawn
   } else if (MX) {
-    const uint64_t om = (1ull << 53) - 1 - vv;  // (1 - S) 2^53, exact
-    float l2s = 0.0f;
-    if (om) {
-      const float t = (float)om * 0x1p-53f;
-      if (t < 0.0625f)
-        l2s = -t * (1.0f + t * (0.5f + t * (0.33333334f + t * (0.25f + t * 0.2f)))) * 1.44269504f;
-      else
-        l2s = __log2f((float)S);
-    }
-    const double q32 = (double)(l2s * pe.qs);
-    const double qe = 0x1p-13 * (q32 + 1.0);
+    const double q32 = (double)(log2_unit_f32(vv) * pe.qs);
+    const double qe = kSkipRel * q32;
     const double qlo = q32 - qe > 0.0 ? q32 - qe : 0.0, qhi = q32 + qe;
     if (qlo >= (double)rem) {
       end = true;
@@ -1399,7 +1457,7 @@ __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
 // 2^62) and the acceptance uniform Acc; tie: the quotient lies within 1e-12
 // (relative) of an integer >= 1 (decided by the walk: it counts when the skip
 // lands in the sequence or ends exactly at its end).  Mixed precision: the
-// FP32 quotient when both ends of its 2^-13 interval have the same floor.
+// FP32 quotient when both ends of its kSkipRel interval have the same floor.
 template <bool MX>
 __device__ __forceinline__ uint64_t seq_draw(uint32_t k0s, uint32_t k1s, uint32_t X, uint32_t g,
                                              uint32_t w3, uint32_t t, const PB& pe, double& acc,
@@ -1410,17 +1468,8 @@ __device__ __forceinline__ uint64_t seq_draw(uint32_t k0s, uint32_t k1s, uint32_
   tie = false;
   if (pe.pbar >= 1.0) return 0;  // every candidate is drawn
   if (MX) {
-    const uint64_t om = (1ull << 53) - 1 - vv;  // (1 - S) 2^53, exact
-    float l2s = 0.0f;
-    if (om) {
-      const float tt = (float)om * 0x1p-53f;
-      if (tt < 0.0625f)
-        l2s = -tt * (1.0f + tt * (0.5f + tt * (0.33333334f + tt * (0.25f + tt * 0.2f)))) * 1.44269504f;
-      else
-        l2s = __log2f((float)((double)(vv + 1) * 0x1p-53));
-    }
-    const double q32 = (double)(l2s * pe.qs);
-    const double qe = 0x1p-13 * (q32 + 1.0);
+    const double q32 = (double)(log2_unit_f32(vv) * pe.qs);
+    const double qe = kSkipRel * q32;
     const double qlo = q32 - qe > 0.0 ? q32 - qe : 0.0, qhi = q32 + qe;
     if (qhi < 0x1p62 && floor(qlo) == floor(qhi)) return (uint64_t)qhi;
     ++nre;

@@ -94,7 +94,7 @@ hipError_t launch_layer_key(const Graph& g, Graph* gd, const double* w, const do
                             uint64_t* keys, uint32_t* ids, double* pts, uint32_t* flag, hipStream_t st);
 hipError_t launch_gather(const Graph& g, const Graph* gd, const uint64_t* keys, const uint32_t* ids,
                          const double* pts, double* sw, double* rec, uint32_t* smort,
-                         uint8_t* slayer, hipStream_t st);
+                         uint8_t* slayer, uint4* frec, hipStream_t st);
 // level tables on the host: comparison level CL(i,j) (Sec. 3.1; HRG by
 // search over levels, Sec. 4.3), insertion level I(i), deepest level D, and
 // the masks of layer pairs served by neighbouring (CL == level) and distant
