@@ -296,7 +296,9 @@ void tables_host(Graph& g, int Dcap) {
 }
 
 // pbar for (i, j, level, gap): largest weights, smallest distance gap
-// 2^-level; one entry per thread over the whole grid (CL from tables_host)
+// 2^-level; one entry per thread over the whole grid (CL from tables_host).
+// Entry ((i (Dcap + 1) + level) L + j) 2 + gap - 1: the row of one source
+// layer and level is contiguous.
 __global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int Dcap,
                                               Pbar* __restrict__ pb, int total) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(256) void k_pbar(const Graph* __restrict__ g, int D
   const int L = g->L, d = g->d;
   const int nl = Dcap + 1;
   {
-    const int gi = p & 1, l = (p >> 1) % nl, ij = (p >> 1) / nl, i = ij / L, j = ij % L;
+    const int gi = p & 1, j = (p >> 1) % L, il = (p >> 1) / L, l = il % nl, i = il / nl;
     const int cl = (i < L && j < L) ? g->CL[i][j] : -1;
     Pbar e{0.0, 0.0, 0, 0};
     if (cl >= l && l >= 2) {

@@ -85,6 +85,21 @@ __device__ __forceinline__ Rec<D, MODEL> load_rec(const double* __restrict__ rec
   return r;
 }
 
+// the records of both vertices of a pair in one round trip to memory: the
+// first slot is needed last (after the distance), and without the empty asm
+// the compiler loads it only then, and each record after the other
+template <int D, int MODEL>
+struct RecPair {
+  Rec<D, MODEL> a, b;
+};
+template <int D, int MODEL>
+__device__ __forceinline__ RecPair<D, MODEL> load_recs(const double* __restrict__ rec, uint32_t su,
+                                                      uint32_t sv) {
+  RecPair<D, MODEL> p{load_rec<D, MODEL>(rec, su), load_rec<D, MODEL>(rec, sv)};
+  asm volatile("" ::"v"(p.a.v[0]), "v"(p.b.v[0]));
+  return p;
+}
+
 // L-infinity torus distance of two records (GIRG: coordinates from slot 1,
 // HRG: the angle / 2 pi in slot 0)
 template <int D, int MODEL>
@@ -161,7 +176,9 @@ __device__ __forceinline__ bool hrg_below(const Graph* __restrict__ g, const Rec
 template <int D, int MODEL>
 __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const Verts& v,
                                             uint32_t su, uint32_t sv) {
-  const Rec<D, MODEL> a = load_rec<D, MODEL>(v.rec, su), b = load_rec<D, MODEL>(v.rec, sv);
+  const RecPair<D, MODEL> ab = load_recs<D, MODEL>(v.rec, su, sv);
+  const Rec<D, MODEL>& a = ab.a;
+  const Rec<D, MODEL>& b = ab.b;
   const double r = torus_r<D, MODEL>(a, b);
   if constexpr (MODEL == 0) {
     return girg_prob<D>(g, a.v[0], b.v[0], r);
@@ -176,7 +193,9 @@ __device__ __forceinline__ double pair_prob(const Graph* __restrict__ g, const V
 template <int D, int MODEL>
 __device__ __forceinline__ bool pair_thresh(const Graph* __restrict__ g, const Verts& v,
                                             uint32_t su, uint32_t sv, bool& nr) {
-  const Rec<D, MODEL> a = load_rec<D, MODEL>(v.rec, su), b = load_rec<D, MODEL>(v.rec, sv);
+  const RecPair<D, MODEL> ab = load_recs<D, MODEL>(v.rec, su, sv);
+  const Rec<D, MODEL>& a = ab.a;
+  const Rec<D, MODEL>& b = ab.b;
   const double r = torus_r<D, MODEL>(a, b);
   if constexpr (MODEL == 0) {
     // ||x_u - x_v|| <= c (w_u w_v / W)^{1/d}  <=>  r^d W <= c^d w_u w_v
@@ -227,6 +246,7 @@ __device__ __forceinline__ bool mixed_logp_f(const Graph* __restrict__ g,
                                              const uint4* __restrict__ frec, uint32_t su,
                                              uint32_t sv, float& Lc, float& err) {
   const uint4 a = frec[su], b = frec[sv];
+  asm volatile("" ::"v"(a.x), "v"(b.x));  // log2 w with the coordinates, in one load
   const uint32_t ax[3] = {a.y, a.z, a.w}, bx[3] = {b.y, b.z, b.w};
   uint32_t R = 0;
 #pragma unroll
@@ -250,7 +270,9 @@ __device__ __forceinline__ bool mixed_logp_f(const Graph* __restrict__ g,
 template <int D>
 __device__ __forceinline__ double mixed_prob64(const Graph* __restrict__ g, const Verts& v,
                                                uint32_t su, uint32_t sv) {
-  const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+  const RecPair<D, 0> ab = load_recs<D, 0>(v.rec, su, sv);
+  const Rec<D, 0>& a = ab.a;
+  const Rec<D, 0>& b = ab.b;
   return girg_prob<D>(g, a.v[0], b.v[0], torus_r<D, 0>(a, b));
 }
 
@@ -270,7 +292,9 @@ __device__ __forceinline__ bool mixed_test(const Graph* __restrict__ g, const Ve
     nr = fabs(U - p) < 1e-12;
     return U < p;
   } else {
-    const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+    const RecPair<D, 0> ab = load_recs<D, 0>(v.rec, su, sv);
+    const Rec<D, 0>& a = ab.a;
+    const Rec<D, 0>& b = ab.b;
     const double r = torus_r<D, 0>(a, b);
     float Lc, err;
     if (U > 0.0 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
@@ -302,7 +326,9 @@ __device__ __forceinline__ bool mixed_cand(const Graph* __restrict__ g, const Ve
     ++nre;
     p = mixed_prob64<D>(g, v, su, sv);
   } else {
-    const Rec<D, 0> a = load_rec<D, 0>(v.rec, su), b = load_rec<D, 0>(v.rec, sv);
+    const RecPair<D, 0> ab = load_recs<D, 0>(v.rec, su, sv);
+    const Rec<D, 0>& a = ab.a;
+    const Rec<D, 0>& b = ab.b;
     const double r = torus_r<D, 0>(a, b);
     float Lc, err;
     if (apb >= 0x1p-120 && mixed_logp<D>(g, a.v[0], b.v[0], r, Lc, err)) {
@@ -473,6 +499,12 @@ struct PB {
   double pbar, ilg;
   float qs;  // 1 / log2(1 - pbar)
 };
+// entry of (i, j, level, gap) in the pbar table, laid out [i][level][j][gap]:
+// the items of one source (i, level) read one contiguous row of L x 2 entries
+__device__ __forceinline__ uint32_t pbar_index(uint32_t i, uint32_t j, uint32_t lvl, uint32_t gap,
+                                               uint32_t L, uint32_t nlev) {
+  return ((i * nlev + lvl) * L + j) * 2u + (gap - 1u);
+}
 __device__ __forceinline__ PB load_pb(const Pbar* __restrict__ pbt, uint32_t pidx) {
   const Pbar e = pbt[pidx];
   return PB{e.pbar, e.ilg, e.qscale};
@@ -529,7 +561,10 @@ __device__ __forceinline__ void test_block(const Graph* __restrict__ g, const Ve
         const double U = h == 0 ? u53(o.x, o.y) : u53(o.z, o.w);
         if constexpr (MX) e = mixed_test<D>(g, v, su, sv, U, nre, nr);
         else if constexpr (MODEL == 1)
-          e = hrg_below<D>(g, load_rec<D, 1>(v.rec, su), load_rec<D, 1>(v.rec, sv), U, nr);
+          {
+            const RecPair<D, 1> ab = load_recs<D, 1>(v.rec, su, sv);
+            e = hrg_below<D>(g, ab.a, ab.b, U, nr);
+          }
         else {
           const double p = pair_prob<D, MODEL>(g, v, su, sv);
           nr = fabs(U - p) < 1e-12;
@@ -679,8 +714,9 @@ __device__ __forceinline__ void take_items1(const Graph* __restrict__ g, const V
   ItemRec rec{};
   if (have) {
     const Src sr = src[e.sidx];
-    const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8, lj = e.j;
     const uint2 cr = crec[e.ridx];
+    asm volatile("" ::"v"(sr.s), "v"(sr.A), "v"(sr.na), "v"(sr.meta), "v"(cr.x), "v"(cr.y));
+    const uint32_t lvl = sr.meta & 255u, li = sr.meta >> 8, lj = e.j;
     const uint32_t b0 = cr.x, nb = cr.y;
     // orientation: the smaller cell is the A side
     const bool fwd = e.Y >= sr.A;
@@ -769,6 +805,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
           const uint32_t lvl = sl.info & 255u, li = sl.info >> 16;
           sidx = sl.sidx;
+          // loaded while the cell is computed (left alone, the compiler loads
+          // them after it, one more round trip before the cell's layer set)
+          const uint64_t mo = g->moff[lvl], jm = g->jI[li][lvl];
           bool ok;
           if (((sl.info >> 8) & 255u) == 0u) {
             // balanced-ternary offset o = HALF + t: t = 0 is X itself
@@ -786,11 +825,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           } else {
             ok = neighbour_cell<D>(sl.A, (int)lvl, t, &Y) && Y >= sl.A;
           }
+          asm volatile("" ::"v"(mo), "v"(jm));
           if (ok) {
-            const CellL ce = cl[g->moff[lvl] + Y];
+            const CellL ce = cl[mo + Y];
             fm = ce.mask;
             base = ce.base;
-            m = fm & g->jI[li][lvl];
+            m = fm & jm;
             if (Y == sl.A) m &= ~((1ull << li) - 1ull);  // j >= i when X = Y
           }
         }
@@ -996,7 +1036,8 @@ __device__ __forceinline__ bool t2_near(const Graph* __restrict__ g, const Verts
     }
   }
   if (lvl < 0) return false;
-  const uint64_t pidx = (((uint64_t)v.layer[su] * g->L + v.layer[sv]) * nlev + lvl) * 2 + (gap - 1);
+  const uint32_t pidx = pbar_index(v.layer[su], v.layer[sv], (uint32_t)lvl, (uint32_t)gap, (uint32_t)g->L,
+                                   (uint32_t)nlev);
   const double pbar = pbt[pidx].pbar;
   return fabs(apb - pair_prob<D, MODEL>(g, v, su, sv)) < 1e-12 * pbar;
 }
@@ -1017,7 +1058,10 @@ __device__ __forceinline__ void eval_cands(const Graph* __restrict__ g, const Ve
     bool nr = false;
     if constexpr (MX) e0 = mixed_cand<D>(g, v, cd.su, cd.sv, cd.apb, nre, sg);
     else if constexpr (MODEL == 1)
-      e0 = hrg_below<D>(g, load_rec<D, 1>(v.rec, cd.su), load_rec<D, 1>(v.rec, cd.sv), cd.apb, nr);
+    {
+      const RecPair<D, 1> ab = load_recs<D, 1>(v.rec, cd.su, cd.sv);
+      e0 = hrg_below<D>(g, ab.a, ab.b, cd.apb, nr);
+    }
     else {
       const double p = pair_prob<D, MODEL>(g, v, cd.su, cd.sv);
       nr = fabs(cd.apb - p) < 1e-12;
@@ -1126,10 +1170,15 @@ __device__ __forceinline__ void take_items2(const Graph* __restrict__ g, const V
                    lvl = e.jg >> 24;
     // three independent loads; the pbar table is symmetric in the layer pair
     // (it depends on w_i w_j only), so it is indexed before the orientation
-    const uint32_t pidx = (uint32_t)((((uint64_t)li * g->L + lj) * nlev + lvl) * 2 + (gp - 1));
+    const uint32_t pidx = pbar_index(li, lj, lvl, gp, (uint32_t)g->L, (uint32_t)nlev);
     const Pbar pv = pbt[pidx];
     const Src sr = src[e.sidx];
     const uint2 cr = crec[e.ridx];
+    // wait for all three here, at once: left alone, the compiler sinks the
+    // source and the second half of the pbar entry into the branch below,
+    // which costs two more round trips to memory per item
+    asm volatile("" ::"v"(pv.pbar), "v"(pv.ilg), "v"(pv.e), "v"(pv.qscale), "v"(sr.s), "v"(sr.A),
+                 "v"(sr.na), "v"(cr.x), "v"(cr.y));
     const uint32_t b0 = cr.x, nb = cr.y;
     // orientation: the smaller cell is the A side
     const bool fwd = e.Y > sr.A;
@@ -1284,12 +1333,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           sidx = sl.sidx;
           tli = li;
           tlvl = lvl;
+          // the level's cell offset and layer mask load beside the offset
+          // table entry, not after it (one round trip to memory instead of two)
+          const uint64_t mo = g->moff[lvl], jm = g->jII[li][lvl];
           bool ok;
           if (par != 255u) {
             uint32_t qa[D], b[D];
             morton_decode<D>(sl.A, qa);
             const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
             const uint32_t en = dtab[kDistHead + par * dstride + t];
+            asm volatile("" ::"v"(en), "v"(mo), "v"(jm));
 #pragma unroll
             for (int kk = 0; kk < D; ++kk) b[kk] = (qa[kk] + ((en >> (3 * kk)) & 7u) - 3u) & cm;
             Y = morton_encode<D>(b);
@@ -1301,10 +1354,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             gap = (uint32_t)gp;
           }
           if (ok) {
-            const CellL ce = cl[g->moff[lvl] + Y];
+            const CellL ce = cl[mo + Y];
             fm = ce.mask;
             base = ce.base;
-            m = fm & g->jII[li][lvl];
+            m = fm & jm;
           }
         }
         push_items2<D, MODEL, MX>(m, fm, base, sidx, Y, gap | (tli << 8) | (tlvl << 16), g, v, crec,
@@ -1375,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_heavy2(const Graph* __restrict__ g, Ver
         const uint64_t s = u - uoff[lo];
         const uint32_t lvl = rr.meta & 255u, li = (rr.meta >> 8) & 255u, lj = (rr.meta >> 16) & 255u,
                        gp = (rr.meta >> 24) & 127u;
-        const uint32_t pidx = (uint32_t)((((uint64_t)li * L + lj) * nlev + lvl) * 2 + (gp - 1));
+        const uint32_t pidx = pbar_index(li, lj, lvl, gp, (uint32_t)L, (uint32_t)nlev);
         const uint64_t N = (uint64_t)rr.na * rr.nb;
         uint64_t G, ns;
         segment_size(N, (int)rr.e, &G, &ns);
@@ -1670,7 +1723,7 @@ __global__ __launch_bounds__(kSeqWaves * 64) __attribute__((amdgpu_waves_per_eu(
           par = sv.info >> 16;
           ecur = gp == 1 ? sv.e0 : sv.e0 + sv.n1;
           eend = gp == 1 ? sv.e0 + sv.n1 : sv.e0 + sv.n;
-          pidx = (uint32_t)((((uint64_t)li * L + j) * nlev + lvl) * 2 + (gp - 1));
+          pidx = pbar_index(li, j, lvl, gp, (uint32_t)L, (uint32_t)nlev);
           const Pbar pv = pbt[pidx];
           pe = PB{pv.pbar, pv.ilg, pv.qscale};
           pexp = pv.e;
