@@ -1027,6 +1027,7 @@ static girg_status run_graph(Ctx& cx, const girg_params& p, const double* w, con
   cx.mark("sources_fill", st);
   if (!cx.dtab[d]) {
     const std::vector<uint32_t> tab = distant_table(d);
+    if (tab.empty()) return fail(GIRG_EDEVICE, "distant-offset table rows shorter than a wave");
     uint32_t* t = nullptr;
     HIPCHK(hipMalloc(&t, tab.size() * sizeof(uint32_t)));
     HIPCHK(hipMemcpyAsync(t, tab.data(), tab.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -1343,6 +1344,7 @@ static girg_status noalloc_setup(int dev, NoAllocSlot** out) {
     c.hcount = reinterpret_cast<unsigned int*>(carve(sizeof(unsigned int)));
     for (int d = 1; d <= 4; ++d) {
       const size_t sz = distant_table_fill(d, g_na_tab, sizeof(g_na_tab) / sizeof(uint32_t));
+      if (sz == 0) return fail(GIRG_EDEVICE, "distant-offset table rows shorter than a wave");
       if (sz > sizeof(g_na_tab) / sizeof(uint32_t))
         return fail(GIRG_EDEVICE, "girg_from_points_noalloc: distant table larger than its buffer");
       uint32_t* t = reinterpret_cast<uint32_t*>(carve(sz * sizeof(uint32_t)));

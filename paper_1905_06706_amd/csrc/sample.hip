@@ -1264,13 +1264,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ QItem2 qs[4][kQCap];
   __shared__ Cand cqs[4][kCCap];
   __shared__ uint2 ebs[4][kEdgeBuf2];
-  __shared__ SrcSlot sss[4][kWave];
+  __shared__ SrcSlot sss[D < 3 ? 4 : 1][kWave];  // (d >= 3 finds sources without it)
   constexpr uint32_t NOFF = Offs<D>::n2;
   const uint32_t wv = threadIdx.x / kWave;
   IEnt* ib = ibs[wv];
   QItem2* q = qs[wv];
   Cand* cq = cqs[wv];
-  SrcSlot* ss = sss[wv];
+  SrcSlot* ss = sss[D < 3 ? wv : 0];
   const uint32_t lane = lane_id();
   const uint32_t dstride = dtab[0];
   uint32_t ndraws = 0, ncand = 0, nre = 0;
@@ -1312,23 +1312,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
       }
       mine.incl = wave_incl_scan(cnt);
-      ss[lane] = mine;
+      if constexpr (D < 3) ss[lane] = mine;
       const uint32_t total = __shfl(mine.incl, 63, 64);
+      const uint32_t mstart = mine.incl - cnt;
       // (source, offset) pairs spread over the lanes
       for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
         const uint32_t k = k0 + lane;
+        // d >= 3: a source with work has at least 64 candidate cells (the
+        // table rows hold 73 to 116 offsets at d = 3, and levels below 3 take
+        // all 6^d; the host checks this), so the window of 64 pairs spans at
+        // most two sources: s0, which holds pair k0, and the next one with
+        // work, s1.  Their fields come from their lanes, without a search.
+        SrcSlot w0{}, w1{};
+        uint32_t i0 = 0, st0 = 0, st1 = 0;
+        if constexpr (D >= 3) {
+          auto rl = [](uint32_t x, uint32_t l) {
+            return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+          };
+          const uint32_t s0 = (uint32_t)__popcll(__ballot(mine.incl <= k0));
+          i0 = rl(mine.incl, s0);
+          const uint32_t s1 = (uint32_t)__popcll(__ballot(mine.incl <= i0));
+          w0 = SrcSlot{(uint32_t)base + s0, rl(mine.A, s0), rl(mine.info, s0), i0};
+          st0 = rl(mstart, s0);
+          if (s1 < 64) {
+            w1 = SrcSlot{(uint32_t)base + s1, rl(mine.A, s1), rl(mine.info, s1), rl(mine.incl, s1)};
+            st1 = i0;
+          }
+        }
         uint64_t m = 0, fm = 0;
         uint32_t Y = 0, gap = 0, sidx = 0, base = 0, tli = 0, tlvl = 0;
-        if (k < total) {
-          // slot = number of inclusive prefixes <= k
-          uint32_t lo = 0, hi = 64;
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (ss[mid].incl <= k) lo = mid + 1;
-            else hi = mid;
+        bool in_window = k < total;
+        SrcSlot sl{};
+        uint32_t t = 0;
+        if constexpr (D >= 3) {
+          const bool second = k >= i0;
+          sl = second ? w1 : w0;
+          t = k - (second ? st1 : st0);
+          in_window = in_window && k < sl.incl;
+        }
+        if (in_window) {
+          if constexpr (D < 3) {
+            // slot = number of inclusive prefixes <= k
+            uint32_t lo = 0, hi = 64;
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (ss[mid].incl <= k) lo = mid + 1;
+              else hi = mid;
+            }
+            sl = ss[lo];
+            t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
           }
-          const SrcSlot sl = ss[lo];
-          const uint32_t t = k - (lo ? ss[lo - 1].incl : 0u);  // offset within the source
           const uint32_t lvl = sl.info & 255u, par = (sl.info >> 8) & 255u, li = sl.info >> 16;
           sidx = sl.sidx;
           tli = li;
@@ -2040,11 +2073,14 @@ static uint32_t distant_offsets(int d, int par, F&& f) {
 
 size_t distant_table_fill(int d, uint32_t* out, size_t cap) {
   const int npar = 1 << d;
-  uint32_t stride = 1;
+  uint32_t stride = 1, least = ~0u;
   for (int par = 0; par < npar; ++par) {
     const uint32_t c = distant_offsets(d, par, [](uint32_t, uint32_t) {});
     stride = c > stride ? c : stride;
+    least = c < least ? c : least;
   }
+  // k_type2 at d >= 3 relies on every row holding at least 64 offsets
+  if (d >= 3 && least < (uint32_t)kWave) return 0;
   const size_t size = (size_t)kDistHead + (size_t)npar * stride;
   if (!out || cap < size) return size;
   for (size_t k = 0; k < size; ++k) out[k] = 0u;
