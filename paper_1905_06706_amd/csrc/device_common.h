@@ -196,6 +196,8 @@ template <int D>
 struct Offs {
   static constexpr int n1 = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;      // neighbour offsets
   static constexpr int n2 = D == 1 ? 6 : D == 2 ? 36 : D == 3 ? 216 : 1296;  // parent-neighbour children
+  // longest row of the distant-offset table (one orientation of each pair)
+  static constexpr int nd = D == 1 ? 2 : D == 2 ? 17 : D == 3 ? 116 : 737;
 };
 
 // ---------------------------------------------------------------------------

@@ -1273,6 +1273,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   SrcSlot* ss = sss[D < 3 ? wv : 0];
   const uint32_t lane = lane_id();
   const uint32_t dstride = dtab[0];
+  // d <= 3: the distant-offset table in LDS (at most 3.8 KB)
+  constexpr uint32_t TL = D <= 3 ? kDistHead + (1u << D) * Offs<D>::nd : 1u;
+  __shared__ uint32_t ltab[TL];
+  if constexpr (D <= 3) {
+    const uint32_t tn = kDistHead + (1u << D) * dstride;
+    for (uint32_t i = threadIdx.x; i < (tn < TL ? tn : TL); i += blockDim.x) ltab[i] = dtab[i];
+    __syncthreads();
+  }
+  const uint32_t* __restrict__ tab = D <= 3 ? ltab : dtab;
   uint32_t ndraws = 0, ncand = 0, nre = 0;
   uint64_t nedge = 0;
   for (;;) {
@@ -1303,7 +1312,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             uint32_t par = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) par |= (qa[k] & 1u) << k;
-            cnt = dtab[1 + par];
+            cnt = tab[1 + par];
             mine.info = lvl | (par << 8) | (li << 16);
           } else {
             cnt = NOFF;
@@ -1374,7 +1383,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             uint32_t qa[D], b[D];
             morton_decode<D>(sl.A, qa);
             const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
-            const uint32_t en = dtab[kDistHead + par * dstride + t];
+            const uint32_t en = tab[kDistHead + par * dstride + t];
             asm volatile("" ::"v"(en), "v"(mo), "v"(jm));
 #pragma unroll
             for (int kk = 0; kk < D; ++kk) b[kk] = (qa[kk] + ((en >> (3 * kk)) & 7u) - 3u) & cm;
@@ -2079,8 +2088,11 @@ size_t distant_table_fill(int d, uint32_t* out, size_t cap) {
     stride = c > stride ? c : stride;
     least = c < least ? c : least;
   }
-  // k_type2 at d >= 3 relies on every row holding at least 64 offsets
+  // k_type2 at d >= 3 relies on every row holding at least 64 offsets, and
+  // at d <= 3 holds the table in LDS sized by the longest row
   if (d >= 3 && least < (uint32_t)kWave) return 0;
+  const int nd = d == 1 ? Offs<1>::nd : d == 2 ? Offs<2>::nd : d == 3 ? Offs<3>::nd : Offs<4>::nd;
+  if (stride > (uint32_t)nd) return 0;
   const size_t size = (size_t)kDistHead + (size_t)npar * stride;
   if (!out || cap < size) return size;
   for (size_t k = 0; k < size; ++k) out[k] = 0u;

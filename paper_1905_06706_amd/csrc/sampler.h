@@ -128,7 +128,8 @@ constexpr int kDistHead = 32;
 std::vector<uint32_t> distant_table(int d);
 // the same table written to out[0..size) without allocating; returns its
 // size (and writes nothing when out is null or cap is smaller), or 0 when a
-// row at d >= 3 holds fewer than 64 offsets (k_type2 relies on at least 64)
+// row at d >= 3 holds fewer than 64 offsets or a row is longer than
+// Offs<d>::nd (k_type2 relies on both)
 size_t distant_table_fill(int d, uint32_t* out, size_t cap);
 
 // sources at levels >= lvl_skip are left to launch_type2s (255: none)
