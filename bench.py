@@ -451,6 +451,33 @@ def hbm_copy(mib: int, steps: int, warmup: int) -> int:
     return 0
 
 
+def hbm_gather(mib: int, steps: int, warmup: int) -> int:
+    """Reads 2^22 random 16-byte rows of a table of `mib` MiB (torch's
+    index_select): beside the plain copy, the reference for what the HBM byte
+    counters report for scattered 16-byte loads such as the sampling kernels'
+    vertex records."""
+    import torch
+    rows = (mib << 20) // 16
+    count = 1 << 22
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    table = torch.ones((rows, 4), dtype=torch.int32, device="cuda")
+    idx = torch.randint(0, rows, (count,), device="cuda", generator=g)
+    out = torch.empty((count, 4), dtype=torch.int32, device="cuda")
+    for _ in range(warmup):
+        torch.index_select(table, 0, idx, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        torch.index_select(table, 0, idx, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    print(json.dumps({"gather_rows": count, "row_bytes": 16, "table_bytes": rows * 16,
+                      "index_bytes": count * 8, "bytes_written": count * 16, "steps": steps,
+                      "ms_per_gather": dt * 1e3}), flush=True)
+    return 0
+
+
 def profiled_steps(hg, call, bp, cap, sp, nprof: int) -> tuple:
     """nprof calls with stage events, the concurrent sampling passes run one
     after another (profiling mode 2): every kernel's time is its own, as a
@@ -536,6 +563,8 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the launch shapes on this workload before the warm-up "
                          "(default: the library's tuning table)")
+    ap.add_argument("--hbm-gather", type=int, default=0, metavar="MIB",
+                    help="read 2^22 random 16-byte rows of a table of MIB MiB (counter reference)")
     ap.add_argument("--hbm-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (HBM calibration)")
     ap.add_argument("--sweep", action="store_true",
@@ -549,6 +578,8 @@ def main() -> int:
         return 2
     if args.hbm_copy:
         return hbm_copy(args.hbm_copy, args.steps, args.warmup)
+    if args.hbm_gather:
+        return hbm_gather(args.hbm_gather, args.steps, args.warmup)
     if args.sweep:
         return sweep(min(args.steps, 5), min(args.warmup, 1))
     if args.coupling:
