@@ -1380,15 +1380,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           const uint64_t mo = g->moff[lvl], jm = g->jII[li][lvl];
           bool ok;
           if (par != 255u) {
-            uint32_t qa[D], b[D];
-            morton_decode<D>(sl.A, qa);
-            const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
             const uint32_t en = tab[kDistHead + par * dstride + t];
             asm volatile("" ::"v"(en), "v"(mo), "v"(jm));
+            if constexpr (D == 3) {
+              // add the dilated displacement per dimension in Morton space:
+              // the other dimensions' bits set to 1 carry through, and the
+              // code is taken mod 2^(3 lvl) (the torus wrap)
+              uint32_t y = 0;
 #pragma unroll
-            for (int kk = 0; kk < D; ++kk) b[kk] = (qa[kk] + ((en >> (3 * kk)) & 7u) - 3u) & cm;
-            Y = morton_encode<D>(b);
-            gap = en >> 28;
+              for (int kk = 0; kk < 3; ++kk) {
+                const uint32_t M = 0x24924924u >> kk;
+                y |= ((sl.A | ~M) + (en & M)) & M;
+              }
+              Y = y & (uint32_t)((1ull << (3 * lvl)) - 1);
+              gap = en >> 30;
+            } else {
+              uint32_t qa[D], b[D];
+              morton_decode<D>(sl.A, qa);
+              const uint32_t cm = (uint32_t)((1ull << lvl) - 1);
+#pragma unroll
+              for (int kk = 0; kk < D; ++kk) b[kk] = (qa[kk] + ((en >> (3 * kk)) & 7u) - 3u) & cm;
+              Y = morton_encode<D>(b);
+              gap = en >> 28;
+            }
             ok = true;
           } else {
             int gp = 0;
@@ -2097,8 +2111,24 @@ size_t distant_table_fill(int d, uint32_t* out, size_t cap) {
   if (!out || cap < size) return size;
   for (size_t k = 0; k < size; ++k) out[k] = 0u;
   out[0] = stride;
+  // d = 3: each entry as the Morton displacement itself, delta_k mod 2^10
+  // spread into dimension k's bits (dimension 0 most significant), with the
+  // gap in bits 30-31; k_type2 adds it to a cell's code per dimension
+  auto spread3h = [](uint32_t v) {
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+  };
   for (int par = 0; par < npar; ++par)
     out[1 + par] = distant_offsets(d, par, [&](uint32_t t, uint32_t en) {
+      if (d == 3) {
+        uint32_t dil = 0;
+        for (int k = 0; k < 3; ++k) {
+          const uint32_t dk = (((en >> (3 * k)) & 7u) - 3u) & 1023u;  // delta_k mod 2^10
+          dil |= spread3h(dk) << (2 - k);
+        }
+        en = dil | ((en >> 28) << 30);
+      }
       out[kDistHead + (size_t)par * stride + t] = en;
     });
   return size;

@@ -121,7 +121,9 @@ hipError_t launch_type1(const Graph& g, const Graph* gd, const Verts& v, const C
                         const DeferOut& dfo, hipStream_t st);
 // distant offsets of a cell at levels >= 3 by the parity pattern p of its
 // coordinates: dtab[0] = stride, dtab[1 + p] = count, entries at
-// dtab[kDistHead + p * stride + t] = sum_k (delta_k + 3) << 3k | gap << 28;
+// dtab[kDistHead + p * stride + t] = sum_k (delta_k + 3) << 3k | gap << 28
+// (d = 3: the Morton displacement, delta_k mod 2^10 spread into dimension k's
+// bits, | gap << 30);
 // only offsets whose first nonzero delta is positive (the other orientation
 // of each pair is listed at the other cell)
 constexpr int kDistHead = 32;
